@@ -1,0 +1,353 @@
+"""Seeded synthetic inputs: triangle meshes and initial states.
+
+This module is shared by the tests, the benchmark and the CPU oracle's
+callers.  It holds no arithmetic of the numerical method itself: it only
+generates meshes (jittered, randomly split lattices that stand in for the
+Delaunay meshes of the paper's test cases) and evaluates closed-form
+initial conditions (isentropic vortex of the paper's Section 3.1, a
+four-quadrant 2D Riemann problem, a decaying Taylor-Green vortex and a
+Mach 1.1 normal shock with an upstream vortex) together with their exact
+spatial derivatives, because the method evolves w, w_x and w_y.
+
+State layout everywhere: ``U[12, V]`` float64, rows ``q + 4*k`` with
+``q`` = (rho, rho*u, rho*v, E) and ``k`` = (value, d/dx, d/dy).
+
+Mesh recipe ``G(nx, ny, Lx, Ly, periodic, G, seed)``:
+
+* lattice spacing ``h = L/(n-1)`` per direction;
+* a periodic direction identifies the last row/column with the first
+  (``n-1`` unique points, coordinates in ``[0, L)``);
+* a non-periodic direction keeps all ``n`` points and adds ``G`` ghost rows
+  outside the domain on each side; vertices on the domain's boundary lines
+  are not jittered;
+* ``numpy.random.default_rng(seed)`` draws, in this order, one diagonal bit
+  per cell (0: triangles (a,b,d),(b,c,d); 1: (a,b,c),(a,c,d), counter-
+  clockwise with a=(i,j), b=(i+1,j), c=(i+1,j+1), d=(i,j+1)), then a jitter
+  ``U(-0.2h, 0.2h)`` per vertex and direction;
+* vertex id ``= j*nxv + i`` (x fastest).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Mesh:
+    xy: np.ndarray          # [V, 2] float64
+    tri: np.ndarray         # [T, 3] int32, counter-clockwise
+    ghost_src: np.ndarray   # [V] int32: -1 owned, >=0 copy source, -2 Dirichlet
+    period: tuple           # (Px, Py), 0.0 = not periodic in that direction
+    shape: tuple            # (nxv, nyv) lattice points actually stored
+    h: tuple                # (hx, hy) lattice spacing
+    ij: np.ndarray          # [V, 2] int lattice indices (ghosts negative / >= n)
+
+    @property
+    def nv(self):
+        return self.xy.shape[0]
+
+    @property
+    def owned(self):
+        return self.ghost_src == -1
+
+    def n_owned(self):
+        return int(np.count_nonzero(self.ghost_src == -1))
+
+
+def jittered_grid(nx, ny, Lx, Ly, periodic=(True, True), ghost_layers=0,
+                  seed=0, jitter=0.2, dirichlet_sides=()):
+    """Jittered, randomly split lattice (recipe in the module docstring).
+
+    ``dirichlet_sides`` lists sides among ('xlo', 'xhi', 'ylo', 'yhi') whose
+    ghost vertices are Dirichlet (-2) instead of copies of the nearest
+    boundary vertex (transmissive).
+    """
+    px, py = bool(periodic[0]), bool(periodic[1])
+    G = int(ghost_layers)
+    hx = Lx / (nx - 1)
+    hy = Ly / (ny - 1)
+    if px:
+        ix = np.arange(nx - 1)
+    else:
+        ix = np.arange(-G, nx + G)
+    if py:
+        iy = np.arange(ny - 1)
+    else:
+        iy = np.arange(-G, ny + G)
+    nxv, nyv = ix.size, iy.size
+    I, J = np.meshgrid(ix, iy)          # [nyv, nxv]
+    I = I.ravel()
+    J = J.ravel()
+    V = I.size
+    ncx = nxv if px else nxv - 1
+    ncy = nyv if py else nyv - 1
+
+    rng = np.random.default_rng(seed)
+    bits = rng.integers(0, 2, size=(ncy, ncx))
+    jit = rng.uniform(-jitter, jitter, size=(V, 2))
+
+    xy = np.empty((V, 2))
+    xy[:, 0] = I * hx + jit[:, 0] * hx
+    xy[:, 1] = J * hy + jit[:, 1] * hy
+    on_line = np.zeros(V, dtype=bool)
+    if not px:
+        on_line |= (I == 0) | (I == nx - 1)
+    if not py:
+        on_line |= (J == 0) | (J == ny - 1)
+    xy[on_line, 0] = I[on_line] * hx
+    xy[on_line, 1] = J[on_line] * hy
+    if px:
+        xy[:, 0] = np.mod(xy[:, 0], Lx)
+    if py:
+        xy[:, 1] = np.mod(xy[:, 1], Ly)
+
+    def vid(ci, cj):
+        if px:
+            ci = ci % nxv
+        if py:
+            cj = cj % nyv
+        return cj * nxv + ci
+
+    cj, ci = np.meshgrid(np.arange(ncy), np.arange(ncx), indexing="ij")
+    a = vid(ci, cj)
+    b = vid(ci + 1, cj)
+    c = vid(ci + 1, cj + 1)
+    d = vid(ci, cj + 1)
+    b0 = bits == 0
+    t1 = np.where(b0[..., None], np.stack([a, b, d], -1), np.stack([a, b, c], -1))
+    t2 = np.where(b0[..., None], np.stack([b, c, d], -1), np.stack([a, c, d], -1))
+    tri = np.stack([t1, t2], axis=2).reshape(-1, 3).astype(np.int32)
+
+    ghost_src = np.full(V, -1, dtype=np.int32)
+    gx = ((I < 0) | (I > nx - 1)) if not px else np.zeros(V, bool)
+    gy = ((J < 0) | (J > ny - 1)) if not py else np.zeros(V, bool)
+    ghost = gx | gy
+    if np.any(ghost):
+        ci_ = np.clip(I, 0, nx - 1) if not px else I
+        cj_ = np.clip(J, 0, ny - 1) if not py else J
+        src = (cj_ - iy[0]) * nxv + (ci_ - ix[0])
+        ghost_src[ghost] = src[ghost].astype(np.int32)
+        for side in dirichlet_sides:
+            m = {"xlo": I < 0, "xhi": I > nx - 1,
+                 "ylo": J < 0, "yhi": J > ny - 1}[side]
+            ghost_src[ghost & m] = -2
+    period = (Lx if px else 0.0, Ly if py else 0.0)
+    return Mesh(xy=xy, tri=tri, ghost_src=ghost_src, period=period,
+                shape=(nxv, nyv), h=(hx, hy), ij=np.stack([I, J], 1))
+
+
+def shuffled(mesh: Mesh, seed=0):
+    """Same mesh with vertices renumbered by a seeded random permutation.
+
+    Real mesh generators emit vertices in no useful order; this is the input
+    that exercises a solver's own renumbering.
+    """
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(mesh.nv)          # new position -> old id
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(mesh.nv)
+    gs = mesh.ghost_src[perm].copy()
+    gs[gs >= 0] = inv[gs[gs >= 0]]
+    return Mesh(xy=mesh.xy[perm].copy(), tri=inv[mesh.tri].astype(np.int32),
+                ghost_src=gs.astype(np.int32), period=mesh.period,
+                shape=mesh.shape, h=mesh.h, ij=mesh.ij[perm].copy())
+
+
+# ----------------------------------------------------------------------------
+# Closed-form initial states with exact derivatives
+# ----------------------------------------------------------------------------
+
+def prim_to_state(gamma, rho, u, v, p, drho, du, dv, dp):
+    """Conservative state and its gradient from primitive fields.
+
+    ``d*`` are pairs (d/dx, d/dy).  Returns U[12, V].
+    """
+    V = np.broadcast_to(rho, np.shape(rho)).size
+    U = np.zeros((12, V))
+    q2 = u * u + v * v
+    U[0] = rho
+    U[1] = rho * u
+    U[2] = rho * v
+    U[3] = p / (gamma - 1.0) + 0.5 * rho * q2
+    for k in (0, 1):
+        r_, u_, v_, p_ = drho[k], du[k], dv[k], dp[k]
+        U[4 * (k + 1) + 0] = r_
+        U[4 * (k + 1) + 1] = r_ * u + rho * u_
+        U[4 * (k + 1) + 2] = r_ * v + rho * v_
+        U[4 * (k + 1) + 3] = (p_ / (gamma - 1.0) + 0.5 * r_ * q2
+                              + rho * (u * u_ + v * v_))
+    return U
+
+
+def _rel(xy, center, period):
+    d = xy - np.asarray(center)[None, :]
+    for k in (0, 1):
+        P = period[k]
+        if P:
+            d[:, k] -= P * np.round(d[:, k] / P)
+    return d[:, 0], d[:, 1]
+
+
+def _vortex_prims(xb, yb, beta, gamma, scale):
+    """Isentropic vortex perturbation (paper Section 3.1) in coordinates
+    scaled by ``scale``; returns temperature-like factor and velocity
+    perturbation with derivatives w.r.t. physical x, y."""
+    r2 = xb * xb + yb * yb
+    kap = (gamma - 1.0) * beta * beta / (8.0 * gamma * math.pi ** 2)
+    phi = np.exp(1.0 - r2)
+    T = 1.0 - kap * phi
+    dT = (2.0 * kap * phi * xb / scale, 2.0 * kap * phi * yb / scale)
+    a = beta / (2.0 * math.pi)
+    psi = np.exp(0.5 * (1.0 - r2))
+    du_ = -a * yb * psi
+    dv_ = a * xb * psi
+    ddu = (a * xb * yb * psi / scale, -a * psi * (1.0 - yb * yb) / scale)
+    ddv = (a * psi * (1.0 - xb * xb) / scale, -a * xb * yb * psi / scale)
+    return T, dT, du_, ddu, dv_, ddv
+
+
+def isentropic_vortex(mesh: Mesh, center=(5.0, 5.0), beta=5.0, gamma=1.4,
+                      free=(1.0, 1.0), t=0.0):
+    """Paper Section 3.1 vortex on a free stream (rho, u, v, p) =
+    (1, free_u, free_v, 1), advected exactly to time ``t``."""
+    c = (center[0] + free[0] * t, center[1] + free[1] * t)
+    xb, yb = _rel(mesh.xy, c, mesh.period)
+    T, dT, du_, ddu, dv_, ddv = _vortex_prims(xb, yb, beta, gamma, 1.0)
+    g1 = 1.0 / (gamma - 1.0)
+    rho = T ** g1
+    drho = tuple(g1 * rho / T * d for d in dT)
+    p = rho ** gamma
+    dp = tuple(gamma * rho ** (gamma - 1.0) * d for d in drho)
+    u = free[0] + du_
+    v = free[1] + dv_
+    return prim_to_state(gamma, rho, u, v, p, drho, ddu, ddv, dp)
+
+
+def riemann_quadrants(mesh: Mesh, gamma=1.4, states=None, split=(0.5, 0.5)):
+    """Four-quadrant piecewise-constant state, zero gradients.
+
+    ``states`` (rho, u, v, p) in the order NE, NW, SW, SE; x >= split_x is
+    east, y >= split_y is north.
+    """
+    if states is None:
+        states = ((1.5, 0.0, 0.0, 1.5), (0.5323, 1.206, 0.0, 0.3),
+                  (0.138, 1.206, 1.206, 0.029), (0.5323, 0.0, 1.206, 0.3))
+    x, y = mesh.xy[:, 0], mesh.xy[:, 1]
+    east = x >= split[0]
+    north = y >= split[1]
+    q = np.where(north & east, 0, np.where(north, 1, np.where(east, 3, 2)))
+    S = np.asarray(states, dtype=np.float64)[q]
+    z = np.zeros(mesh.nv)
+    return prim_to_state(gamma, S[:, 0], S[:, 1], S[:, 2], S[:, 3],
+                         (z, z), (z, z), (z, z), (z, z))
+
+
+def taylor_green(mesh: Mesh, gamma=1.4, mach=0.1, rho0=1.0, U0=1.0, R=1.0,
+                 t=0.0, nu=0.0):
+    """Compressible decaying Taylor-Green vortex on [0, 2pi]^2 at low Mach
+    number: p0 = rho0 U0^2/(gamma M^2), isothermal density rho = p/(R T0)
+    with T0 = p0/(rho0 R).  With ``nu`` and ``t`` the incompressible decay
+    factors exp(-2 nu t) (velocity) and exp(-4 nu t) (pressure perturbation)
+    are applied."""
+    p0 = rho0 * U0 * U0 / (gamma * mach * mach)
+    T0 = p0 / (rho0 * R)
+    fu = math.exp(-2.0 * nu * t)
+    fp = fu * fu
+    x, y = mesh.xy[:, 0], mesh.xy[:, 1]
+    sx, cx, sy, cy = np.sin(x), np.cos(x), np.sin(y), np.cos(y)
+    u = U0 * fu * sx * cy
+    v = -U0 * fu * cx * sy
+    du = (U0 * fu * cx * cy, -U0 * fu * sx * sy)
+    dv = (U0 * fu * sx * sy, -U0 * fu * cx * cy)
+    A = rho0 * U0 * U0 / 4.0 * fp
+    p = p0 + A * (np.cos(2 * x) + np.cos(2 * y))
+    dp = (-2.0 * A * np.sin(2 * x), -2.0 * A * np.sin(2 * y))
+    rho = p / (R * T0)
+    drho = (dp[0] / (R * T0), dp[1] / (R * T0))
+    return prim_to_state(gamma, rho, u, v, p, drho, du, dv, dp)
+
+
+def normal_shock_states(mach, gamma=1.4, rho1=1.0, p1=1.0):
+    """Upstream/downstream (rho, u, v, p) of a stationary normal shock
+    (Rankine-Hugoniot relations)."""
+    c1 = math.sqrt(gamma * p1 / rho1)
+    u1 = mach * c1
+    m2 = mach * mach
+    rho2 = rho1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    u2 = u1 * rho1 / rho2
+    return (rho1, u1, 0.0, p1), (rho2, u2, 0.0, p2)
+
+
+def shock_vortex(mesh: Mesh, gamma=1.4, mach=1.1, x_shock=0.5,
+                 center=(0.25, 0.5), beta=0.3, rc=0.05):
+    """Stationary Mach ``mach`` normal shock at x = x_shock with the paper's
+    isentropic vortex (strength ``beta``, coordinates scaled by ``rc``)
+    superposed upstream as velocity and isentropic temperature perturbations
+    of the pre-shock state (rho, p) = (1, 1)."""
+    (r1, u1, _, p1), (r2, u2, _, p2) = normal_shock_states(mach, gamma)
+    x = mesh.xy[:, 0]
+    up = x < x_shock
+    xb = (mesh.xy[:, 0] - center[0]) / rc
+    yb = (mesh.xy[:, 1] - center[1]) / rc
+    T, dT, du_, ddu, dv_, ddv = _vortex_prims(xb, yb, beta, gamma, rc)
+    g1 = 1.0 / (gamma - 1.0)
+    rho_v = T ** g1
+    drho_v = tuple(g1 * rho_v / T * d for d in dT)
+    p_v = rho_v ** gamma
+    dp_v = tuple(gamma * rho_v ** (gamma - 1.0) * d for d in drho_v)
+    z = np.zeros(mesh.nv)
+    rho = np.where(up, rho_v, r2)
+    p = np.where(up, p_v, p2)
+    u = np.where(up, u1 + du_, u2)
+    v = np.where(up, dv_, 0.0)
+    drho = tuple(np.where(up, d, z) for d in drho_v)
+    dp = tuple(np.where(up, d, z) for d in dp_v)
+    du = tuple(np.where(up, d, z) for d in ddu)
+    dv = tuple(np.where(up, d, z) for d in ddv)
+    return prim_to_state(gamma, rho, u, v, p, drho, du, dv, dp)
+
+
+# ----------------------------------------------------------------------------
+# Named workloads (mesh recipe + initial state), sizes as stated per case
+# ----------------------------------------------------------------------------
+
+def workload(name, scale=None):
+    """Return (mesh, U0, params) for a named workload.
+
+    ``scale`` overrides the lattice size n (n x n, or (2n-1) x n for the
+    shock-vortex case) to build a smaller instance of the same recipe.
+    """
+    if name == "vortex21":
+        n = scale or 21
+        m = jittered_grid(n, n, 10.0, 10.0, (True, True), 0, seed=1)
+        U = isentropic_vortex(m, center=(5.0, 5.0), beta=5.0)
+        prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=20)
+    elif name == "riemann201":
+        n = scale or 201
+        m = jittered_grid(n, n, 1.0, 1.0, (False, False), 5, seed=2)
+        U = riemann_quadrants(m)
+        prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=10)
+    elif name == "tgv513":
+        n = scale or 513
+        L = 2.0 * math.pi
+        m = jittered_grid(n, n, L, L, (True, True), 0, seed=3)
+        U = taylor_green(m)
+        prm = dict(gamma=1.4, mu=0.01, prandtl=0.72, gas_R=1.0,
+                   switch="smooth", cfl=0.3, steps=500)
+    elif name == "vortex257":
+        n = scale or 257
+        m = jittered_grid(n, n, 10.0, 10.0, (True, True), 0, seed=4)
+        U = isentropic_vortex(m, center=(5.0, 5.0), beta=5.0)
+        prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=200)
+    elif name == "shockvortex2049":
+        n = scale or 1025
+        m = jittered_grid(2 * n - 1, n, 2.0, 1.0, (False, False), 5, seed=5,
+                          dirichlet_sides=("xlo",))
+        U = shock_vortex(m)
+        prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=10)
+    else:
+        raise KeyError(name)
+    return m, U, prm
