@@ -1,0 +1,222 @@
+#!/usr/bin/env python
+"""Throughput of the Hermite finite-difference hot path on one MI355X.
+
+One step = one full three-stage TVD Runge-Kutta step of the whole mesh:
+time step (min over vertices), then per stage the edge pass (Hermite/WENO
+reconstruction + Rusanov flux of every edge) and the vertex pass
+(least-squares divergence + Runge-Kutta update of every owned vertex).
+Inputs are synthetic (seeded jittered lattice, closed-form initial state)
+and resident in HBM before the timed region.
+
+Default workload: Mach 1.1 normal shock + isentropic vortex on [0,2]x[0,1],
+2049 x 1025 jittered lattice with 5 ghost layers (2.1 M owned vertices,
+6.4 M active edges).  The metric is vertex-RK-stage updates per second
+(owned vertices x 3 stages x steps / wall time); the float32 mixed form is
+the reported value, float64 is measured beside it.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_options(name, prm):
+    kw = dict(switch=prm["switch"], mu=prm.get("mu", 0.0))
+    if prm.get("mu", 0.0) > 0:
+        kw.update(prandtl=prm["prandtl"], gas_R=prm["gas_R"])
+    if name in ("shockvortex2049", "riemann201"):
+        kw["w3_cap"] = 2.0
+    return kw
+
+
+def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
+    """Time `steps` steps in chunks of `chunk` steps, each chunk starting
+    again from the initial state (the captured shock of this method grows
+    until the solution fails after a few dozen steps, so every timed step
+    is one of the first `chunk` steps of the same evolution).  Only the
+    steps are inside the timed regions, each bracketed by device
+    synchronisations."""
+    import torch
+    S.set_precision(prec, wref)
+    U = U0d.clone()
+    dt = torch.empty(1, dtype=torch.float64, device=U.device)
+    for _ in range(warmup):
+        S.stable_dt(U, cfl, out=dt)
+        S.rk_step(U, dt)
+    torch.cuda.synchronize()
+    S.check()
+    S.kernel_times()
+    wall = 0.0
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        U.copy_(U0d)
+        torch.cuda.synchronize()
+        S.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            S.stable_dt(U, cfl, out=dt)
+            S.rk_step(U, dt)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        S.set_timing(False)
+        S.check()
+        done += n
+    e_ms, n_e, v_ms, n_v = S.kernel_times()
+    info = S.refresh_info()
+    return dict(U=U, wall=wall, edge_ms=e_ms / max(n_e, 1), vertex_ms=v_ms / max(n_v, 1),
+                n_edge=n_e, n_vertex=n_v, bytes_edge=info["bytes_edge_launch"],
+                bytes_vertex=info["bytes_vertex_launch"])
+
+
+def roofline(r):
+    kern = {}
+    for k in ("edge", "vertex"):
+        ms = r[f"{k}_ms"]
+        gbs = r[f"bytes_{k}"] / (ms * 1e-3) / 1e9
+        kern[k] = dict(avg_ms=ms, alg_bytes=r[f"bytes_{k}"], achieved_gbs=gbs,
+                       frac=gbs / HBM_PEAK_GBS, launches=r[f"n_{k}"])
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    return dom, kern
+
+
+def cpu_baseline(m, U0, prm, kw, budget_s):
+    """The oracle, as it is, on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+
+    from oracle import scheme as osch
+    owned = np.nonzero(m.ghost_src == -1)[0]
+    # a compact patch of owned vertices around the vortex / shock region
+    c = m.xy[owned].mean(axis=0) if m.period[0] else np.array([0.4, 0.5])
+    d = np.max(np.abs(m.xy[owned] - c), axis=1)
+    sample = owned[np.argsort(d, kind="stable")[:1024]]
+    sample.sort()
+    opts = osch.Options(gamma=1.4, mu=kw.get("mu", 0.0), w3_cap=kw.get("w3_cap", 0.0))
+    t0 = time.perf_counter()
+    sc = osch.Scheme(m.xy, m.tri, m.ghost_src, m.period, opts, verts=sample)
+    setup = time.perf_counter() - t0
+    Ut = torch.as_tensor(U0)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        sc.residual(Ut, kw["switch"])
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s:
+            break
+    rate = sample.size * n / el
+    return dict(value=rate, unit="vertex-stage/s", cores=torch.get_num_threads(),
+                kind="oracle",
+                sample=f"{sample.size} owned vertices (a compact patch), {n} residual "
+                       f"evaluations in {el:.1f} s; oracle setup {setup:.1f} s not timed")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--chunk", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="shockvortex2049")
+    ap.add_argument("--scale", type=int, default=None)
+    ap.add_argument("--cfl", type=float, default=0.3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the mesh would be partitioned with a halo exchange per stage).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+
+    t0 = time.perf_counter()
+    m, U0, prm = inputs.workload(a.workload, a.scale)
+    kw = workload_options(a.workload, prm)
+    log(f"[bench] {a.workload}: {m.nv} vertices ({m.n_owned()} owned), inputs "
+        f"{time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, **kw)
+    info = S.info
+    log(f"[bench] setup {time.perf_counter() - t0:.1f} s (host {info['setup_ms'][0]:.0f} ms, "
+        f"upload {info['setup_ms'][1]:.0f} ms, GPU precompute {info['setup_ms'][2]:.0f} ms); "
+        f"{info['n_edges']} active edges, ranks {info['rank_hist'][10:15]}")
+    U0d = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+    wref = U0[0:4, m.ghost_src == -1].mean(axis=1)
+
+    res = {}
+    for prec in ("fp64", "fp32"):
+        if a.only and prec != a.only:
+            continue
+        r = time_precision(S, U0d, prec, wref, a.steps, a.warmup, a.cfl, a.chunk)
+        r["rate"] = m.n_owned() * 3 * a.steps / r["wall"]
+        dom, kern = roofline(r)
+        r["dom"], r["kern"] = dom, kern
+        res[prec] = r
+        log(f"[bench] {prec}: {r['wall'] / a.steps * 1e3:.3f} ms/step, "
+            f"{r['rate'] / 1e9:.3f} G vertex-stage/s; edge {kern['edge']['avg_ms']:.3f} ms "
+            f"({kern['edge']['achieved_gbs']:.0f} GB/s), vertex {kern['vertex']['avg_ms']:.3f} ms "
+            f"({kern['vertex']['achieved_gbs']:.0f} GB/s)")
+    main_prec = "fp32" if "fp32" in res else "fp64"
+    r = res[main_prec]
+    dom, kern = r["dom"], r["kern"]
+    diff = None
+    if "fp32" in res and "fp64" in res:
+        a64 = res["fp64"]["U"][0, :S.n_owned]
+        a32 = res["fp32"]["U"][0, :S.n_owned]
+        diff = float(torch.linalg.norm(a32 - a64) / torch.linalg.norm(a64))
+    out = {
+        "metric": "vertex-RK-stage updates/s",
+        "value": r["rate"],
+        "unit": "vertex-stage/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["wall"] / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 RK state)" if main_prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "vertices": int(m.nv), "owned": int(m.n_owned()),
+                   "edges": int(info["n_edges"]), "switch": kw["switch"],
+                   "w3_cap": kw.get("w3_cap", 0.0), "cfl": a.cfl,
+                   "steps_per_restart": a.chunk},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": kern[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kern[dom]["frac"], "traffic": None},
+        "kernels": kern,
+    }
+    if "fp64" in res and main_prec == "fp32":
+        out["fp64"] = {"value": res["fp64"]["rate"],
+                       "ms_per_step": res["fp64"]["wall"] / a.steps * 1e3,
+                       "kernels": res["fp64"]["kern"]}
+        out["fp32_vs_fp64_rho_rel_l2"] = diff
+    if not a.no_cpu:
+        log("[bench] timing the CPU oracle on a sample ...")
+        out["cpu_baseline"] = cpu_baseline(m, U0, prm, kw, a.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,696 @@
+// C ABI of libhfd (declared in include/hfd.h): context life cycle, device
+// memory, the geometric precompute and the hot-path launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hfd.h"
+#include "kernels.h"
+#include "setup.h"
+
+using hfd::GasParams;
+
+struct hfd_ctx {
+  hfd_opts o{};
+  int device = -1;
+  std::string err;
+  hfd::HostSetup hs;
+  hfd_info info{};
+  std::vector<void*> allocs;
+
+  // float64 coefficients
+  int32_t* stg = nullptr;
+  double *n = nullptr, *w5 = nullptr, *w3 = nullptr;
+  int32_t* rank = nullptr;
+  int8_t* trunc3 = nullptr;
+  int32_t *vptr = nullptr, *eptr = nullptr, *vg = nullptr, *ve = nullptr;
+  double *dv = nullptr, *de = nullptr, *dvis = nullptr;
+  double* hmin = nullptr;
+  int32_t *dir_rows = nullptr, *copy_rows = nullptr, *copy_src = nullptr;
+  // float32 copies (mixed form)
+  float *fn = nullptr, *fw5 = nullptr, *fw3 = nullptr, *fdv = nullptr,
+        *fde = nullptr, *fdvis = nullptr;
+  // work buffers
+  double *U1 = nullptr, *U2 = nullptr, *H = nullptr;
+  float *S0 = nullptr, *S1 = nullptr, *S2 = nullptr, *SH = nullptr;
+  double* dtpart = nullptr;
+  int64_t ndtpart = 0;
+  int32_t* flag = nullptr;
+  const uint8_t* force = nullptr;
+  // measurement: event pairs around the edge (0) and vertex (1) passes
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2];
+};
+
+namespace {
+
+thread_local std::string g_create_err;  // message of the last failed hfd_create
+
+hfd_status fail(hfd_ctx* c, hfd_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, HFD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+hfd_status dalloc(hfd_ctx* c, T** p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) return HFD_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, size_t(n) * sizeof(T));
+  if (e != hipSuccess)
+    return fail(c, HFD_E_NOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) +
+                                    " bytes: " + hipGetErrorString(e));
+  c->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return HFD_OK;
+}
+
+template <class T>
+hfd_status upload(hfd_ctx* c, T** p, const std::vector<T>& h) {
+  hfd_status s = dalloc(c, p, int64_t(h.size()));
+  if (s != HFD_OK) return s;
+  if (!h.empty()) HIPCHK(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HFD_OK;
+}
+
+void dfree(hfd_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  hipFree(p);
+}
+
+GasParams gas_params(const hfd_ctx* c, bool mixed) {
+  GasParams g{};
+  g.gamma = c->o.gamma;
+  g.gas_R = c->o.gas_R;
+  g.mu = c->o.mu;
+  g.prandtl = c->o.prandtl;
+  g.eps = c->o.weno_eps;
+  g.sw_lo = c->o.sw_lo;
+  g.sw_hi = c->o.sw_hi;
+  for (int q = 0; q < 4; ++q) g.wref[q] = mixed ? c->o.w_ref[q] : 0.0;
+  g.sw = c->o.switch_mode;
+  return g;
+}
+
+bool mixed(const hfd_ctx* c) { return c->o.precision == HFD_FP32_MIXED; }
+
+void byte_model(hfd_ctx* c) {
+  hfd_info& I = c->info;
+  const double s = mixed(c) ? 4.0 : 8.0;
+  const double ne = double(I.n_edges), nv = double(I.nv), no = double(I.n_owned);
+  const double visc = c->o.mu > 0.0 ? 1.0 : 0.0;
+  // edge pass: ids, direction + Hermite + 3-node weights, the stage state
+  // (12 values per vertex), flux out
+  I.bytes_edge_launch = ne * (6 * 4 + 50 * s + 4 * s) + nv * 12 * s;
+  // vertex pass: CSR offsets and ids, coefficient records, state (values,
+  // plus gradients with viscosity), edge fluxes, float64 RK update
+  // averaged over the three stages: U^n read and U^new written every stage,
+  // U^k read in stages 2 and 3, float32 shadow written in stages 1 and 2
+  double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + (mixed(c) ? (2.0 / 3.0) * 48.0 : 0.0));
+  I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (4 + 6 * s + visc * 5 * s) +
+                          double(I.n_eslots) * (4 + 3 * s) + nv * (4 + 8 * visc) * s +
+                          ne * 4 * s + rk;
+}
+
+hfd_status ensure_mixed_buffers(hfd_ctx* c) {
+  hfd_status s;
+  const hfd::HostSetup& h = c->hs;
+  const int64_t ne = h.ne, nv = h.nv, nvs = h.vptr[h.n_owned], nes = h.eptr[h.n_owned];
+  if (!c->fw5) {
+    if ((s = dalloc(c, &c->fn, 2 * ne)) || (s = dalloc(c, &c->fw5, 30 * ne)) ||
+        (s = dalloc(c, &c->fw3, 18 * ne)) || (s = dalloc(c, &c->fdv, 6 * nvs)) ||
+        (s = dalloc(c, &c->fde, 3 * nes)))
+      return s;
+    if (c->dvis && (s = dalloc(c, &c->fdvis, 5 * nvs))) return s;
+    if ((s = dalloc(c, &c->S0, 12 * nv)) || (s = dalloc(c, &c->S1, 12 * nv)) ||
+        (s = dalloc(c, &c->S2, 12 * nv)) || (s = dalloc(c, &c->SH, 4 * ne)))
+      return s;
+  }
+  HIPCHK(c, hfd::launch_cast(2 * ne, c->n, c->fn, nullptr));
+  HIPCHK(c, hfd::launch_cast(30 * ne, c->w5, c->fw5, nullptr));
+  HIPCHK(c, hfd::launch_cast(18 * ne, c->w3, c->fw3, nullptr));
+  HIPCHK(c, hfd::launch_cast(6 * nvs, c->dv, c->fdv, nullptr));
+  HIPCHK(c, hfd::launch_cast(3 * nes, c->de, c->fde, nullptr));
+  if (c->dvis) HIPCHK(c, hfd::launch_cast(5 * nvs, c->dvis, c->fdvis, nullptr));
+  HIPCHK(c, hipDeviceSynchronize());
+  return HFD_OK;
+}
+
+hfd::EdgeCoef<double> ecoef64(const hfd_ctx* c) { return {c->stg, c->n, c->w5, c->w3}; }
+hfd::EdgeCoef<float> ecoef32(const hfd_ctx* c) { return {c->stg, c->fn, c->fw5, c->fw3}; }
+hfd::VertexCoef<double> vcoef64(const hfd_ctx* c) {
+  return {c->vptr, c->eptr, c->vg, c->ve, c->dv, c->de, c->dvis};
+}
+hfd::VertexCoef<float> vcoef32(const hfd_ctx* c) {
+  return {c->vptr, c->eptr, c->vg, c->ve, c->fdv, c->fde, c->fdvis};
+}
+
+hfd_status need_device(const hfd_ctx* c) {
+  if (!c) return HFD_E_INVAL;
+  if (c->device < 0) return fail(const_cast<hfd_ctx*>(c), HFD_E_STATE, "host-only context");
+  return HFD_OK;
+}
+
+// Brackets one launch with events when timing is on (kind 0 edge, 1 vertex).
+struct PassTimer {
+  hfd_ctx* c;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  static hipEvent_t take(hfd_ctx* c) {
+    if (!c->ev_pool.empty()) {
+      hipEvent_t e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  PassTimer(hfd_ctx* c_, int k, hipStream_t s) : c(c_), kind(k), st(s) {
+    if (!c->timing) return;
+    a = take(c);
+    b = take(c);
+    if (a && b && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+  }
+  ~PassTimer() {
+    if (!c->timing || !a || !b) return;
+    if (hipEventRecord(b, st) == hipSuccess) c->ev_pending[kind].emplace_back(a, b);
+  }
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+hfd_status rk_step_impl(hfd_ctx* c, double* U, double dt, const double* dt_dev,
+                        hipStream_t st) {
+  const hfd::HostSetup& h = c->hs;
+  const int64_t nv = h.nv, ne = h.ne, no = h.n_owned;
+  const bool mx = mixed(c);
+  const GasParams gp = gas_params(c, mx);
+  const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+  const int64_t nd = int64_t(h.dir_rows.size());
+  if (!mx) {
+    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
+    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
+    const double* in[3] = {U, c->U1, c->U2};
+    double* outp[3] = {c->U1, c->U2, U};
+    for (int k = 0; k < 3; ++k) {
+      {
+        PassTimer t(c, 0, st);
+        HIPCHK(c, hfd::launch_edge64(ne, nv, ecoef64(c), gp, in[k], c->force, c->H,
+                                     nullptr, nullptr, st));
+      }
+      hfd::RkArgs rk{U, in[k], outp[k], nullptr, a[k], b[k], dt, dt_dev};
+      PassTimer t(c, 1, st);
+      HIPCHK(c, hfd::launch_vertex64(no, nv, vcoef64(c), gp, in[k], c->H, ne, 1,
+                                     nullptr, rk, c->flag, st));
+    }
+  } else {
+    HIPCHK(c, hfd::launch_to_shadow(nv, U, gp, c->S0, st));
+    HIPCHK(c, hfd::launch_copy_rows<float>(nd, c->dir_rows, nullptr, nv, c->S0, c->S1, st));
+    HIPCHK(c, hfd::launch_copy_rows<float>(nd, c->dir_rows, nullptr, nv, c->S0, c->S2, st));
+    const float* sin[3] = {c->S0, c->S1, c->S2};
+    float* sout[3] = {c->S1, c->S2, nullptr};
+    const double* in[3] = {U, c->U1, c->U2};
+    double* outp[3] = {c->U1, c->U2, U};
+    for (int k = 0; k < 3; ++k) {
+      {
+        PassTimer t(c, 0, st);
+        HIPCHK(c, hfd::launch_edge32(ne, nv, ecoef32(c), gp, sin[k], c->force, c->SH,
+                                     nullptr, nullptr, st));
+      }
+      hfd::RkArgs rk{U, in[k], outp[k], sout[k], a[k], b[k], dt, dt_dev};
+      PassTimer t(c, 1, st);
+      HIPCHK(c, hfd::launch_vertex32(no, nv, vcoef32(c), gp, sin[k], c->SH, ne, 1,
+                                     nullptr, rk, c->flag, st));
+    }
+  }
+  const int64_t ncp = int64_t(h.copy_rows.size());
+  HIPCHK(c, hfd::launch_copy_rows<double>(ncp, c->copy_rows, c->copy_src, nv, U, U, st));
+  return HFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hfd_default_opts(hfd_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->gamma = 1.4;
+  o->gas_R = 1.0;
+  o->mu = 0.0;
+  o->prandtl = 0.72;
+  o->weno_eps = 1e-6;
+  o->sw_lo = 0.01;
+  o->sw_hi = 0.79;
+  o->w3_cap = 0.0;
+  o->switch_mode = HFD_SWITCH_PAPER;
+  o->precision = HFD_FP64;
+  o->order = HFD_ORDER_HILBERT;
+}
+
+const char* hfd_status_string(hfd_status s) {
+  switch (s) {
+    case HFD_OK: return "ok";
+    case HFD_E_INVAL: return "invalid argument";
+    case HFD_E_MESH: return "unusable mesh";
+    case HFD_E_NOMEM: return "out of memory";
+    case HFD_E_DEVICE: return "device error";
+    case HFD_E_NUMERIC: return "non-finite or non-physical state";
+    case HFD_E_STATE: return "invalid call for this context";
+  }
+  return "unknown status";
+}
+
+const char* hfd_last_error(const hfd_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+hfd_status hfd_destroy(hfd_ctx* ctx) {
+  if (!ctx) return HFD_OK;
+  if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+  for (int k = 0; k < 2; ++k)
+    for (auto& pr : ctx->ev_pending[k]) {
+      (void)hipEventSynchronize(pr.second);
+      ctx->ev_pool.push_back(pr.first);
+      ctx->ev_pool.push_back(pr.second);
+    }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+  return HFD_OK;
+}
+
+hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t nt,
+                      const int32_t* ghost_src, const hfd_opts* o, int device,
+                      hfd_ctx** out) {
+  if (!out) return HFD_E_INVAL;
+  *out = nullptr;
+  hfd_ctx* c = new (std::nothrow) hfd_ctx();
+  if (!c) return HFD_E_NOMEM;
+  auto bail = [&](hfd_status s) {
+    g_create_err = c->err;
+    hfd_destroy(c);
+    return s;
+  };
+  if (o) c->o = *o;
+  else hfd_default_opts(&c->o);
+  const hfd_opts& op = c->o;
+  if (!(op.gamma > 1.0) || op.mu < 0.0 || !(op.weno_eps > 0.0) || op.w3_cap < 0.0 ||
+      op.switch_mode < 0 || op.switch_mode > 2 || op.precision < 0 || op.precision > 1 ||
+      op.period[0] < 0.0 || op.period[1] < 0.0 ||
+      (op.mu > 0.0 && (!(op.prandtl > 0.0) || !(op.gas_R > 0.0)))) {
+    c->err = "invalid options";
+    return bail(HFD_E_INVAL);
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  hfd_status s = hfd::host_setup(xy, nv, tri, nt, ghost_src, op, &c->hs, &c->err);
+  if (s != HFD_OK) return bail(s);
+  hfd::HostSetup& h = c->hs;
+  hfd_info& I = c->info;
+  I.nv = h.nv;
+  I.n_owned = h.n_owned;
+  I.n_dirichlet = h.n_dir;
+  I.n_copy_ghost = h.n_copy;
+  I.n_edges_mesh = h.ne_mesh;
+  I.n_edges = h.ne;
+  I.n_vslots = h.vptr[h.n_owned];
+  I.n_eslots = h.eptr[h.n_owned];
+  I.max_vslots = h.max_vs;
+  I.max_eslots = h.max_es;
+  I.setup_ms[0] = ms_since(t0);
+  if (I.n_vslots >= (int64_t(1) << 31) || I.n_eslots >= (int64_t(1) << 31)) {
+    c->err = "mesh too large for 32-bit slot offsets";
+    return bail(HFD_E_MESH);
+  }
+  const int64_t msys = 2 * int64_t(h.max_vs) + h.max_es;
+  if (msys > 192 || h.max_vs > 64) {
+    c->err = "divergence system with " + std::to_string(msys) + " rows (limit 192) or " +
+             std::to_string(h.max_vs) + " stencil vertices (limit 64)";
+    return bail(HFD_E_MESH);
+  }
+  byte_model(c);
+  if (device < 0) {
+    *out = c;
+    return HFD_OK;
+  }
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    c->err = "hipSetDevice failed";
+    return bail(HFD_E_DEVICE);
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  const int64_t ne = h.ne, no = h.n_owned, nvs = I.n_vslots, nes = I.n_eslots;
+  std::vector<int32_t> vp32(no + 1), ep32(no + 1);
+  for (int64_t k = 0; k <= no; ++k) {
+    vp32[k] = int32_t(h.vptr[k]);
+    ep32[k] = int32_t(h.eptr[k]);
+  }
+  double *d_pts = nullptr, *d_eh = nullptr, *d_vpts = nullptr, *d_mpts = nullptr,
+         *d_mnrm = nullptr, *d_vh = nullptr;
+  int64_t *d_vptr64 = nullptr, *d_eptr64 = nullptr;
+  int32_t* d_status = nullptr;
+  if ((s = upload(c, &c->stg, h.e_stg)) || (s = upload(c, &c->n, h.e_n)) ||
+      (s = upload(c, &c->vptr, vp32)) || (s = upload(c, &c->eptr, ep32)) ||
+      (s = upload(c, &c->vg, h.v_gather)) || (s = upload(c, &c->ve, h.v_edges)) ||
+      (s = upload(c, &c->hmin, h.v_hmin)) || (s = upload(c, &c->dir_rows, h.dir_rows)) ||
+      (s = upload(c, &c->copy_rows, h.copy_rows)) || (s = upload(c, &c->copy_src, h.copy_src)) ||
+      (s = upload(c, &d_pts, h.e_pts)) || (s = upload(c, &d_eh, h.e_h)) ||
+      (s = upload(c, &d_vpts, h.v_pts)) || (s = upload(c, &d_mpts, h.m_pts)) ||
+      (s = upload(c, &d_mnrm, h.m_nrm)) || (s = upload(c, &d_vh, h.v_h)) ||
+      (s = upload(c, &d_vptr64, h.vptr)) || (s = upload(c, &d_eptr64, h.eptr)))
+    return bail(s);
+  if ((s = dalloc(c, &c->w5, 30 * ne)) || (s = dalloc(c, &c->w3, 18 * ne)) ||
+      (s = dalloc(c, &c->rank, 2 * ne)) || (s = dalloc(c, &c->trunc3, 6 * ne)) ||
+      (s = dalloc(c, &c->dv, 6 * nvs)) || (s = dalloc(c, &c->de, 3 * nes)) ||
+      (s = dalloc(c, &d_status, no)) || (s = dalloc(c, &c->U1, 12 * h.nv)) ||
+      (s = dalloc(c, &c->U2, 12 * h.nv)) || (s = dalloc(c, &c->H, 4 * ne)) ||
+      (s = dalloc(c, &c->flag, 1)))
+    return bail(s);
+  if (op.mu > 0.0 && (s = dalloc(c, &c->dvis, 5 * nvs))) return bail(s);
+  c->ndtpart = std::max<int64_t>(1, std::min<int64_t>(1024, (no + 255) / 256));
+  if ((s = dalloc(c, &c->dtpart, c->ndtpart))) return bail(s);
+  if (hipMemset(c->flag, 0, sizeof(int32_t)) != hipSuccess) {
+    c->err = "hipMemset failed";
+    return bail(HFD_E_DEVICE);
+  }
+  I.setup_ms[1] = ms_since(t1);
+  auto t2 = std::chrono::steady_clock::now();
+  // ---- precompute ----------------------------------------------------------
+  const int rpl = (2 * h.max_vs + h.max_es) <= 128 ? 2 : 3;
+  hipError_t he;
+  if ((he = hfd::launch_edge_weights(ne, d_pts, d_eh, op.w3_cap, c->w5, c->w3, c->rank,
+                                     c->trunc3, nullptr)) != hipSuccess ||
+      (he = hfd::launch_div_rows(no, rpl, d_vptr64, d_eptr64, d_vpts, d_mpts, d_mnrm,
+                                 d_vh, c->dv, c->de, d_status, nullptr)) != hipSuccess ||
+      (he = hipDeviceSynchronize()) != hipSuccess) {
+    c->err = std::string("precompute: ") + hipGetErrorString(he);
+    return bail(HFD_E_DEVICE);
+  }
+  std::vector<int32_t> stat(no);
+  if (hipMemcpy(stat.data(), d_status, no * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+    c->err = "status copy failed";
+    return bail(HFD_E_DEVICE);
+  }
+  for (int64_t k = 0; k < no; ++k)
+    if (stat[k] == 1) {
+      c->err = "rank-deficient divergence system at vertex " +
+               std::to_string(h.old_of_new[k]);
+      return bail(HFD_E_MESH);
+    }
+  if (op.mu > 0.0) {
+    if ((he = hfd::launch_visc_rows(no, d_vptr64, d_vpts, d_vh, c->dvis, d_status,
+                                    nullptr)) != hipSuccess ||
+        (he = hipDeviceSynchronize()) != hipSuccess) {
+      c->err = std::string("viscous precompute: ") + hipGetErrorString(he);
+      return bail(HFD_E_DEVICE);
+    }
+  }
+  {
+    std::vector<int32_t> rk(2 * ne);
+    std::vector<int8_t> t3(6 * ne);
+    if (hipMemcpy(rk.data(), c->rank, rk.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(t3.data(), c->trunc3, t3.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      c->err = "rank copy failed";
+      return bail(HFD_E_DEVICE);
+    }
+    for (int32_t r : rk) I.rank_hist[std::min(15, std::max(0, r))]++;
+    for (int8_t t : t3) I.w3_truncated += (t > 0);
+  }
+  for (void* p : {(void*)d_pts, (void*)d_eh, (void*)d_vpts, (void*)d_mpts, (void*)d_mnrm,
+                  (void*)d_vh, (void*)d_vptr64, (void*)d_eptr64, (void*)d_status})
+    dfree(c, p);
+  // host copies of the frames are no longer needed
+  std::vector<double>().swap(h.e_pts);
+  std::vector<double>().swap(h.v_pts);
+  std::vector<double>().swap(h.m_pts);
+  std::vector<double>().swap(h.m_nrm);
+  I.setup_ms[2] = ms_since(t2);
+  if (mixed(c) && (s = ensure_mixed_buffers(c))) return bail(s);
+  I.setup_ms[3] = ms_since(t0);
+  *out = c;
+  return HFD_OK;
+}
+
+hfd_status hfd_get_info(const hfd_ctx* ctx, hfd_info* out) {
+  if (!ctx || !out) return HFD_E_INVAL;
+  *out = ctx->info;
+  return HFD_OK;
+}
+
+hfd_status hfd_permutation(const hfd_ctx* ctx, int32_t* new_of_old) {
+  if (!ctx || !new_of_old) return HFD_E_INVAL;
+  std::memcpy(new_of_old, ctx->hs.new_of_old.data(), ctx->hs.nv * sizeof(int32_t));
+  return HFD_OK;
+}
+
+hfd_status hfd_export_edges(const hfd_ctx* ctx, int32_t* ends, int32_t* stencil) {
+  if (!ctx) return HFD_E_INVAL;
+  if (ends) std::memcpy(ends, ctx->hs.e_end.data(), ctx->hs.e_end.size() * 4);
+  if (stencil) std::memcpy(stencil, ctx->hs.e_st.data(), ctx->hs.e_st.size() * 4);
+  return HFD_OK;
+}
+
+hfd_status hfd_export_vertex_stencils(const hfd_ctx* ctx, int64_t* vptr, int32_t* vnodes,
+                                      int64_t* eptr, int32_t* vedges) {
+  if (!ctx) return HFD_E_INVAL;
+  const hfd::HostSetup& h = ctx->hs;
+  if (vptr) std::memcpy(vptr, h.vptr.data(), h.vptr.size() * 8);
+  if (eptr) std::memcpy(eptr, h.eptr.data(), h.eptr.size() * 8);
+  if (vnodes) std::memcpy(vnodes, h.v_nodes.data(), h.v_nodes.size() * 4);
+  if (vedges) std::memcpy(vedges, h.v_edges.data(), h.v_edges.size() * 4);
+  return HFD_OK;
+}
+
+hfd_status hfd_export_weights(const hfd_ctx* ctx, double* w5, double* w3, int32_t* rank,
+                              double* dv, double* de, double* dvis) {
+  hfd_status s = need_device(ctx);
+  if (s) return s;
+  hfd_ctx* c = const_cast<hfd_ctx*>(ctx);
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  const int64_t ne = c->hs.ne;
+  auto soa_to_aos = [&](const double* d, int64_t rows, double* out) -> hfd_status {
+    std::vector<double> tmp(rows * ne);
+    HIPCHK(c, hipMemcpy(tmp.data(), d, tmp.size() * 8, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < ne; ++e)
+      for (int64_t r = 0; r < rows; ++r) out[e * rows + r] = tmp[r * ne + e];
+    return HFD_OK;
+  };
+  if (w5 && (s = soa_to_aos(c->w5, 30, w5))) return s;
+  if (w3 && (s = soa_to_aos(c->w3, 18, w3))) return s;
+  if (rank) {
+    std::vector<int32_t> tmp(2 * ne);
+    HIPCHK(c, hipMemcpy(tmp.data(), c->rank, tmp.size() * 4, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < ne; ++e)
+      for (int r = 0; r < 2; ++r) rank[2 * e + r] = tmp[r * ne + e];
+  }
+  if (dv) HIPCHK(c, hipMemcpy(dv, c->dv, 6 * c->info.n_vslots * 8, hipMemcpyDeviceToHost));
+  if (de) HIPCHK(c, hipMemcpy(de, c->de, 3 * c->info.n_eslots * 8, hipMemcpyDeviceToHost));
+  if (dvis) {
+    if (!c->dvis) return fail(c, HFD_E_STATE, "no viscous rows (mu == 0)");
+    HIPCHK(c, hipMemcpy(dvis, c->dvis, 5 * c->info.n_vslots * 8, hipMemcpyDeviceToHost));
+  }
+  return HFD_OK;
+}
+
+hfd_status hfd_import_weights(hfd_ctx* c, const double* w5, const double* w3,
+                              const double* dv, const double* de, const double* dvis) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  const int64_t ne = c->hs.ne;
+  auto aos_to_soa = [&](const double* in, int64_t rows, double* d) -> hfd_status {
+    std::vector<double> tmp(rows * ne);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int64_t r = 0; r < rows; ++r) tmp[r * ne + e] = in[e * rows + r];
+    HIPCHK(c, hipMemcpy(d, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
+    return HFD_OK;
+  };
+  if (w5 && (s = aos_to_soa(w5, 30, c->w5))) return s;
+  if (w3 && (s = aos_to_soa(w3, 18, c->w3))) return s;
+  if (dv) HIPCHK(c, hipMemcpy(c->dv, dv, 6 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
+  if (de) HIPCHK(c, hipMemcpy(c->de, de, 3 * c->info.n_eslots * 8, hipMemcpyHostToDevice));
+  if (dvis) {
+    if (!c->dvis) return fail(c, HFD_E_STATE, "no viscous rows (mu == 0)");
+    HIPCHK(c, hipMemcpy(c->dvis, dvis, 5 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
+  }
+  if (c->fw5) return ensure_mixed_buffers(c);
+  return HFD_OK;
+}
+
+hfd_status hfd_set_precision(hfd_ctx* c, int32_t precision, const double* w_ref) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (precision != HFD_FP64 && precision != HFD_FP32_MIXED)
+    return fail(c, HFD_E_INVAL, "precision must be HFD_FP64 or HFD_FP32_MIXED");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (w_ref)
+    for (int q = 0; q < 4; ++q) c->o.w_ref[q] = w_ref[q];
+  c->o.precision = precision;
+  byte_model(c);
+  if (precision == HFD_FP32_MIXED) return ensure_mixed_buffers(c);
+  return HFD_OK;
+}
+
+hfd_status hfd_residual(hfd_ctx* c, const double* U, double* dU, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !dU) return fail(c, HFD_E_INVAL, "null state");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hfd::HostSetup& h = c->hs;
+  hfd::RkArgs none{};
+  if (!mixed(c)) {
+    const GasParams gp = gas_params(c, false);
+    {
+      PassTimer t(c, 0, st);
+      HIPCHK(c, hfd::launch_edge64(h.ne, h.nv, ecoef64(c), gp, U, c->force, c->H, nullptr,
+                                   nullptr, st));
+    }
+    PassTimer t(c, 1, st);
+    HIPCHK(c, hfd::launch_vertex64(h.n_owned, h.nv, vcoef64(c), gp, U, c->H, h.ne, 0, dU,
+                                   none, c->flag, st));
+  } else {
+    const GasParams gp = gas_params(c, true);
+    HIPCHK(c, hfd::launch_to_shadow(h.nv, U, gp, c->S0, st));
+    {
+      PassTimer t(c, 0, st);
+      HIPCHK(c, hfd::launch_edge32(h.ne, h.nv, ecoef32(c), gp, c->S0, c->force, c->SH,
+                                   nullptr, nullptr, st));
+    }
+    PassTimer t(c, 1, st);
+    HIPCHK(c, hfd::launch_vertex32(h.n_owned, h.nv, vcoef32(c), gp, c->S0, c->SH, h.ne, 0,
+                                   dU, none, c->flag, st));
+  }
+  HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, dU, st));
+  return HFD_OK;
+}
+
+hfd_status hfd_rk_step(hfd_ctx* c, double* U, double dt, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U) return fail(c, HFD_E_INVAL, "null state");
+  return rk_step_impl(c, U, dt, nullptr, static_cast<hipStream_t>(stream));
+}
+
+hfd_status hfd_rk_step_dev(hfd_ctx* c, double* U, const double* dt_dev, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !dt_dev) return fail(c, HFD_E_INVAL, "null state or dt");
+  return rk_step_impl(c, U, 0.0, dt_dev, static_cast<hipStream_t>(stream));
+}
+
+hfd_status hfd_stable_dt(hfd_ctx* c, const double* U, double cfl, double* dt_dev,
+                         void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !dt_dev || !(cfl > 0.0)) return fail(c, HFD_E_INVAL, "null pointer or cfl <= 0");
+  HIPCHK(c, hfd::launch_stable_dt(c->hs.n_owned, c->hs.nv, U, c->hmin, c->o.gamma, cfl,
+                                  c->dtpart, c->ndtpart, dt_dev,
+                                  static_cast<hipStream_t>(stream)));
+  return HFD_OK;
+}
+
+hfd_status hfd_edge_states(hfd_ctx* c, const double* U, double* wlr, uint8_t* mask,
+                           double* hout, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !wlr) return fail(c, HFD_E_INVAL, "null state or output");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hfd::HostSetup& h = c->hs;
+  if (!mixed(c)) {
+    HIPCHK(c, hfd::launch_edge64(h.ne, h.nv, ecoef64(c), gas_params(c, false), U, c->force,
+                                 hout ? hout : c->H, wlr, mask, st));
+  } else {
+    const GasParams gp = gas_params(c, true);
+    HIPCHK(c, hfd::launch_to_shadow(h.nv, U, gp, c->S0, st));
+    HIPCHK(c, hfd::launch_edge32(h.ne, h.nv, ecoef32(c), gp, c->S0, c->force, c->SH, wlr,
+                                 mask, st));
+    if (hout) HIPCHK(c, hfd::launch_widen(4 * h.ne, c->SH, hout, st));
+  }
+  return HFD_OK;
+}
+
+hfd_status hfd_force_switch_mask(hfd_ctx* c, const uint8_t* mask_dev) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  c->force = mask_dev;
+  return HFD_OK;
+}
+
+hfd_status hfd_fill_ghosts(hfd_ctx* c, double* U, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U) return fail(c, HFD_E_INVAL, "null state");
+  const int64_t ncp = int64_t(c->hs.copy_rows.size());
+  HIPCHK(c, hfd::launch_copy_rows<double>(ncp, c->copy_rows, c->copy_src, c->hs.nv, U, U,
+                                          static_cast<hipStream_t>(stream)));
+  return HFD_OK;
+}
+
+hfd_status hfd_check(hfd_ctx* c, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(c, hipStreamSynchronize(st));
+  int32_t f = 0;
+  HIPCHK(c, hipMemcpy(&f, c->flag, sizeof(f), hipMemcpyDeviceToHost));
+  if (f) {
+    HIPCHK(c, hipMemset(c->flag, 0, sizeof(int32_t)));
+    return fail(c, HFD_E_NUMERIC, "non-finite value or rho <= 0 or p <= 0 at an owned vertex");
+  }
+  return HFD_OK;
+}
+
+hfd_status hfd_set_timing(hfd_ctx* c, int32_t on) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  c->timing = on != 0;
+  return HFD_OK;
+}
+
+hfd_status hfd_kernel_times(hfd_ctx* c, double* edge_ms, int64_t* n_edge, double* vertex_ms,
+                            int64_t* n_vertex) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  double tot[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
+  for (int k = 0; k < 2; ++k) {
+    for (auto& pr : c->ev_pending[k]) {
+      HIPCHK(c, hipEventSynchronize(pr.second));
+      float ms = 0.0f;
+      HIPCHK(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+      tot[k] += ms;
+      cnt[k] += 1;
+      c->ev_pool.push_back(pr.first);
+      c->ev_pool.push_back(pr.second);
+    }
+    c->ev_pending[k].clear();
+  }
+  if (edge_ms) *edge_ms = tot[0];
+  if (n_edge) *n_edge = cnt[0];
+  if (vertex_ms) *vertex_ms = tot[1];
+  if (n_vertex) *n_vertex = cnt[1];
+  return HFD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+the host-only setup validates its inputs (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2109_01286_amd import hfd, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "hfd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hfd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hfd.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hfd.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_sizes_match_header_layout():
+    # hfd_opts: 14 doubles + 8 int32; hfd_info: 8 int64 + 2 int32 + 17 int64 + 6 double
+    assert ctypes.sizeof(hfd.Opts) == 14 * 8 + 8 * 4
+    assert ctypes.sizeof(hfd.Info) == 8 * 8 + 2 * 4 + 17 * 8 + 6 * 8
+
+
+def test_default_opts():
+    o = hfd.default_opts()
+    assert o.gamma == 1.4 and o.weno_eps == 1e-6 and o.sw_lo == 0.01 and o.sw_hi == 0.79
+    assert o.switch_mode == 0 and o.precision == 0 and o.order == 1
+
+
+def _mesh():
+    return inputs.jittered_grid(9, 9, 1.0, 1.0, (False, False), 5, seed=2)
+
+
+def test_bad_triangle_index_is_a_mesh_error():
+    m = _mesh()
+    tri = m.tri.copy()
+    tri[3, 1] = m.nv + 5
+    with pytest.raises(hfd.HfdError) as e:
+        hfd.Solver(m.xy, tri, m.ghost_src, m.period, device=-1)
+    assert e.value.status == 2 and "triangle 3" in str(e.value)
+
+
+def test_ghost_source_must_be_owned():
+    m = _mesh()
+    gs = m.ghost_src.copy()
+    g = np.nonzero(gs >= 0)[0]
+    gs[g[0]] = g[1]            # a ghost copying another ghost
+    with pytest.raises(hfd.HfdError) as e:
+        hfd.Solver(m.xy, m.tri, gs, m.period, device=-1)
+    assert e.value.status == 2
+
+
+def test_invalid_options():
+    m = _mesh()
+    with pytest.raises(hfd.HfdError) as e:
+        hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1, gamma=0.9)
+    assert e.value.status == 1
+
+
+def test_dead_end_stencil_is_a_mesh_error():
+    # a single triangle: no edge can be extended twice
+    xy = np.array([[0, 0], [1, 0], [0, 1.0]])
+    tri = np.array([[0, 1, 2]], dtype=np.int32)
+    with pytest.raises(hfd.HfdError) as e:
+        hfd.Solver(xy, tri, None, (0, 0), device=-1)
+    assert e.value.status == 2 and "dead end" in str(e.value)
+
+
+def test_host_only_context_refuses_device_calls():
+    m = _mesh()
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1)
+    L = hfd.lib()
+    assert L.hfd_residual(S._h, None, None, None) == 6
+    assert L.hfd_rk_step(S._h, None, 0.1, None) == 6
+    assert S.info["n_owned"] == 81 and S.info["nv"] == 19 * 19

@@ -1,0 +1,55 @@
+"""Host setup of the library (C++) against the oracle: edges, six-node
+stencils, vertex stencils, active set and renumbering must agree bit for
+bit (integer results decided by float64 comparisons in the same order)."""
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh
+from paper_2109_01286_amd import inputs
+
+from ._helpers import edge_map, lib_solver
+
+CASES = [("vortex21", None, {}), ("riemann201", 31, {}), ("shockvortex2049", 25, {}),
+         ("tgv513", 33, {}), ("vortex257", 33, {"order": "none"})]
+
+
+@pytest.mark.parametrize("name,scale,opts", CASES)
+def test_stencils_bit_exact(name, scale, opts):
+    m, _, _ = inputs.workload(name, scale)
+    S = lib_solver(m, -1, **opts)
+    topo = omesh.build(m.xy, m.tri, m.ghost_src, m.period)
+    emap = edge_map(S, topo)
+    assert set(emap.tolist()) == set(np.nonzero(topo.active)[0].tolist())
+    ends, st = S.export_edges()
+    assert np.array_equal(topo.stencil[emap], st.astype(np.int64))
+    vptr, vn, eptr, ve = S.export_vertex_stencils()
+    owned = np.nonzero(m.ghost_src == -1)[0]
+    assert sorted(S.old_of_new[:S.n_owned].tolist()) == owned.tolist()
+    for k in range(S.n_owned):
+        v = int(S.old_of_new[k])
+        assert vn[vptr[k]:vptr[k + 1]].tolist() == topo.vnodes[v]
+        assert emap[ve[eptr[k]:eptr[k + 1]]].tolist() == topo.vedges[v]
+
+
+def test_renumbering_of_a_shuffled_mesh_gives_the_same_stencils():
+    m, _, _ = inputs.workload("riemann201", 21)
+    ms = inputs.shuffled(m, seed=9)
+    S = lib_solver(ms, -1)
+    topo = omesh.build(ms.xy, ms.tri, ms.ghost_src, ms.period)
+    emap = edge_map(S, topo)
+    _, st = S.export_edges()
+    assert np.array_equal(topo.stencil[emap], st.astype(np.int64))
+    # Hilbert order keeps neighbours close: mean index distance along edges
+    ends, _ = S.export_edges()
+    a, b = S.new_of_old[ends[:, 0]], S.new_of_old[ends[:, 1]]
+    assert np.median(np.abs(a - b)) < 0.05 * S.nv
+    # owned vertices first, then Dirichlet, then copying ghosts
+    g = ms.ghost_src[S.old_of_new]
+    assert (g[:S.n_owned] == -1).all() and (g[S.n_owned:] != -1).all()
+
+
+def test_sizes_match_the_lattice_recipe():
+    m, _, _ = inputs.workload("riemann201", 201)
+    S = lib_solver(m, -1)
+    assert S.info["n_owned"] == 40401 and S.info["nv"] == 44521
+    assert S.info["n_edges_mesh"] == 132720
