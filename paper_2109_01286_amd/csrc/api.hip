@@ -35,9 +35,17 @@ struct hfd_ctx {
   // float32 copies (mixed form)
   float *fn = nullptr, *fw5 = nullptr, *fw3 = nullptr, *fdv = nullptr,
         *fde = nullptr, *fdvis = nullptr;
-  // work buffers
-  double *U1 = nullptr, *U2 = nullptr, *H = nullptr;
-  float *S0 = nullptr, *S1 = nullptr, *S2 = nullptr, *SH = nullptr;
+  // work buffers: float64 Runge-Kutta stage states [12][nv], and per
+  // precision the gather-layout stage states and the edge fluxes
+  double *U1 = nullptr, *U2 = nullptr;
+  template <class T>
+  struct Bufs {
+    hfd::V4<T>* Gv[3] = {nullptr, nullptr, nullptr};
+    hfd::V4<T>* Gg[3] = {nullptr, nullptr, nullptr};
+    hfd::V4<T>* H = nullptr;
+  };
+  Bufs<double> b64;
+  Bufs<float> b32;
   double* dtpart = nullptr;
   int64_t ndtpart = 0;
   int32_t* flag = nullptr;
@@ -120,11 +128,19 @@ void byte_model(hfd_ctx* c) {
   // vertex pass: CSR offsets and ids, coefficient records, state (values,
   // plus gradients with viscosity), edge fluxes, float64 RK update
   // averaged over the three stages: U^n read and U^new written every stage,
-  // U^k read in stages 2 and 3, float32 shadow written in stages 1 and 2
-  double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + (mixed(c) ? (2.0 / 3.0) * 48.0 : 0.0));
+  // U^k read in stages 2 and 3, gather-layout copy written in stages 1 and 2
+  double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + (2.0 / 3.0) * 12 * s);
   I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (4 + 6 * s + visc * 5 * s) +
                           double(I.n_eslots) * (4 + 3 * s) + nv * (4 + 8 * visc) * s +
                           ne * 4 * s + rk;
+}
+
+template <class T>
+hfd_status alloc_bufs(hfd_ctx* c, hfd_ctx::Bufs<T>& B, int64_t nv, int64_t ne) {
+  hfd_status s;
+  for (int k = 0; k < 3; ++k)
+    if ((s = dalloc(c, &B.Gv[k], nv)) || (s = dalloc(c, &B.Gg[k], 2 * nv))) return s;
+  return dalloc(c, &B.H, ne);
 }
 
 hfd_status ensure_mixed_buffers(hfd_ctx* c) {
@@ -137,9 +153,7 @@ hfd_status ensure_mixed_buffers(hfd_ctx* c) {
         (s = dalloc(c, &c->fde, 3 * nes)))
       return s;
     if (c->dvis && (s = dalloc(c, &c->fdvis, 5 * nvs))) return s;
-    if ((s = dalloc(c, &c->S0, 12 * nv)) || (s = dalloc(c, &c->S1, 12 * nv)) ||
-        (s = dalloc(c, &c->S2, 12 * nv)) || (s = dalloc(c, &c->SH, 4 * ne)))
-      return s;
+    if ((s = alloc_bufs(c, c->b32, nv, ne))) return s;
   }
   HIPCHK(c, hfd::launch_cast(2 * ne, c->n, c->fn, nullptr));
   HIPCHK(c, hfd::launch_cast(30 * ne, c->w5, c->fw5, nullptr));
@@ -198,52 +212,75 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-hfd_status rk_step_impl(hfd_ctx* c, double* U, double dt, const double* dt_dev,
-                        hipStream_t st) {
+template <class T>
+hfd_status rk_step_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
+                     const hfd::VertexCoef<T>& vc, bool mx, double* U, double dt,
+                     const double* dt_dev, hipStream_t st) {
   const hfd::HostSetup& h = c->hs;
   const int64_t nv = h.nv, ne = h.ne, no = h.n_owned;
-  const bool mx = mixed(c);
   const GasParams gp = gas_params(c, mx);
   const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
   const int64_t nd = int64_t(h.dir_rows.size());
-  if (!mx) {
-    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
-    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
-    const double* in[3] = {U, c->U1, c->U2};
-    double* outp[3] = {c->U1, c->U2, U};
-    for (int k = 0; k < 3; ++k) {
-      {
-        PassTimer t(c, 0, st);
-        HIPCHK(c, hfd::launch_edge64(ne, nv, ecoef64(c), gp, in[k], c->force, c->H,
-                                     nullptr, nullptr, st));
-      }
-      hfd::RkArgs rk{U, in[k], outp[k], nullptr, a[k], b[k], dt, dt_dev};
-      PassTimer t(c, 1, st);
-      HIPCHK(c, hfd::launch_vertex64(no, nv, vcoef64(c), gp, in[k], c->H, ne, 1,
-                                     nullptr, rk, c->flag, st));
+  HIPCHK(c, hfd::launch_to_gather<T>(nv, U, gp, B.Gv[0], B.Gg[0], st));
+  for (int k = 1; k < 3; ++k)
+    HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
+                                              B.Gg[k], st));
+  const double* in[3] = {U, c->U1, c->U2};
+  double* outp[3] = {c->U1, c->U2, U};
+  for (int k = 0; k < 3; ++k) {
+    {
+      PassTimer t(c, 0, st);
+      HIPCHK(c, hfd::launch_edge<T>(ne, ec, gp, B.Gv[k], B.Gg[k], c->force, B.H, nullptr,
+                                    nullptr, nullptr, st));
     }
-  } else {
-    HIPCHK(c, hfd::launch_to_shadow(nv, U, gp, c->S0, st));
-    HIPCHK(c, hfd::launch_copy_rows<float>(nd, c->dir_rows, nullptr, nv, c->S0, c->S1, st));
-    HIPCHK(c, hfd::launch_copy_rows<float>(nd, c->dir_rows, nullptr, nv, c->S0, c->S2, st));
-    const float* sin[3] = {c->S0, c->S1, c->S2};
-    float* sout[3] = {c->S1, c->S2, nullptr};
-    const double* in[3] = {U, c->U1, c->U2};
-    double* outp[3] = {c->U1, c->U2, U};
-    for (int k = 0; k < 3; ++k) {
-      {
-        PassTimer t(c, 0, st);
-        HIPCHK(c, hfd::launch_edge32(ne, nv, ecoef32(c), gp, sin[k], c->force, c->SH,
-                                     nullptr, nullptr, st));
-      }
-      hfd::RkArgs rk{U, in[k], outp[k], sout[k], a[k], b[k], dt, dt_dev};
-      PassTimer t(c, 1, st);
-      HIPCHK(c, hfd::launch_vertex32(no, nv, vcoef32(c), gp, sin[k], c->SH, ne, 1,
-                                     nullptr, rk, c->flag, st));
-    }
+    hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, dt_dev};
+    PassTimer t(c, 1, st);
+    HIPCHK(c, hfd::launch_vertex<T>(no, nv, vc, gp, B.Gv[k], B.Gg[k], B.H, 1, nullptr, rk,
+                                    k < 2 ? B.Gv[k + 1] : nullptr,
+                                    k < 2 ? B.Gg[k + 1] : nullptr, c->flag, st));
   }
   const int64_t ncp = int64_t(h.copy_rows.size());
   HIPCHK(c, hfd::launch_copy_rows<double>(ncp, c->copy_rows, c->copy_src, nv, U, U, st));
+  return HFD_OK;
+}
+
+hfd_status rk_step_impl(hfd_ctx* c, double* U, double dt, const double* dt_dev,
+                        hipStream_t st) {
+  if (mixed(c)) return rk_step_t<float>(c, c->b32, ecoef32(c), vcoef32(c), true, U, dt, dt_dev, st);
+  return rk_step_t<double>(c, c->b64, ecoef64(c), vcoef64(c), false, U, dt, dt_dev, st);
+}
+
+template <class T>
+hfd_status residual_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
+                      const hfd::VertexCoef<T>& vc, bool mx, const double* U, double* dU,
+                      hipStream_t st) {
+  const hfd::HostSetup& h = c->hs;
+  const GasParams gp = gas_params(c, mx);
+  HIPCHK(c, hfd::launch_to_gather<T>(h.nv, U, gp, B.Gv[0], B.Gg[0], st));
+  {
+    PassTimer t(c, 0, st);
+    HIPCHK(c, hfd::launch_edge<T>(h.ne, ec, gp, B.Gv[0], B.Gg[0], c->force, B.H, nullptr,
+                                  nullptr, nullptr, st));
+  }
+  hfd::RkArgs none{};
+  {
+    PassTimer t(c, 1, st);
+    HIPCHK(c, hfd::launch_vertex<T>(h.n_owned, h.nv, vc, gp, B.Gv[0], B.Gg[0], B.H, 0, dU,
+                                    none, nullptr, nullptr, c->flag, st));
+  }
+  HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, dU, st));
+  return HFD_OK;
+}
+
+template <class T>
+hfd_status edge_states_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
+                         bool mx, const double* U, double* wlr, uint8_t* mask, double* hout,
+                         hipStream_t st) {
+  const hfd::HostSetup& h = c->hs;
+  const GasParams gp = gas_params(c, mx);
+  HIPCHK(c, hfd::launch_to_gather<T>(h.nv, U, gp, B.Gv[0], B.Gg[0], st));
+  HIPCHK(c, hfd::launch_edge<T>(h.ne, ec, gp, B.Gv[0], B.Gg[0], c->force, B.H, hout, wlr,
+                                mask, st));
   return HFD_OK;
 }
 
@@ -382,7 +419,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
       (s = dalloc(c, &c->rank, 2 * ne)) || (s = dalloc(c, &c->trunc3, 6 * ne)) ||
       (s = dalloc(c, &c->dv, 6 * nvs)) || (s = dalloc(c, &c->de, 3 * nes)) ||
       (s = dalloc(c, &d_status, no)) || (s = dalloc(c, &c->U1, 12 * h.nv)) ||
-      (s = dalloc(c, &c->U2, 12 * h.nv)) || (s = dalloc(c, &c->H, 4 * ne)) ||
+      (s = dalloc(c, &c->U2, 12 * h.nv)) || (s = alloc_bufs(c, c->b64, h.nv, ne)) ||
       (s = dalloc(c, &c->flag, 1)))
     return bail(s);
   if (op.mu > 0.0 && (s = dalloc(c, &c->dvis, 5 * nvs))) return bail(s);
@@ -557,32 +594,8 @@ hfd_status hfd_residual(hfd_ctx* c, const double* U, double* dU, void* stream) {
   if (s) return s;
   if (!U || !dU) return fail(c, HFD_E_INVAL, "null state");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const hfd::HostSetup& h = c->hs;
-  hfd::RkArgs none{};
-  if (!mixed(c)) {
-    const GasParams gp = gas_params(c, false);
-    {
-      PassTimer t(c, 0, st);
-      HIPCHK(c, hfd::launch_edge64(h.ne, h.nv, ecoef64(c), gp, U, c->force, c->H, nullptr,
-                                   nullptr, st));
-    }
-    PassTimer t(c, 1, st);
-    HIPCHK(c, hfd::launch_vertex64(h.n_owned, h.nv, vcoef64(c), gp, U, c->H, h.ne, 0, dU,
-                                   none, c->flag, st));
-  } else {
-    const GasParams gp = gas_params(c, true);
-    HIPCHK(c, hfd::launch_to_shadow(h.nv, U, gp, c->S0, st));
-    {
-      PassTimer t(c, 0, st);
-      HIPCHK(c, hfd::launch_edge32(h.ne, h.nv, ecoef32(c), gp, c->S0, c->force, c->SH,
-                                   nullptr, nullptr, st));
-    }
-    PassTimer t(c, 1, st);
-    HIPCHK(c, hfd::launch_vertex32(h.n_owned, h.nv, vcoef32(c), gp, c->S0, c->SH, h.ne, 0,
-                                   dU, none, c->flag, st));
-  }
-  HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, dU, st));
-  return HFD_OK;
+  if (mixed(c)) return residual_t<float>(c, c->b32, ecoef32(c), vcoef32(c), true, U, dU, st);
+  return residual_t<double>(c, c->b64, ecoef64(c), vcoef64(c), false, U, dU, st);
 }
 
 hfd_status hfd_rk_step(hfd_ctx* c, double* U, double dt, void* stream) {
@@ -616,18 +629,8 @@ hfd_status hfd_edge_states(hfd_ctx* c, const double* U, double* wlr, uint8_t* ma
   if (s) return s;
   if (!U || !wlr) return fail(c, HFD_E_INVAL, "null state or output");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const hfd::HostSetup& h = c->hs;
-  if (!mixed(c)) {
-    HIPCHK(c, hfd::launch_edge64(h.ne, h.nv, ecoef64(c), gas_params(c, false), U, c->force,
-                                 hout ? hout : c->H, wlr, mask, st));
-  } else {
-    const GasParams gp = gas_params(c, true);
-    HIPCHK(c, hfd::launch_to_shadow(h.nv, U, gp, c->S0, st));
-    HIPCHK(c, hfd::launch_edge32(h.ne, h.nv, ecoef32(c), gp, c->S0, c->force, c->SH, wlr,
-                                 mask, st));
-    if (hout) HIPCHK(c, hfd::launch_widen(4 * h.ne, c->SH, hout, st));
-  }
-  return HFD_OK;
+  if (mixed(c)) return edge_states_t<float>(c, c->b32, ecoef32(c), true, U, wlr, mask, hout, st);
+  return edge_states_t<double>(c, c->b64, ecoef64(c), false, U, wlr, mask, hout, st);
 }
 
 hfd_status hfd_force_switch_mask(hfd_ctx* c, const uint8_t* mask_dev) {

@@ -50,43 +50,48 @@ struct VertexCoef {
   const T* dvis;           // [n_vslots][5] or null
 };
 
-// Edge pass: H[4][ne] (and optional states / mask).  U is float64 in the FP64
-// form (Us = null) or the float32 perturbation state in the mixed form.
-hipError_t launch_edge64(int64_t ne, int64_t nv, const EdgeCoef<double>& c,
-                         const GasParams& gp, const double* U,
-                         const uint8_t* force, double* H, double* wlr,
-                         uint8_t* mask, hipStream_t st);
-hipError_t launch_edge32(int64_t ne, int64_t nv, const EdgeCoef<float>& c,
-                         const GasParams& gp, const float* Us,
-                         const uint8_t* force, float* H, double* wlr,
-                         uint8_t* mask, hipStream_t st);
+// Gather layout of a stage state: values Gv[nv] and gradients Gg[2 nv]
+// (x then y) as 4-vectors, so that one vertex's data is one or two
+// contiguous 16/32-byte loads.  In the mixed form it holds w - w_ref.
+template <class T>
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
+};
 
-// Vertex pass.  mode 0: dU = R (float64 rows, owned vertices);
-// mode 1: Unew = a*Un + b*(Uk + dt*R) in float64, plus the float32 shadow
-// (mixed form).  dt is read from dt_dev when non-null.
+// Edge pass: H[ne] (4 components per edge), optional float64 copies
+// hsoa[4][ne], states wlr[8][ne] and WENO mask.
+template <class T>
+hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
+                       const V4<T>* Gv, const V4<T>* Gg, const uint8_t* force, V4<T>* H,
+                       double* hsoa, double* wlr, uint8_t* mask, hipStream_t st);
+
+// Vertex pass.  mode 0: dU = R (float64 rows [12][nv], owned vertices);
+// mode 1: Unew = a*Un + b*(Uk + dt*R) in float64 (dt from dt_dev when
+// non-null), plus the gather-layout copy of Unew when Gv_new is non-null.
 struct RkArgs {
   const double* Un;
   const double* Uk;
   double* Unew;
-  float* Us_new;       // mixed form: float32 perturbation shadow of Unew
   double a, b, dt;
   const double* dt_dev;
 };
-hipError_t launch_vertex64(int64_t nowned, int64_t nv, const VertexCoef<double>& c,
-                           const GasParams& gp, const double* U, const double* H,
-                           int64_t ne, int mode, double* dU, const RkArgs& rk,
-                           int32_t* flag, hipStream_t st);
-hipError_t launch_vertex32(int64_t nowned, int64_t nv, const VertexCoef<float>& c,
-                           const GasParams& gp, const float* Us, const float* H,
-                           int64_t ne, int mode, double* dU, const RkArgs& rk,
-                           int32_t* flag, hipStream_t st);
+template <class T>
+hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
+                         const GasParams& gp, const V4<T>* Gv, const V4<T>* Gg,
+                         const V4<T>* H, int mode, double* dU, const RkArgs& rk,
+                         V4<T>* Gv_new, V4<T>* Gg_new, int32_t* flag, hipStream_t st);
+
+template <class T>
+hipError_t launch_to_gather(int64_t nv, const double* U, const GasParams& gp, V4<T>* Gv,
+                            V4<T>* Gg, hipStream_t st);
+template <class T>
+hipError_t launch_copy_gather_rows(int64_t nrows, const int32_t* rows, const V4<T>* fv,
+                                   const V4<T>* fg, V4<T>* tv, V4<T>* tg, hipStream_t st);
 
 // Ghost rows and helpers.
 template <class T>
 hipError_t launch_copy_rows(int64_t nrows, const int32_t* rows, const int32_t* src,
                             int64_t nv, const T* from, T* to, hipStream_t st);
-hipError_t launch_to_shadow(int64_t nv, const double* U, const GasParams& gp,
-                            float* Us, hipStream_t st);
 hipError_t launch_zero_ghost_rows(int64_t nowned, int64_t nv, double* dU,
                                   hipStream_t st);
 hipError_t launch_stable_dt(int64_t nowned, int64_t nv, const double* U,

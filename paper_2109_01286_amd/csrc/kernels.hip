@@ -86,9 +86,10 @@ __device__ inline Ref<T> make_ref(const GasParams& gp) {
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(256)
-k_edge(int64_t ne, int64_t nv, EdgeCoef<T> c, GasParams gp,
-       const T* __restrict__ U, const uint8_t* __restrict__ force,
-       T* __restrict__ H, double* __restrict__ wlr, uint8_t* __restrict__ mask) {
+k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
+       const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
+       V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
+       uint8_t* __restrict__ mask) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const Ref<T> ref = make_ref<T>(gp);
@@ -101,10 +102,11 @@ k_edge(int64_t ne, int64_t nv, EdgeCoef<T> c, GasParams gp,
   // Roe average of the two end states (nodes i, i+1)
   T u, v, hh, cc;
   {
-    T ra = ref.w[0] + U[id[2]], rb = ref.w[0] + U[id[3]];
-    T ua = (ref.w[1] + U[nv + id[2]]) / ra, ub = (ref.w[1] + U[nv + id[3]]) / rb;
-    T va = (ref.w[2] + U[2 * nv + id[2]]) / ra, vb = (ref.w[2] + U[2 * nv + id[3]]) / rb;
-    T Ea = ref.w[3] + U[3 * nv + id[2]], Eb = ref.w[3] + U[3 * nv + id[3]];
+    const V4<T> A = Gv[id[2]], B = Gv[id[3]];
+    T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
+    T ua = (ref.w[1] + A.y) / ra, ub = (ref.w[1] + B.y) / rb;
+    T va = (ref.w[2] + A.z) / ra, vb = (ref.w[2] + B.z) / rb;
+    T Ea = ref.w[3] + A.w, Eb = ref.w[3] + B.w;
     T pa = gm1 * (Ea - T(0.5) * ra * (ua * ua + va * va));
     T pb = gm1 * (Eb - T(0.5) * rb * (ub * ub + vb * vb));
     T sa = sqrt(ra), sb = sqrt(rb);
@@ -128,13 +130,10 @@ k_edge(int64_t ne, int64_t nv, EdgeCoef<T> c, GasParams gp,
   T cv[4][6], cx[4][6], cy[4][6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    T w[4], wx[4], wy[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      w[q] = U[q * nv + id[j]];
-      wx[q] = U[(4 + q) * nv + id[j]];
-      wy[q] = U[(8 + q) * nv + id[j]];
-    }
+    const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
+    const T w[4] = {a.x, a.y, a.z, a.w};
+    const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
+    const T wy[4] = {by.x, by.y, by.z, by.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       cv[q][j] = L[q][0] * w[0] + L[q][1] * w[1] + L[q][2] * w[2] + L[q][3] * w[3];
@@ -215,11 +214,15 @@ k_edge(int64_t ne, int64_t nv, EdgeCoef<T> c, GasParams gp,
   const T sr = fabs(ur * nx + vr * ny) + sqrt(gam * pr / rr);
   // NaN-propagating maximum: a non-physical state must not be hidden
   const T lam = (isnan(sl) || isnan(sr)) ? sl + sr : (sl > sr ? sl : sr);
+  T h[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    T h = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
-          T(0.5) * lam * (wr[q] - wl[q]);
-    H[q * ne + e] = h;
+  for (int q = 0; q < 4; ++q)
+    h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
+           T(0.5) * lam * (wr[q] - wl[q]);
+  H[e] = V4<T>{h[0], h[1], h[2], h[3]};
+  if (hsoa) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hsoa[q * ne + e] = double(h[q]);
   }
   if (wlr) {
 #pragma unroll
@@ -234,7 +237,8 @@ k_edge(int64_t ne, int64_t nv, EdgeCoef<T> c, GasParams gp,
 // ---------------------------------------------------------------------------
 // Vertex pass
 // ---------------------------------------------------------------------------
-constexpr int VL = 16;  // lanes per vertex
+constexpr int VL = 16;       // lanes per vertex
+constexpr int VPB = 16;      // vertices per block (256 threads)
 
 template <class T>
 __device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
@@ -268,65 +272,113 @@ __device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
   gv[3] = u * txy + v * tyy + kap * Ty;
 }
 
+// Contribution of one vertex slot (node u of S(v)) to the 12 accumulators.
+template <class T, bool VISC>
+__device__ inline void vslot(const V4<T>& a, const V4<T>* gx, const T* d, const T* k,
+                             const Ref<T>& ref, T gm1, const GasParams& gp, T acc[12]) {
+  const T w[4] = {a.x, a.y, a.z, a.w};
+  T f[4], g[4];
+  pert_flux<T>(w, ref, gm1, f, g);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[q] -= d[0] * f[q] + d[1] * g[q];
+    acc[4 + q] -= d[2] * f[q] + d[3] * g[q];
+    acc[8 + q] -= d[4] * f[q] + d[5] * g[q];
+  }
+  if (VISC) {
+    const T wf[4] = {w[0] + ref.w[0], w[1] + ref.w[1], w[2] + ref.w[2], w[3] + ref.w[3]};
+    const T wx[4] = {gx[0].x, gx[0].y, gx[0].z, gx[0].w};
+    const T wy[4] = {gx[1].x, gx[1].y, gx[1].z, gx[1].w};
+    T fv[4], gv[4];
+    viscous_flux<T>(wf, wx, wy, gp, fv, gv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[q] += k[0] * fv[q] + k[1] * gv[q];
+      acc[4 + q] += k[2] * fv[q] + k[3] * gv[q];
+      acc[8 + q] += k[3] * fv[q] + k[4] * gv[q];
+    }
+  }
+}
+
 template <class T, bool VISC>
 __global__ void __launch_bounds__(256)
 k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
-         const T* __restrict__ U, const T* __restrict__ H, int64_t ne, int mode,
-         double* __restrict__ dU, RkArgs rk, int32_t* __restrict__ flag) {
-  const int sub = threadIdx.x & (VL - 1);
-  const int64_t v = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / VL;
-  if (v >= nowned) return;
+         const V4<T>* __restrict__ Gv, const V4<T>* __restrict__ Gg,
+         const V4<T>* __restrict__ H, int mode, double* __restrict__ dU, RkArgs rk,
+         V4<T>* __restrict__ Gv_new, V4<T>* __restrict__ Gg_new,
+         int32_t* __restrict__ flag) {
+  __shared__ double sres[VPB][13];
+  const int vl = threadIdx.x / VL, sub = threadIdx.x & (VL - 1);
+  const int64_t v0 = int64_t(blockIdx.x) * VPB;
+  const int64_t v = v0 + vl;
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = T(gp.gamma - 1.0);
   T acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = T(0);
 
-  const int s0 = c.vptr[v], s1 = c.vptr[v + 1];
-  for (int s = s0 + sub; s < s1; s += VL) {
-    const int u = c.vg[s];
-    T w[4], f[4], g[4];
+  if (v < nowned) {
+    // vertex slots, two per lane and iteration (all loads issued first)
+    const int s0 = c.vptr[v], s1 = c.vptr[v + 1];
+    for (int s = s0 + sub; s < s1; s += 2 * VL) {
+      const int sb = (s + VL < s1) ? s + VL : s;
+      const int ua = c.vg[s], ub = c.vg[sb];
+      T da[6], db[6], ka[5], kb[5];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) w[q] = U[q * nv + u];
-    pert_flux<T>(w, ref, gm1, f, g);
-    const T* d = c.dv + int64_t(6) * s;
-    const T d0f = d[0], d0g = d[1], dxf = d[2], dxg = d[3], dyf = d[4], dyg = d[5];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      acc[q] -= d0f * f[q] + d0g * g[q];
-      acc[4 + q] -= dxf * f[q] + dxg * g[q];
-      acc[8 + q] -= dyf * f[q] + dyg * g[q];
-    }
-    if (VISC) {
-      T wf[4], wx[4], wy[4], fv[4], gv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        wf[q] = w[q] + ref.w[q];
-        wx[q] = U[(4 + q) * nv + u];
-        wy[q] = U[(8 + q) * nv + u];
+      for (int q = 0; q < 6; ++q) {
+        da[q] = c.dv[int64_t(6) * s + q];
+        db[q] = c.dv[int64_t(6) * sb + q];
       }
-      viscous_flux<T>(wf, wx, wy, gp, fv, gv);
-      const T* k = c.dvis + int64_t(5) * s;
-      const T k0 = k[0], k1 = k[1], k2 = k[2], k3 = k[3], k4 = k[4];
+      if (VISC) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        acc[q] += k0 * fv[q] + k1 * gv[q];
-        acc[4 + q] += k2 * fv[q] + k3 * gv[q];
-        acc[8 + q] += k3 * fv[q] + k4 * gv[q];
+        for (int q = 0; q < 5; ++q) {
+          ka[q] = c.dvis[int64_t(5) * s + q];
+          kb[q] = c.dvis[int64_t(5) * sb + q];
+        }
       }
+      const V4<T> A = Gv[ua], B = Gv[ub];
+      V4<T> gA[2], gB[2];
+      if (VISC) {
+        gA[0] = Gg[2 * int64_t(ua)];
+        gA[1] = Gg[2 * int64_t(ua) + 1];
+        gB[0] = Gg[2 * int64_t(ub)];
+        gB[1] = Gg[2 * int64_t(ub) + 1];
+      }
+      vslot<T, VISC>(A, gA, da, ka, ref, gm1, gp, acc);
+      if (sb != s) vslot<T, VISC>(B, gB, db, kb, ref, gm1, gp, acc);
     }
-  }
-  const int e0 = c.eptr[v], e1 = c.eptr[v + 1];
-  for (int s = e0 + sub; s < e1; s += VL) {
-    const int m = c.ve[s];
-    const T* d = c.de + int64_t(3) * s;
-    const T d0 = d[0], dx = d[1], dy = d[2];
+    // edge slots, four per lane and iteration
+    const int e0 = c.eptr[v], e1 = c.eptr[v + 1];
+    for (int s = e0 + sub; s < e1; s += 4 * VL) {
+      int j[4];
+      bool ok[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T h = H[q * ne + m];
-      acc[q] -= d0 * h;
-      acc[4 + q] -= dx * h;
-      acc[8 + q] -= dy * h;
+      for (int k = 0; k < 4; ++k) {
+        ok[k] = s + k * VL < e1;
+        j[k] = ok[k] ? s + k * VL : s;
+      }
+      int m[4];
+      T d[4][3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        m[k] = c.ve[j[k]];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) d[k][q] = c.de[int64_t(3) * j[k] + q];
+      }
+      V4<T> h[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) h[k] = H[m[k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!ok[k]) continue;
+        const T hq[4] = {h[k].x, h[k].y, h[k].z, h[k].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[q] -= d[k][0] * hq[q];
+          acc[4 + q] -= d[k][1] * hq[q];
+          acc[8 + q] -= d[k][2] * hq[q];
+        }
+      }
     }
   }
 #pragma unroll
@@ -338,31 +390,71 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
 #pragma unroll
   for (int k = 1; k < 12; ++k)
     if (sub == k) r = acc[k];
-  const int comp = sub < 12 ? sub : 0;
+  if (sub < 12) sres[vl][sub] = double(r);
+  __syncthreads();
+
+  // epilogue: thread (component cmp, vertex vl2), consecutive vertices in
+  // consecutive lanes so every component row is written in 16-wide runs
+  const int t = threadIdx.x;
   bool bad = false;
-  double out = 0.0;
-  if (mode == 0) {
-    out = double(r);
-    if (sub < 12) dU[int64_t(comp) * nv + v] = out;
-    bad = !isfinite(out);
-  } else {
-    const double dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
-    const int64_t o = int64_t(comp) * nv + v;
-    out = rk.a * rk.Un[o] + rk.b * (rk.Uk[o] + dt * double(r));
-    if (sub < 12) {
-      rk.Unew[o] = out;
-      if (rk.Us_new) rk.Us_new[o] = float(out - (comp < 4 ? gp.wref[comp] : 0.0));
-    }
-    bad = !isfinite(out);
-    // positivity of rho and p at the new state
-    const double rho = __shfl(out, 0, VL), m = __shfl(out, 1, VL),
-                 n = __shfl(out, 2, VL), E = __shfl(out, 3, VL);
-    if (sub == 0) {
-      const double p = (gp.gamma - 1.0) * (E - 0.5 * (m * m + n * n) / rho);
-      bad = bad || !(rho > 0.0) || !(p > 0.0);
+  if (t < 12 * VPB) {
+    const int cmp = t / VPB, vl2 = t % VPB;
+    const int64_t vv = v0 + vl2;
+    if (vv < nowned) {
+      const double rv = sres[vl2][cmp];
+      const int64_t o = int64_t(cmp) * nv + vv;
+      if (mode == 0) {
+        dU[o] = rv;
+        bad = !isfinite(rv);
+      } else {
+        const double dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
+        const double out = rk.a * rk.Un[o] + rk.b * (rk.Uk[o] + dt * rv);
+        rk.Unew[o] = out;
+        if (Gv_new) {
+          const T g = T(out - (cmp < 4 ? gp.wref[cmp] : 0.0));
+          if (cmp < 4) reinterpret_cast<T*>(Gv_new)[4 * vv + cmp] = g;
+          else reinterpret_cast<T*>(Gg_new)[8 * vv + (cmp - 4)] = g;
+        }
+        bad = !isfinite(out);
+        if (cmp < 4) sres[vl2][cmp] = out;
+      }
     }
   }
-  if (bad && sub < 12 && flag) flag[0] = 1;
+  __syncthreads();
+  if (mode == 1 && t < VPB && v0 + t < nowned) {
+    // positivity of rho and p at the new state
+    const double rho = sres[t][0], m = sres[t][1], n = sres[t][2], E = sres[t][3];
+    const double p = (gp.gamma - 1.0) * (E - 0.5 * (m * m + n * n) / rho);
+    bad = bad || !(rho > 0.0) || !(p > 0.0);
+  }
+  if (bad && flag) flag[0] = 1;
+}
+
+// State in the float64 [12][nv] layout -> gather layout (values [nv] of V4,
+// gradients [2 nv] of V4), minus the reference state in the mixed form.
+template <class T>
+__global__ void k_to_gather(int64_t nv, const double* __restrict__ U, GasParams gp,
+                            V4<T>* __restrict__ Gv, V4<T>* __restrict__ Gg) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  T w[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) w[q] = T(U[q * nv + i] - (q < 4 ? gp.wref[q] : 0.0));
+  Gv[i] = V4<T>{w[0], w[1], w[2], w[3]};
+  Gg[2 * i] = V4<T>{w[4], w[5], w[6], w[7]};
+  Gg[2 * i + 1] = V4<T>{w[8], w[9], w[10], w[11]};
+}
+
+template <class T>
+__global__ void k_copy_gather_rows(int64_t nrows, const int32_t* __restrict__ rows,
+                                   const V4<T>* __restrict__ fv, const V4<T>* __restrict__ fg,
+                                   V4<T>* __restrict__ tv, V4<T>* __restrict__ tg) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nrows) return;
+  const int64_t r = rows[k];
+  tv[r] = fv[r];
+  tg[2 * r] = fg[2 * r];
+  tg[2 * r + 1] = fg[2 * r + 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -377,14 +469,6 @@ __global__ void k_copy_rows(int64_t nrows, const int32_t* __restrict__ rows,
   const int64_t k = i / 12, q = i % 12;
   const int32_t dst = rows[k], s = src ? src[k] : rows[k];
   to[q * nv + dst] = from[q * nv + s];
-}
-
-__global__ void k_to_shadow(int64_t nv, const double* __restrict__ U,
-                            GasParams gp, float* __restrict__ Us) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= 12 * nv) return;
-  const int64_t q = i / nv;
-  Us[i] = float(U[i] - (q < 4 ? gp.wref[q] : 0.0));
 }
 
 __global__ void k_zero_rows(int64_t nowned, int64_t nv, double* __restrict__ dU) {
@@ -450,55 +534,73 @@ inline unsigned nblocks(int64_t n, int bs) { return unsigned((n + bs - 1) / bs);
 
 }  // namespace
 
-hipError_t launch_edge64(int64_t ne, int64_t nv, const EdgeCoef<double>& c,
-                         const GasParams& gp, const double* U,
-                         const uint8_t* force, double* H, double* wlr,
-                         uint8_t* mask, hipStream_t st) {
+template <class T>
+hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
+                       const V4<T>* Gv, const V4<T>* Gg, const uint8_t* force, V4<T>* H,
+                       double* hsoa, double* wlr, uint8_t* mask, hipStream_t st) {
   if (ne == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_edge<double>, dim3(nblocks(ne, 256)), dim3(256), 0, st, ne,
-                     nv, c, gp, U, force, H, wlr, mask);
+  hipLaunchKernelGGL(k_edge<T>, dim3(nblocks(ne, 256)), dim3(256), 0, st, ne, c, gp, Gv, Gg,
+                     force, H, hsoa, wlr, mask);
   return hipGetLastError();
 }
-
-hipError_t launch_edge32(int64_t ne, int64_t nv, const EdgeCoef<float>& c,
-                         const GasParams& gp, const float* Us,
-                         const uint8_t* force, float* H, double* wlr,
-                         uint8_t* mask, hipStream_t st) {
-  if (ne == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_edge<float>, dim3(nblocks(ne, 256)), dim3(256), 0, st, ne,
-                     nv, c, gp, Us, force, H, wlr, mask);
-  return hipGetLastError();
-}
+template hipError_t launch_edge<double>(int64_t, const EdgeCoef<double>&, const GasParams&,
+                                        const V4<double>*, const V4<double>*, const uint8_t*,
+                                        V4<double>*, double*, double*, uint8_t*, hipStream_t);
+template hipError_t launch_edge<float>(int64_t, const EdgeCoef<float>&, const GasParams&,
+                                       const V4<float>*, const V4<float>*, const uint8_t*,
+                                       V4<float>*, double*, double*, uint8_t*, hipStream_t);
 
 template <class T>
-static hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
-                                const GasParams& gp, const T* U, const T* H,
-                                int64_t ne, int mode, double* dU, const RkArgs& rk,
-                                int32_t* flag, hipStream_t st) {
+hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
+                         const GasParams& gp, const V4<T>* Gv, const V4<T>* Gg,
+                         const V4<T>* H, int mode, double* dU, const RkArgs& rk,
+                         V4<T>* Gv_new, V4<T>* Gg_new, int32_t* flag, hipStream_t st) {
   if (nowned == 0) return hipSuccess;
-  const unsigned nb = nblocks(nowned * VL, 256);
+  const unsigned nb = nblocks(nowned, VPB);
   if (c.dvis)
-    hipLaunchKernelGGL((k_vertex<T, true>), dim3(nb), dim3(256), 0, st, nowned, nv,
-                       c, gp, U, H, ne, mode, dU, rk, flag);
+    hipLaunchKernelGGL((k_vertex<T, true>), dim3(nb), dim3(VL * VPB), 0, st, nowned, nv, c,
+                       gp, Gv, Gg, H, mode, dU, rk, Gv_new, Gg_new, flag);
   else
-    hipLaunchKernelGGL((k_vertex<T, false>), dim3(nb), dim3(256), 0, st, nowned,
-                       nv, c, gp, U, H, ne, mode, dU, rk, flag);
+    hipLaunchKernelGGL((k_vertex<T, false>), dim3(nb), dim3(VL * VPB), 0, st, nowned, nv, c,
+                       gp, Gv, Gg, H, mode, dU, rk, Gv_new, Gg_new, flag);
   return hipGetLastError();
 }
+template hipError_t launch_vertex<double>(int64_t, int64_t, const VertexCoef<double>&,
+                                          const GasParams&, const V4<double>*,
+                                          const V4<double>*, const V4<double>*, int, double*,
+                                          const RkArgs&, V4<double>*, V4<double>*, int32_t*,
+                                          hipStream_t);
+template hipError_t launch_vertex<float>(int64_t, int64_t, const VertexCoef<float>&,
+                                         const GasParams&, const V4<float>*, const V4<float>*,
+                                         const V4<float>*, int, double*, const RkArgs&,
+                                         V4<float>*, V4<float>*, int32_t*, hipStream_t);
 
-hipError_t launch_vertex64(int64_t nowned, int64_t nv, const VertexCoef<double>& c,
-                           const GasParams& gp, const double* U, const double* H,
-                           int64_t ne, int mode, double* dU, const RkArgs& rk,
-                           int32_t* flag, hipStream_t st) {
-  return launch_vertex<double>(nowned, nv, c, gp, U, H, ne, mode, dU, rk, flag, st);
+template <class T>
+hipError_t launch_to_gather(int64_t nv, const double* U, const GasParams& gp, V4<T>* Gv,
+                            V4<T>* Gg, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_gather<T>, dim3(nblocks(nv, 256)), dim3(256), 0, st, nv, U, gp,
+                     Gv, Gg);
+  return hipGetLastError();
 }
+template hipError_t launch_to_gather<double>(int64_t, const double*, const GasParams&,
+                                             V4<double>*, V4<double>*, hipStream_t);
+template hipError_t launch_to_gather<float>(int64_t, const double*, const GasParams&,
+                                            V4<float>*, V4<float>*, hipStream_t);
 
-hipError_t launch_vertex32(int64_t nowned, int64_t nv, const VertexCoef<float>& c,
-                           const GasParams& gp, const float* Us, const float* H,
-                           int64_t ne, int mode, double* dU, const RkArgs& rk,
-                           int32_t* flag, hipStream_t st) {
-  return launch_vertex<float>(nowned, nv, c, gp, Us, H, ne, mode, dU, rk, flag, st);
+template <class T>
+hipError_t launch_copy_gather_rows(int64_t nrows, const int32_t* rows, const V4<T>* fv,
+                                   const V4<T>* fg, V4<T>* tv, V4<T>* tg, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_gather_rows<T>, dim3(nblocks(nrows, 256)), dim3(256), 0, st,
+                     nrows, rows, fv, fg, tv, tg);
+  return hipGetLastError();
 }
+template hipError_t launch_copy_gather_rows<double>(int64_t, const int32_t*,
+                                                    const V4<double>*, const V4<double>*,
+                                                    V4<double>*, V4<double>*, hipStream_t);
+template hipError_t launch_copy_gather_rows<float>(int64_t, const int32_t*, const V4<float>*,
+                                                   const V4<float>*, V4<float>*, V4<float>*,
+                                                   hipStream_t);
 
 template <class T>
 hipError_t launch_copy_rows(int64_t nrows, const int32_t* rows, const int32_t* src,
@@ -512,13 +614,6 @@ template hipError_t launch_copy_rows<double>(int64_t, const int32_t*, const int3
                                              int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_copy_rows<float>(int64_t, const int32_t*, const int32_t*,
                                             int64_t, const float*, float*, hipStream_t);
-
-hipError_t launch_to_shadow(int64_t nv, const double* U, const GasParams& gp,
-                            float* Us, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_shadow, dim3(nblocks(12 * nv, 256)), dim3(256), 0, st, nv,
-                     U, gp, Us);
-  return hipGetLastError();
-}
 
 hipError_t launch_zero_ghost_rows(int64_t nowned, int64_t nv, double* dU,
                                   hipStream_t st) {
