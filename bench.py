@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this size first (a "
+                         "known-size kernel for calibrating HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -162,6 +165,15 @@ def main():
         f"upload {info['setup_ms'][1]:.0f} ms, GPU precompute {info['setup_ms'][2]:.0f} ms); "
         f"{info['n_edges']} active edges, ranks {info['rank_hist'][10:15]}")
     U0d = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+    if a.copy_probe_mb:
+        n = a.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {a.copy_probe_mb} MiB device-to-device")
+        del src, dst
     wref = U0[0:4, m.ghost_src == -1].mean(axis=1)
 
     res = {}

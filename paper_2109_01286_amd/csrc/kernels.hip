@@ -81,28 +81,47 @@ __device__ inline Ref<T> make_ref(const GasParams& gp) {
   return r;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumber them so that XCD x runs one contiguous range of logical
+// blocks: neighbouring vertices / edges then share an L2 for their gathers.
+constexpr int kXcd = 8;
+__device__ inline int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t x = b % kXcd, k = b / kXcd;
+  const int64_t q = nb / kXcd, r = nb % kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Edge pass
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256)
+// LPE lanes per edge.  LPE = 2: lane side s = 0 interpolates the left state
+// from nodes (i-2 .. i+2), s = 1 the right state from (i+3 .. i-1); the pair
+// swaps states and both evaluate the flux (lane 0 stores it).  LPE = 1: one
+// lane does both sides in turn.
+// Waves per SIMD the edge pass is compiled for (register budget 512/waves).
+template <class T> struct EdgeWaves { static constexpr int value = 3; };
+template <> struct EdgeWaves<double> { static constexpr int value = 2; };
+
+template <class T, int LPE>
+__global__ void __launch_bounds__(256, EdgeWaves<T>::value)
 k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
        const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
        V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
        uint8_t* __restrict__ mask) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
+  const int s0 = LPE == 2 ? int(tid & 1) : 0;
+  const int64_t e = tid / LPE;
   if (e >= ne) return;
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
-  int id[6];
-#pragma unroll
-  for (int t = 0; t < 6; ++t) id[t] = c.stg[t * ne + e];
+  const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
   const T nx = c.n[e], ny = c.n[ne + e];
 
   // Roe average of the two end states (nodes i, i+1)
   T u, v, hh, cc;
   {
-    const V4<T> A = Gv[id[2]], B = Gv[id[3]];
+    const V4<T> A = Gv[ia], B = Gv[ib];
     T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
     T ua = (ref.w[1] + A.y) / ra, ub = (ref.w[1] + B.y) / rb;
     T va = (ref.w[2] + A.z) / ra, vb = (ref.w[2] + B.z) / rb;
@@ -125,43 +144,49 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
       {T(1) - b2, b1 * u, b1 * v, -b1},
       {T(0.5) * (b2 - un * ic), T(-0.5) * (b1 * u - nx * ic), T(-0.5) * (b1 * v - ny * ic), T(0.5) * b1},
       {-ut, -ny, nx, T(0)}};
-
-  // characteristic values / gradients at the six nodes
-  T cv[4][6], cx[4][6], cy[4][6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
-    const T w[4] = {a.x, a.y, a.z, a.w};
-    const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
-    const T wy[4] = {by.x, by.y, by.z, by.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cv[q][j] = L[q][0] * w[0] + L[q][1] * w[1] + L[q][2] * w[2] + L[q][3] * w[3];
-      cx[q][j] = L[q][0] * wx[0] + L[q][1] * wx[1] + L[q][2] * wx[2] + L[q][3] * wx[3];
-      cy[q][j] = L[q][0] * wy[0] + L[q][1] * wy[1] + L[q][2] * wy[2] + L[q][3] * wy[3];
-    }
-  }
-
+  const T Rm[4][4] = {{T(1), T(1), T(1), T(0)},
+                      {u - cc * nx, u, u + cc * nx, -ny},
+                      {v - cc * ny, v, v + cc * ny, nx},
+                      {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}};
   const uint8_t fm = force ? force[e] : uint8_t(0);
   uint8_t bits = 0;
-  T C[2][4];
   const T eps = T(gp.eps), lo = T(gp.sw_lo), hi = T(gp.sw_hi);
   const T d1 = T(1.0 / 16.0), d2 = T(10.0 / 16.0), d3 = T(5.0 / 16.0);
+
+  T wm0[4], wm1[4];
+#pragma unroll 1
+  for (int k = 0; k < 3 - LPE; ++k) {
+    const int s = s0 + k;
+    int id[5];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    // side nodes: left (0,1,2,3,4), right (5,4,3,2,1)
-    int ix[5];
+    for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
+    // The 5-node Hermite row is the same for the four characteristic
+    // components, so L (sum_t w5_t . data_t) is the projected Hermite value:
+    // only the node values need projecting (for the smoothness indicators
+    // and the 3-node values); the gradients enter through the physical sum.
+    T w5[15];
 #pragma unroll
-    for (int t = 0; t < 5; ++t) ix[t] = s == 0 ? t : 5 - t;
-    T w5[15], w3[9];
+    for (int j = 0; j < 15; ++j) w5[j] = c.w5[int64_t(s * 15 + j) * ne + e];
+    T cv[4][5], hs[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int k = 0; k < 15; ++k) w5[k] = c.w5[int64_t(s * 15 + k) * ne + e];
+    for (int j = 0; j < 5; ++j) {
+      const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
+      const T w[4] = {a.x, a.y, a.z, a.w};
+      const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
+      const T wy[4] = {by.x, by.y, by.z, by.w};
 #pragma unroll
-    for (int k = 0; k < 9; ++k) w3[k] = c.w3[int64_t(s * 9 + k) * ne + e];
+      for (int q = 0; q < 4; ++q) {
+        cv[q][j] = L[q][0] * w[0] + L[q][1] * w[1] + L[q][2] * w[2] + L[q][3] * w[3];
+        hs[q] += w5[3 * j] * w[q] + w5[3 * j + 1] * wx[q] + w5[3 * j + 2] * wy[q];
+      }
+    }
+    T w3[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) w3[j] = c.w3[int64_t(s * 9 + j) * ne + e];
+    T C[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const T c0 = cv[q][ix[0]], c1 = cv[q][ix[1]], c2 = cv[q][ix[2]],
-              c3 = cv[q][ix[3]], c4 = cv[q][ix[4]];
+      const T c0 = cv[q][0], c1 = cv[q][1], c2 = cv[q][2], c3 = cv[q][3], c4 = cv[q][4];
       const T t1 = c0 - T(2) * c1 + c2, t2 = c0 - T(4) * c1 + T(3) * c2;
       const T t3 = c1 - T(2) * c2 + c3, t4 = c1 - c3;
       const T t5 = c2 - T(2) * c3 + c4, t6 = T(3) * c2 - T(4) * c3 + c4;
@@ -183,28 +208,34 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
               o2 * (w3[3] * c1 + w3[4] * c2 + w3[5] * c3) +
               o3 * (w3[6] * c2 + w3[7] * c3 + w3[8] * c4);
       } else {
-        val = T(0);
-#pragma unroll
-        for (int t = 0; t < 5; ++t)
-          val += w5[3 * t] * cv[q][ix[t]] + w5[3 * t + 1] * cx[q][ix[t]] +
-                 w5[3 * t + 2] * cy[q][ix[t]];
+        val = L[q][0] * hs[0] + L[q][1] * hs[1] + L[q][2] * hs[2] + L[q][3] * hs[3];
       }
-      C[s][q] = val;
+      C[q] = val;
       bits |= uint8_t(weno ? 1 : 0) << (4 * s + q);
     }
-  }
-  // back-projection w' = R C
-  T wl[4], wr[4];
-  {
-    const T Rm[4][4] = {{T(1), T(1), T(1), T(0)},
-                        {u - cc * nx, u, u + cc * nx, -ny},
-                        {v - cc * ny, v, v + cc * ny, nx},
-                        {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}};
+    // back-projection w' = R C of this side
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      wl[r] = Rm[r][0] * C[0][0] + Rm[r][1] * C[0][1] + Rm[r][2] * C[0][2] + Rm[r][3] * C[0][3];
-      wr[r] = Rm[r][0] * C[1][0] + Rm[r][1] * C[1][1] + Rm[r][2] * C[1][2] + Rm[r][3] * C[1][3];
+      const T x = Rm[r][0] * C[0] + Rm[r][1] * C[1] + Rm[r][2] * C[2] + Rm[r][3] * C[3];
+      if (k == 0) wm0[r] = x;
+      else wm1[r] = x;
     }
+  }
+  T wl[4], wr[4];
+  if (LPE == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wl[q] = wm0[q];
+      wr[q] = wm1[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T o = __shfl_xor(wm0[q], 1);
+      wl[q] = s0 == 0 ? wm0[q] : o;
+      wr[q] = s0 == 0 ? o : wm0[q];
+    }
+    bits |= uint8_t(__shfl_xor(int(bits), 1));
   }
   // Rusanov flux along n (perturbation form)
   T fl[4], gl[4], fr[4], gr[4], pl, rl, ul, vl, pr, rr, ur, vr;
@@ -219,19 +250,21 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   for (int q = 0; q < 4; ++q)
     h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
            T(0.5) * lam * (wr[q] - wl[q]);
-  H[e] = V4<T>{h[0], h[1], h[2], h[3]};
-  if (hsoa) {
+  if (s0 == 0) {
+    H[e] = V4<T>{h[0], h[1], h[2], h[3]};
+    if (mask) mask[e] = bits;
+    if (hsoa) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) hsoa[q * ne + e] = double(h[q]);
+      for (int q = 0; q < 4; ++q) hsoa[q * ne + e] = double(h[q]);
+    }
   }
   if (wlr) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      wlr[q * ne + e] = double(wl[q]) + gp.wref[q];
-      wlr[(4 + q) * ne + e] = double(wr[q]) + gp.wref[q];
+      if (LPE == 1 || s0 == 0) wlr[q * ne + e] = double(wl[q]) + gp.wref[q];
+      if (LPE == 1 || s0 == 1) wlr[(4 + q) * ne + e] = double(wr[q]) + gp.wref[q];
     }
   }
-  if (mask) mask[e] = bits;
 }
 
 // ---------------------------------------------------------------------------
@@ -309,7 +342,7 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
          int32_t* __restrict__ flag) {
   __shared__ double sres[VPB][13];
   const int vl = threadIdx.x / VL, sub = threadIdx.x & (VL - 1);
-  const int64_t v0 = int64_t(blockIdx.x) * VPB;
+  const int64_t v0 = xcd_block() * VPB;
   const int64_t v = v0 + vl;
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = T(gp.gamma - 1.0);
@@ -539,8 +572,10 @@ hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
                        const V4<T>* Gv, const V4<T>* Gg, const uint8_t* force, V4<T>* H,
                        double* hsoa, double* wlr, uint8_t* mask, hipStream_t st) {
   if (ne == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_edge<T>, dim3(nblocks(ne, 256)), dim3(256), 0, st, ne, c, gp, Gv, Gg,
-                     force, H, hsoa, wlr, mask);
+  // float: one lane per edge; double: two (one per side), register budget
+  constexpr int lpe = sizeof(T) == 8 ? 2 : 1;
+  hipLaunchKernelGGL((k_edge<T, lpe>), dim3(nblocks(lpe * ne, 256)), dim3(256), 0, st, ne, c,
+                     gp, Gv, Gg, force, H, hsoa, wlr, mask);
   return hipGetLastError();
 }
 template hipError_t launch_edge<double>(int64_t, const EdgeCoef<double>&, const GasParams&,
