@@ -83,6 +83,23 @@ def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
                 bytes_vertex=info["bytes_vertex_launch"])
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken for this workload and the current kernel source."""
+    from paper_2109_01286_amd import profile_summary
+    path = os.path.join(ROOT, "profiles", f"{workload}_kernel_stats_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("workload") != workload or d.get("kernels_hip_sha256") != profile_summary.source_digest():
+        return None
+    for name, v in d["per_launch"].items():
+        if name.startswith(kernel):
+            return v["bytes"]
+    return None
+
+
 def roofline(r):
     kern = {}
     for k in ("edge", "vertex"):
@@ -126,6 +143,53 @@ def cpu_baseline(m, U0, prm, kw, budget_s):
                        f"evaluations in {el:.1f} s; oracle setup {setup:.1f} s not timed")
 
 
+def adjoint_ratio(steps=200, ckpt=20):
+    """Adjoint/forward time of the isentropic vortex on the 257 x 257 periodic
+    jittered lattice: gradient of J = sum A_v [|x - (7,7)| < 1] p^2 after
+    `steps` RK3 steps of fixed size (from the initial state, CFL 0.3) with
+    respect to the initial state, checkpoints every `ckpt` steps.  WENO-only
+    switch with the 3-node cap: the paper's switch does not stay finite for
+    200 steps at this resolution."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+    from paper_2109_01286_amd.adjoint import pressure_disk_objective, rk_steps
+    m, U, prm = inputs.workload("vortex257")
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, switch="weno", w3_cap=2.0)
+    Ud = torch.as_tensor(S.to_internal(U), device="cuda:0")
+    dt = S.stable_dt(Ud, 0.3).item()
+    xy = torch.as_tensor(m.xy[S.old_of_new], device="cuda:0")
+    area = torch.as_tensor(inputs.vertex_areas(m)[S.old_of_new], device="cuda:0")
+    # forward alone (warm once)
+    X = Ud.clone()
+    S.rk_step(X, dt)
+    torch.cuda.synchronize()
+    X = Ud.clone()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.rk_step(X, dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # forward with checkpoints + objective, then the backward pass
+    U0 = Ud.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    Uf = rk_steps(U0, S, steps, dt, ckpt)
+    J = pressure_disk_objective(Uf, xy, (7.0, 7.0), 1.0, area)
+    torch.cuda.synchronize()
+    t_fwd_ck = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    (g,) = torch.autograd.grad(J, U0)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    S.check()
+    return {"workload": "vortex257", "steps": steps, "ckpt_every": ckpt, "dtype": "f64",
+            "switch": "weno", "forward_ms": t_fwd * 1e3,
+            "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
+            "adjoint_over_forward": t_bwd / t_fwd, "J": J.item(),
+            "grad_finite": bool(torch.isfinite(g).all().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +202,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (a "
                          "known-size kernel for calibrating HBM byte counters)")
@@ -216,7 +281,10 @@ def main():
                    "steps_per_restart": a.chunk},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": kern[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": kern[dom]["frac"], "traffic": None},
+                     "unit": "GB/s", "frac": kern[dom]["frac"],
+                     "traffic": (measured_traffic(a.workload, "k_vertex<float" if dom == "vertex"
+                                                  else "k_edge<float")
+                                 if main_prec == "fp32" else None)},
         "kernels": kern,
     }
     if "fp64" in res and main_prec == "fp32":
@@ -224,6 +292,12 @@ def main():
                        "ms_per_step": res["fp64"]["wall"] / a.steps * 1e3,
                        "kernels": res["fp64"]["kern"]}
         out["fp32_vs_fp64_rho_rel_l2"] = diff
+    if not a.no_adjoint:
+        del S
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_ratio()
+        log(f"[bench] adjoint/forward (vortex257, 200 steps, f64): "
+            f"{out['adjoint']['adjoint_over_forward']:.2f}")
     if not a.no_cpu:
         log("[bench] timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(m, U0, prm, kw, a.cpu_budget)

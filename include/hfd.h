@@ -222,6 +222,24 @@ hfd_status hfd_fill_ghosts(hfd_ctx* ctx, double* U, void* stream);
  * vertex (the flag is then cleared). */
 hfd_status hfd_check(hfd_ctx* ctx, void* stream);
 
+/* Adjoint of the residual (float64, Euler fluxes only; mu > 0 gives
+ * HFD_E_STATE): out = (dR/dU)^T lam, all device [12][nv] float64.  The
+ * branch of eq. 2d_hweno_intp and the WENO weights are differentiated
+ * through the branch the forward pass takes, the Rusanov maximum through its
+ * larger argument.  Rows of ghost vertices of out are zero (derivatives with
+ * respect to copying ghosts land on their sources; Dirichlet data are
+ * constants).  Allocates transposed maps and work buffers on first use. */
+hfd_status hfd_adjoint_residual(hfd_ctx* ctx, const double* U, const double* lam,
+                                double* out, void* stream);
+
+/* Adjoint of one hfd_rk_step with step size dt (float64): given the step's
+ * input state U_n and lam_np1 = dJ/dU_{n+1}, lam_n = (dU_{n+1}/dU_n)^T
+ * lam_np1 (device, [12][nv]).  The two intermediate stages are recomputed.
+ * Dirichlet rows of lam_n carry lam_np1 through; rows of copying ghosts are
+ * zero.  lam_n may not alias lam_np1. */
+hfd_status hfd_rk_step_adjoint(hfd_ctx* ctx, const double* U_n, double dt,
+                               const double* lam_np1, double* lam_n, void* stream);
+
 /* Per-kernel timing, for measurement.  With timing on, every edge pass and
  * every vertex pass launched by hfd_residual / hfd_rk_step* is bracketed by
  * two HIP events recorded on the call's stream.  hfd_kernel_times

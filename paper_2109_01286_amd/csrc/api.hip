@@ -50,6 +50,18 @@ struct hfd_ctx {
   int64_t ndtpart = 0;
   int32_t* flag = nullptr;
   const uint8_t* force = nullptr;
+  // adjoint: transposed maps and work buffers (built at first use)
+  bool adj_ready = false;
+  int32_t *etp = nullptr, *etv = nullptr, *ets = nullptr;
+  int32_t *vtp = nullptr, *vtv = nullptr, *vts = nullptr;
+  int32_t *ntp = nullptr, *nte = nullptr;
+  int8_t* ntj = nullptr;
+  int32_t *gsp = nullptr, *gsr = nullptr, *gsg = nullptr;  // copy source -> ghosts
+  int64_t n_gsrc = 0;
+  double *bnode = nullptr, *AL1 = nullptr, *AL2 = nullptr, *AL3 = nullptr, *AB = nullptr;
+  hfd::V4<double>* lh = nullptr;
+  hfd::V4<double>* LGv = nullptr;
+  hfd::V4<double>* LGg = nullptr;
   // measurement: event pairs around the edge (0) and vertex (1) passes
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -281,6 +293,127 @@ hfd_status edge_states_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>
   HIPCHK(c, hfd::launch_to_gather<T>(h.nv, U, gp, B.Gv[0], B.Gg[0], st));
   HIPCHK(c, hfd::launch_edge<T>(h.ne, ec, gp, B.Gv[0], B.Gg[0], c->force, B.H, hout, wlr,
                                 mask, st));
+  return HFD_OK;
+}
+
+
+// Transposed maps of the adjoint, by counting sort (deterministic order:
+// owner vertex, then slot).
+void transpose(int64_t nrows, const std::vector<int32_t>& key, std::vector<int32_t>& ptr,
+               std::vector<int32_t>& pos) {
+  ptr.assign(nrows + 1, 0);
+  for (int32_t k : key) ptr[k + 1]++;
+  for (int64_t r = 0; r < nrows; ++r) ptr[r + 1] += ptr[r];
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  pos.resize(key.size());
+  for (size_t i = 0; i < key.size(); ++i) pos[fill[key[i]]++] = int32_t(i);
+}
+
+hfd_status ensure_adjoint(hfd_ctx* c) {
+  if (c->adj_ready) return HFD_OK;
+  const hfd::HostSetup& h = c->hs;
+  const int64_t ne = h.ne, nv = h.nv, no = h.n_owned;
+  hfd_status s;
+  std::vector<int32_t> ptr, pos;
+  // edge <- (owner, edge slot)
+  {
+    std::vector<int32_t> owner(h.v_edges.size());
+    for (int64_t v = 0; v < no; ++v)
+      for (int64_t k = h.eptr[v]; k < h.eptr[v + 1]; ++k) owner[k] = int32_t(v);
+    transpose(ne, h.v_edges, ptr, pos);
+    std::vector<int32_t> tv(pos.size()), ts(pos.size());
+    for (size_t i = 0; i < pos.size(); ++i) {
+      ts[i] = pos[i];
+      tv[i] = owner[pos[i]];
+    }
+    if ((s = upload(c, &c->etp, ptr)) || (s = upload(c, &c->etv, tv)) || (s = upload(c, &c->ets, ts)))
+      return s;
+  }
+  // gather row <- (owner, vertex slot)
+  {
+    std::vector<int32_t> owner(h.v_gather.size());
+    for (int64_t v = 0; v < no; ++v)
+      for (int64_t k = h.vptr[v]; k < h.vptr[v + 1]; ++k) owner[k] = int32_t(v);
+    transpose(nv, h.v_gather, ptr, pos);
+    std::vector<int32_t> tv(pos.size()), ts(pos.size());
+    for (size_t i = 0; i < pos.size(); ++i) {
+      ts[i] = pos[i];
+      tv[i] = owner[pos[i]];
+    }
+    if ((s = upload(c, &c->vtp, ptr)) || (s = upload(c, &c->vtv, tv)) || (s = upload(c, &c->vts, ts)))
+      return s;
+  }
+  // gather row <- (edge, stencil position); keys in edge-major order
+  {
+    std::vector<int32_t> key(6 * ne);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int j = 0; j < 6; ++j) key[6 * e + j] = h.e_stg[j * ne + e];
+    transpose(nv, key, ptr, pos);
+    std::vector<int32_t> te(pos.size());
+    std::vector<int8_t> tj(pos.size());
+    for (size_t i = 0; i < pos.size(); ++i) {
+      te[i] = pos[i] / 6;
+      tj[i] = int8_t(pos[i] % 6);
+    }
+    if ((s = upload(c, &c->ntp, ptr)) || (s = upload(c, &c->nte, te)) || (s = upload(c, &c->ntj, tj)))
+      return s;
+  }
+  // copy source -> its ghosts
+  {
+    std::vector<int32_t> srcs(h.copy_src), order(h.copy_src.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int32_t(i);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return srcs[a] < srcs[b]; });
+    std::vector<int32_t> sp{0}, sr, sg;
+    for (size_t i = 0; i < order.size(); ++i) {
+      const int32_t src = srcs[order[i]];
+      if (sr.empty() || sr.back() != src) {
+        if (!sr.empty()) sp.push_back(int32_t(i));
+        sr.push_back(src);
+      }
+      sg.push_back(h.copy_rows[order[i]]);
+    }
+    sp.push_back(int32_t(order.size()));
+    if (sr.empty()) sp.assign(1, 0);
+    c->n_gsrc = int64_t(sr.size());
+    if ((s = upload(c, &c->gsp, sp)) || (s = upload(c, &c->gsr, sr)) || (s = upload(c, &c->gsg, sg)))
+      return s;
+  }
+  if ((s = dalloc(c, &c->bnode, 72 * ne)) || (s = dalloc(c, &c->AL1, 12 * nv)) ||
+      (s = dalloc(c, &c->AL2, 12 * nv)) || (s = dalloc(c, &c->AL3, 12 * nv)) ||
+      (s = dalloc(c, &c->AB, 12 * nv)) || (s = dalloc(c, &c->lh, ne)) ||
+      (s = dalloc(c, &c->LGv, nv)) || (s = dalloc(c, &c->LGg, 2 * nv)))
+    return s;
+  c->adj_ready = true;
+  return HFD_OK;
+}
+
+// out = J(U)^T lam, U given in both layouts (SoA U, gather Gv/Gg)
+hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<double>* Gv,
+                         const hfd::V4<double>* Gg, const double* lam, double* out,
+                         hipStream_t st) {
+  const hfd::HostSetup& h = c->hs;
+  GasParams zero = gas_params(c, false);
+  HIPCHK(c, hfd::launch_to_gather<double>(h.nv, lam, zero, c->LGv, c->LGg, st));
+  hfd::AdjointArgs a{};
+  a.ne = h.ne;
+  a.nowned = h.n_owned;
+  a.nv = h.nv;
+  a.etp = c->etp; a.etv = c->etv; a.ets = c->ets;
+  a.de = c->de;
+  a.Lv = c->LGv; a.Lg = c->LGg;
+  a.lh = c->lh;
+  a.ec = ecoef64(c);
+  a.gp = zero;
+  a.Gv = Gv; a.Gg = Gg;
+  a.force = c->force;
+  a.bnode = c->bnode;
+  a.U = U;
+  a.vtp = c->vtp; a.vtv = c->vtv; a.vts = c->vts;
+  a.dv = c->dv;
+  a.ntp = c->ntp; a.nte = c->nte; a.ntj = c->ntj;
+  a.out = out;
+  HIPCHK(c, hfd::launch_adjoint_residual(a, st));
+  HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, out, st));
   return HFD_OK;
 }
 
@@ -661,6 +794,71 @@ hfd_status hfd_check(hfd_ctx* c, void* stream) {
     HIPCHK(c, hipMemset(c->flag, 0, sizeof(int32_t)));
     return fail(c, HFD_E_NUMERIC, "non-finite value or rho <= 0 or p <= 0 at an owned vertex");
   }
+  return HFD_OK;
+}
+
+
+hfd_status hfd_adjoint_residual(hfd_ctx* c, const double* U, const double* lam, double* out,
+                                void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !lam || !out) return fail(c, HFD_E_INVAL, "null pointer");
+  if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
+  if ((s = ensure_adjoint(c))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto& B = c->b64;
+  HIPCHK(c, hfd::launch_to_gather<double>(c->hs.nv, U, gas_params(c, false), B.Gv[0], B.Gg[0], st));
+  return adjoint_apply(c, U, B.Gv[0], B.Gg[0], lam, out, st);
+}
+
+hfd_status hfd_rk_step_adjoint(hfd_ctx* c, const double* U, double dt, const double* lam_np1,
+                               double* lam_n, void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !lam_np1 || !lam_n) return fail(c, HFD_E_INVAL, "null pointer");
+  if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
+  if ((s = ensure_adjoint(c))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hfd::HostSetup& h = c->hs;
+  const int64_t nv = h.nv, ne = h.ne, no = h.n_owned, n12 = 12 * nv;
+  const int64_t nd = int64_t(h.dir_rows.size());
+  auto& B = c->b64;
+  const GasParams gp = gas_params(c, false);
+  // forward stages 1 and 2 (float64): U1, U2 and their gather copies
+  HIPCHK(c, hfd::launch_to_gather<double>(nv, U, gp, B.Gv[0], B.Gg[0], st));
+  for (int k = 1; k < 3; ++k)
+    HIPCHK(c, hfd::launch_copy_gather_rows<double>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
+                                                   B.Gg[k], st));
+  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
+  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
+  const double a[2] = {0.0, 0.75}, b[2] = {1.0, 0.25};
+  const double* in[2] = {U, c->U1};
+  double* outp[2] = {c->U1, c->U2};
+  for (int k = 0; k < 2; ++k) {
+    HIPCHK(c, hfd::launch_edge<double>(ne, ecoef64(c), gp, B.Gv[k], B.Gg[k], c->force, B.H,
+                                       nullptr, nullptr, nullptr, st));
+    hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, nullptr};
+    HIPCHK(c, hfd::launch_vertex<double>(no, nv, vcoef64(c), gp, B.Gv[k], B.Gg[k], B.H, 1,
+                                         nullptr, rk, B.Gv[k + 1], B.Gg[k + 1], c->flag, st));
+  }
+  // reverse.  A3 = lam_{n+1} with the final ghost fill transposed
+  double *A3 = c->AL3, *L2 = c->AL2, *L1 = c->AL1, *Bt = c->AB;
+  HIPCHK(c, hipMemcpyAsync(A3, lam_np1, n12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hfd::launch_adj_copy_ghosts(c->n_gsrc, c->gsp, c->gsr, c->gsg, nv, A3, st));
+  // stage 3: U3 = U/3 + 2/3 (U2 + dt R(U2))
+  if ((s = adjoint_apply(c, c->U2, B.Gv[2], B.Gg[2], A3, Bt, st))) return s;
+  HIPCHK(c, hfd::launch_axpbypcz(n12, 2.0 / 3.0, A3, 2.0 / 3.0 * dt, Bt, 0.0, nullptr, L2, st));
+  HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0 / 3.0, A3, 0.0, A3, 0.0, nullptr, lam_n, st));
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
+  if ((s = adjoint_apply(c, c->U1, B.Gv[1], B.Gg[1], L2, Bt, st))) return s;
+  HIPCHK(c, hfd::launch_axpbypcz(n12, 0.25, L2, 0.25 * dt, Bt, 0.0, nullptr, L1, st));
+  HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0, lam_n, 0.75, L2, 0.0, nullptr, lam_n, st));
+  // stage 1: U1 = U + dt R(U)
+  if ((s = adjoint_apply(c, U, B.Gv[0], B.Gg[0], L1, Bt, st))) return s;
+  HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0, lam_n, 1.0, L1, dt, Bt, lam_n, st));
+  // ghost rows: Dirichlet rows pass lam_{n+1} through, copies carry nothing
+  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, A3, lam_n, st));
+  HIPCHK(c, hfd::launch_zero_ghost_rows(no + nd, nv, lam_n, st));
   return HFD_OK;
 }
 

@@ -101,4 +101,36 @@ hipError_t launch_stable_dt(int64_t nowned, int64_t nv, const double* U,
 hipError_t launch_cast(int64_t n, const double* a, float* b, hipStream_t st);
 hipError_t launch_widen(int64_t n, const float* a, double* b, hipStream_t st);
 
+// ---- adjoint (float64, Euler) ---------------------------------------------------
+struct AdjointArgs {
+  int64_t ne, nowned, nv;
+  const int32_t *etp, *etv, *ets;   // edge m <- (owner vertex, edge slot)
+  const double* de;
+  const V4<double>* Lv;             // lambda in gather layout
+  const V4<double>* Lg;
+  V4<double>* lh;                   // [ne] flux adjoint
+  EdgeCoef<double> ec;
+  GasParams gp;
+  const V4<double>* Gv;             // state in gather layout
+  const V4<double>* Gg;
+  const uint8_t* force;
+  double* bnode;                    // [ne][6][12] edge-pass contributions
+  const double* U;                  // state [12][nv]
+  const int32_t *vtp, *vtv, *vts;   // gather row <- (owner vertex, vertex slot)
+  const double* dv;
+  const int32_t *ntp, *nte;         // gather row <- (edge, stencil position)
+  const int8_t* ntj;
+  double* out;                      // [12][nv], owned rows written
+};
+hipError_t launch_adjoint_residual(const AdjointArgs& a, hipStream_t st);
+
+// out[i] = a x[i] + b y[i] (+ c z[i] if z), i < n
+hipError_t launch_axpbypcz(int64_t n, double a, const double* x, double b, const double* y,
+                           double c, const double* z, double* out, hipStream_t st);
+// lambda of a step's final ghost fill: src rows gather their copies, the
+// copies' rows are cleared
+hipError_t launch_adj_copy_ghosts(int64_t nsrc, const int32_t* sptr, const int32_t* srows,
+                                  const int32_t* gsts, int64_t nv, double* lam,
+                                  hipStream_t st);
+
 }  // namespace hfd

@@ -553,6 +553,33 @@ k_dt_final(int64_t np, const double* __restrict__ partial, double cfl,
   }
 }
 
+__global__ void k_axpbypcz(int64_t n, double a, const double* __restrict__ x, double b,
+                           const double* __restrict__ y, double c, const double* __restrict__ z,
+                           double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double r = a * x[i] + b * y[i];
+  if (z) r += c * z[i];
+  out[i] = r;
+}
+
+// one thread per (source row, component)
+__global__ void k_adj_copy_ghosts(int64_t nsrc, const int32_t* __restrict__ sptr,
+                                  const int32_t* __restrict__ srows,
+                                  const int32_t* __restrict__ gsts, int64_t nv,
+                                  double* __restrict__ lam) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nsrc * 12) return;
+  const int64_t k = i / 12, q = i % 12;
+  const int64_t src = srows[k];
+  double acc = lam[q * nv + src];
+  for (int j = sptr[k]; j < sptr[k + 1]; ++j) {
+    acc += lam[q * nv + gsts[j]];
+    lam[q * nv + gsts[j]] = 0.0;
+  }
+  lam[q * nv + src] = acc;
+}
+
 __global__ void k_cast(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = float(a[i]);
@@ -666,6 +693,23 @@ hipError_t launch_stable_dt(int64_t nowned, int64_t nv, const double* U,
                      nowned, nv, U, hmin, gamma, partial);
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(DT_BLOCK), 0, st, npartial, partial,
                      cfl, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpbypcz(int64_t n, double a, const double* x, double b, const double* y,
+                           double c, const double* z, double* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpbypcz, dim3(nblocks(n, 256)), dim3(256), 0, st, n, a, x, b, y, c, z,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_copy_ghosts(int64_t nsrc, const int32_t* sptr, const int32_t* srows,
+                                  const int32_t* gsts, int64_t nv, double* lam,
+                                  hipStream_t st) {
+  if (nsrc == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_copy_ghosts, dim3(nblocks(nsrc * 12, 256)), dim3(256), 0, st, nsrc,
+                     sptr, srows, gsts, nv, lam);
   return hipGetLastError();
 }
 

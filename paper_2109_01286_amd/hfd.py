@@ -85,6 +85,8 @@ SIGNATURES = {
     "hfd_force_switch_mask": (ctypes.c_int, [_P, _P]),
     "hfd_fill_ghosts": (ctypes.c_int, [_P, _P, _P]),
     "hfd_check": (ctypes.c_int, [_P, _P]),
+    "hfd_adjoint_residual": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "hfd_rk_step_adjoint": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
     "hfd_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "hfd_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, _P]),
 }
@@ -307,6 +309,24 @@ class Solver:
         return to the configured switch (None)."""
         self._force = mask
         self._chk(lib().hfd_force_switch_mask(self._h, _dptr(mask)))
+
+    def adjoint_residual(self, U, lam, out=None):
+        """(dR/dU)^T lam (float64 device tensors [12, V], internal order)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(U)
+        self._chk(lib().hfd_adjoint_residual(self._h, _dptr(U), _dptr(lam), _dptr(out),
+                                             _stream()))
+        return out
+
+    def rk_step_adjoint(self, U_n, dt, lam_np1, out=None):
+        """(dU_{n+1}/dU_n)^T lam_np1 for one RK3 step of size dt from U_n."""
+        import torch
+        if out is None:
+            out = torch.empty_like(U_n)
+        self._chk(lib().hfd_rk_step_adjoint(self._h, _dptr(U_n), float(dt), _dptr(lam_np1),
+                                            _dptr(out), _stream()))
+        return out
 
     def fill_ghosts(self, U):
         self._chk(lib().hfd_fill_ghosts(self._h, _dptr(U), _stream()))

@@ -310,6 +310,25 @@ def shock_vortex(mesh: Mesh, gamma=1.4, mach=1.1, x_shock=0.5,
     return prim_to_state(gamma, rho, u, v, p, drho, du, dv, dp)
 
 
+def vertex_areas(mesh: Mesh):
+    """One third of the areas of the triangles around each vertex (periodic
+    displacements by the minimum image)."""
+    t = mesh.tri.astype(np.int64)
+    a = mesh.xy[t[:, 0]]
+    d1 = mesh.xy[t[:, 1]] - a
+    d2 = mesh.xy[t[:, 2]] - a
+    for d in (d1, d2):
+        for k in (0, 1):
+            P = mesh.period[k]
+            if P:
+                d[:, k] -= P * np.round(d[:, k] / P)
+    area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    out = np.zeros(mesh.nv)
+    for k in range(3):
+        np.add.at(out, t[:, k], area / 3.0)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Named workloads (mesh recipe + initial state), sizes as stated per case
 # ----------------------------------------------------------------------------

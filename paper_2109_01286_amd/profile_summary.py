@@ -1,0 +1,69 @@
+"""Summarise rocprofv3 CSV output of a bench.py run into a short markdown
+table (kernel statistics, and HBM traffic from FETCH_SIZE / WRITE_SIZE runs
+calibrated on k_cast, a streaming kernel of known size: it reads 8 bytes and
+writes 4 bytes per element).
+
+    python -m paper_2109_01286_amd.profile_summary STATS_DIR FETCH_DIR WRITE_DIR OUT.md "COMMAND"
+"""
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+
+
+def source_digest():
+    """sha256 of the hot-path kernel source the counters belong to."""
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def _short(name):
+    return name.replace("hfd::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+
+def _agg(path):
+    rows = list(csv.DictReader(open(path)))
+    a = collections.defaultdict(list)
+    for r in rows:
+        a[(_short(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return a
+
+
+def main(stats_dir, fetch_dir, write_dir, out, command):
+    lines = ["# rocprofv3 summary: shock-vortex 2049 x 1025 (2.1 M owned vertices, 6.33 M active edges)", "",
+             "Commands (on the MI355X box, from the repository root, `export TMPDIR=/tmp`):", "",
+             "    " + command, "", "## Kernel statistics (`--kernel-trace --stats`)", "",
+             "| kernel | calls | average (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
+    rows = list(csv.DictReader(open(os.path.join(stats_dir, "run_kernel_stats.csv"))))
+    for r in rows[:14]:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                     f"{float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} | "
+                     f"{float(r['Percentage']):.2f} % |")
+    F = _agg(os.path.join(fetch_dir, "run_counter_collection.csv"))
+    W = _agg(os.path.join(write_dir, "run_counter_collection.csv"))
+    ck = max((k for k in F if k[0] == "k_cast"), key=lambda k: k[1])
+    n = ck[1]
+    ff = (8 * n / 1024) / (sum(F[ck]) / len(F[ck]))
+    fw = (4 * n / 1024) / (sum(W[ck]) / len(W[ck]))
+    lines += ["", "## HBM traffic per launch (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`)", "",
+              f"Calibration on `k_cast` ({n} elements): FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f}.", "",
+              "| kernel | launches | fetch (GB) | write (GB) | total (GB) |", "|---|---|---|---|---|"]
+    traffic = {}
+    for k in sorted(F, key=lambda k: -sum(F[k])):
+        if k[0].startswith(("k_vertex", "k_edge<", "k_to_gather")):
+            f = sum(F[k]) / len(F[k]) * 1024 * ff
+            w = sum(W[k]) / len(W[k]) * 1024 * fw
+            lines.append(f"| `{k[0]}` | {len(F[k])} | {f / 1e9:.3f} | {w / 1e9:.3f} | {(f + w) / 1e9:.3f} |")
+            traffic[k[0]] = {"fetch_bytes": f, "write_bytes": w, "bytes": f + w}
+    open(out, "w").write("\n".join(lines) + "\n")
+    js = os.path.splitext(out)[0] + "_traffic.json"
+    json.dump({"workload": "shockvortex2049", "kernels_hip_sha256": source_digest(),
+               "fetch_factor": ff, "write_factor": fw, "per_launch": traffic},
+              open(js, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:6])

@@ -1,0 +1,179 @@
+"""GPU adjoint (hand-written, float64) against (i) torch autograd through
+the CPU oracle and (ii) central finite differences of the GPU residual."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2109_01286_amd import hfd, inputs
+
+from ._helpers import lib_solver, oracle_scheme, oracle_weights_for_lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+CASES = {
+    "vortex21": ("vortex21", None, {}, "paper"),
+    "vortex21-weno": ("vortex21", None, {"w3_cap": 2.0}, "weno"),
+    "shockvortex": ("shockvortex2049", 17, {"w3_cap": 2.0}, "paper"),
+}
+
+
+def setup_case(key, force=True, switch=None):
+    """Oracle and library on one mesh, the oracle's weights imported.  With
+    ``force`` the library's switch is pinned to the oracle's decisions at U
+    (valid for one residual evaluation; a Runge-Kutta step re-decides at
+    every stage on both sides)."""
+    name, scale, kw, sw = CASES[key]
+    sw = switch or sw
+    m, U, _ = inputs.workload(name, scale)
+    sc = oracle_scheme(m, **kw)
+    S = lib_solver(m, 0, switch=sw, **kw)
+    ow = oracle_weights_for_lib(S, sc)
+    S.import_weights(ow["w5"], ow["w3"], ow["dv"], ow["de"])
+    if force:
+        _, _, mask, _ = sc.edge_states(torch.as_tensor(U), sw)
+        S.force_switch_mask(torch.as_tensor(mask.numpy()[ow["pos"]], device=DEV))
+    return m, U, sc, S, sw
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("key", list(CASES))
+def test_adjoint_residual_matches_autograd(key):
+    m, U, sc, S, sw = setup_case(key)
+    rng = np.random.default_rng(3)
+    lam = rng.standard_normal(U.shape)
+    lam[:, m.ghost_src != -1] = 0.0
+    Ut = torch.tensor(U, requires_grad=True)
+    R = sc.residual(Ut, sw)
+    (ref,) = torch.autograd.grad(R, Ut, torch.as_tensor(lam))
+    ref = ref.numpy()
+    # the oracle's derivative w.r.t. ghost rows: copies were moved onto
+    # their sources by the ghost fill; Dirichlet data are not differentiated
+    owned = m.ghost_src == -1
+    Ud = torch.as_tensor(S.to_internal(U), device=DEV)
+    ld = torch.as_tensor(S.to_internal(lam), device=DEV)
+    got = S.to_input(S.adjoint_residual(Ud, ld).cpu().numpy())
+    assert np.all(got[:, ~owned] == 0.0)
+    err = rel(got[:, owned], ref[:, owned])
+    print(f"[adjoint] {key}: rel err vs autograd {err:.2e}")
+    assert err < 1e-10
+
+
+def test_adjoint_dot_product_with_finite_differences():
+    """<lam, (R(U + e d) - R(U - e d)) / 2e> = <J^T lam, d> on the GPU, 32
+    seeded directions, on the smooth branch (central differences through the
+    WENO weights alpha = d/(1e-6 + beta)^2 are not accurate at any step size;
+    those branches are checked against autograd above).  The step is 1e-8
+    of each component's scale: the FD error falls linearly with the step down
+    to rounding (kinks of |u.n| and of the maximum in the Rusanov flux are
+    crossed with a probability proportional to it), ~1e-7 here."""
+    m, U, sc, S, sw = setup_case("vortex21", force=False, switch="smooth")
+    rng = np.random.default_rng(4)
+    owned = m.ghost_src == -1
+    Ud = torch.as_tensor(S.to_internal(U), device=DEV)
+    lam = torch.as_tensor(S.to_internal(rng.standard_normal(U.shape)), device=DEV)
+    JTl = S.adjoint_residual(Ud, lam)
+    fds, ads = [], []
+    for k in range(32):
+        d = torch.as_tensor(S.to_internal(rng.standard_normal(U.shape) * np.abs(U).max(axis=1, keepdims=True)),
+                            device=DEV)
+        eps = 1e-8
+        Rp = S.residual(Ud + eps * d)
+        Rm = S.residual(Ud - eps * d)
+        fds.append(float(torch.sum(lam * (Rp - Rm)) / (2 * eps)))
+        ads.append(float(torch.sum(JTl * d)))
+    fds, ads = np.array(fds), np.array(ads)
+    # relative to the typical directional derivative (a single random
+    # direction can make <J^T lam, d> small by cancellation)
+    errs = np.abs(fds - ads) / np.sqrt(np.mean(ads ** 2))
+    print(f"[adjoint] FD directional errors: max {errs.max():.2e}, median {np.median(errs):.2e}")
+    assert errs.max() < 1e-6
+
+
+@pytest.mark.parametrize("key", ["vortex21-weno", "shockvortex"])
+def test_rk_step_adjoint_matches_autograd(key):
+    m, U, sc, S, sw = setup_case(key, force=False)
+    dt = sc.stable_dt(U, 0.3)
+    rng = np.random.default_rng(5)
+    lam = rng.standard_normal(U.shape)
+    Ut = torch.tensor(U, requires_grad=True)
+    U1 = sc.rk3_step(Ut, dt, sw)
+    (ref,) = torch.autograd.grad(U1, Ut, torch.as_tensor(lam))
+    ref = ref.numpy()
+    Ud = torch.as_tensor(S.to_internal(U), device=DEV)
+    ld = torch.as_tensor(S.to_internal(lam), device=DEV)
+    got = S.to_input(S.rk_step_adjoint(Ud, dt, ld).cpu().numpy())
+    # both sides took the same branches at every stage
+    U1g = Ud.clone()
+    S.rk_step(U1g, dt)
+    assert np.abs(S.to_input(U1g.cpu().numpy()) - U1.detach().numpy()).max() < 1e-10
+    owned = m.ghost_src == -1
+    dirich = m.ghost_src == -2
+    err = rel(got[:, owned], ref[:, owned])
+    print(f"[adjoint] {key} rk step: rel err vs autograd {err:.2e}")
+    assert err < 1e-10
+    # Dirichlet data pass through; the oracle's gradient there also holds the
+    # residual's dependence on them, which the library leaves out
+    assert np.array_equal(got[:, dirich], lam[:, dirich])
+    assert np.all(got[:, m.ghost_src >= 0] == 0.0)
+
+
+def test_viscous_adjoint_is_refused():
+    m, _, _ = inputs.workload("tgv513", 9)
+    S = lib_solver(m, 0, mu=0.01)
+    U = torch.zeros(12, m.nv, dtype=torch.float64, device=DEV)
+    with pytest.raises(hfd.HfdError) as e:
+        S.adjoint_residual(U, U)
+    assert e.value.status == 6
+
+
+def test_gradient_through_steps_with_checkpoints():
+    """rk_steps (checkpointed, hand-written adjoint) against autograd through
+    the oracle's steps and against central differences of the GPU forward,
+    smooth branch, 12 steps, checkpoints every 5 steps (partial segment)."""
+    from paper_2109_01286_amd.adjoint import pressure_disk_objective, rk_steps
+    m, U, sc, S, sw = setup_case("vortex21", force=False, switch="smooth")
+    dt = 0.5 * sc.stable_dt(U, 0.3)
+    nsteps = 12
+    xy = torch.as_tensor(m.xy[S.old_of_new], device=DEV)
+    area = torch.as_tensor(inputs.vertex_areas(m)[S.old_of_new], device=DEV)
+
+    def J_gpu(U0d):
+        return pressure_disk_objective(rk_steps(U0d, S, nsteps, dt, 5), xy, (7.0, 7.0), 1.5, area)
+
+    U0d = torch.as_tensor(S.to_internal(U), device=DEV).requires_grad_(True)
+    J = J_gpu(U0d)
+    (g,) = torch.autograd.grad(J, U0d)
+    g = S.to_input(g.cpu().numpy())
+    # oracle: autograd through its own steps
+    Ut = torch.tensor(U, requires_grad=True)
+    X = Ut
+    for _ in range(nsteps):
+        X = sc.rk3_step(X, dt, sw)
+    xo = torch.as_tensor(m.xy)
+    ao = torch.as_tensor(inputs.vertex_areas(m))
+    Jo = pressure_disk_objective(X, xo, (7.0, 7.0), 1.5, ao)
+    (go,) = torch.autograd.grad(Jo, Ut)
+    go = go.numpy()
+    assert abs(J.item() - Jo.item()) <= 1e-12 * abs(Jo.item())
+    err = rel(g, go)
+    print(f"[adjoint] {nsteps}-step gradient vs oracle autograd: rel err {err:.2e}")
+    assert err < 1e-10
+    # central differences of the GPU forward in 8 seeded directions
+    rng = np.random.default_rng(6)
+    errs = []
+    with torch.no_grad():
+        for k in range(8):
+            d = rng.standard_normal(U.shape) * np.abs(U).max(axis=1, keepdims=True)
+            dd = torch.as_tensor(S.to_internal(d), device=DEV)
+            eps = 1e-7
+            Jp = J_gpu(U0d.detach() + eps * dd).item()
+            Jm = J_gpu(U0d.detach() - eps * dd).item()
+            fd = (Jp - Jm) / (2 * eps)
+            ad = float(np.sum(g * d))
+            errs.append(abs(fd - ad) / abs(ad))
+    print(f"[adjoint] {nsteps}-step gradient FD errors: max {max(errs):.2e}")
+    assert max(errs) < 1e-6
