@@ -146,9 +146,10 @@ hfd_status hfd_permutation(const hfd_ctx* ctx, int32_t* new_of_old);
 hfd_status hfd_export_edges(const hfd_ctx* ctx, int32_t* ends, int32_t* stencil);
 
 /* Vertex stencils of the owned vertices in internal order (host outputs):
- *   vptr[n_owned+1], vnodes[n_vslots]  S(v), input vertex ids, sorted
- *   eptr[n_owned+1], vedges[n_eslots]  M(v), internal edge indices, sorted by
- *                                      the edges' input end ids */
+ *   vptr[n_owned+1], vnodes[n_vslots]  S(v), input vertex ids
+ *   eptr[n_owned+1], vedges[n_eslots]  M(v), internal edge indices
+ * Slots are in the library's order (by internal index, for coalesced
+ * gathers); weight exports and imports use the same slot order. */
 hfd_status hfd_export_vertex_stencils(const hfd_ctx* ctx, int64_t* vptr,
                                       int32_t* vnodes, int64_t* eptr,
                                       int32_t* vedges);

@@ -23,8 +23,30 @@
 
 #include "kernels.h"
 
+// Tuning parameters (compile-time).
+#ifndef HFD_VERTEX_LANES
+#define HFD_VERTEX_LANES 16   // lanes per vertex in the vertex pass
+#endif
+#ifndef HFD_NT_COEF
+#define HFD_NT_COEF 0         // 1: non-temporal loads for single-use coefficient streams
+#endif
+#ifndef HFD_XCD_REMAP
+#define HFD_XCD_REMAP 1       // 1: contiguous block ranges per XCD
+#endif
+
 namespace hfd {
 namespace {
+
+// Load of a value that is used once per launch (coefficients, indices):
+// optionally marked non-temporal so it does not displace gathered data.
+template <class T>
+__device__ inline T ldc(const T* p) {
+#if HFD_NT_COEF
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
 
 // Fluxes minus the reference fluxes, from the perturbation w' and the full
 // density/momenta.  With a zero reference these are the plain fluxes.
@@ -86,6 +108,9 @@ __device__ inline Ref<T> make_ref(const GasParams& gp) {
 // blocks: neighbouring vertices / edges then share an L2 for their gathers.
 constexpr int kXcd = 8;
 __device__ inline int64_t xcd_block() {
+#if !HFD_XCD_REMAP
+  return blockIdx.x;
+#endif
   const int64_t b = blockIdx.x, nb = gridDim.x;
   const int64_t x = b % kXcd, k = b / kXcd;
   const int64_t q = nb / kXcd, r = nb % kXcd;
@@ -159,14 +184,14 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     const int s = s0 + k;
     int id[5];
 #pragma unroll
-    for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
+    for (int t = 0; t < 5; ++t) id[t] = ldc(c.stg + (s == 0 ? t : 5 - t) * ne + e);
     // The 5-node Hermite row is the same for the four characteristic
     // components, so L (sum_t w5_t . data_t) is the projected Hermite value:
     // only the node values need projecting (for the smoothness indicators
     // and the 3-node values); the gradients enter through the physical sum.
     T w5[15];
 #pragma unroll
-    for (int j = 0; j < 15; ++j) w5[j] = c.w5[int64_t(s * 15 + j) * ne + e];
+    for (int j = 0; j < 15; ++j) w5[j] = ldc(c.w5 + int64_t(s * 15 + j) * ne + e);
     T cv[4][5], hs[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -182,7 +207,7 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     }
     T w3[9];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) w3[j] = c.w3[int64_t(s * 9 + j) * ne + e];
+    for (int j = 0; j < 9; ++j) w3[j] = ldc(c.w3 + int64_t(s * 9 + j) * ne + e);
     T C[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -270,8 +295,8 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 // ---------------------------------------------------------------------------
 // Vertex pass
 // ---------------------------------------------------------------------------
-constexpr int VL = 16;       // lanes per vertex
-constexpr int VPB = 16;      // vertices per block (256 threads)
+constexpr int VL = HFD_VERTEX_LANES;   // lanes per vertex
+constexpr int VPB = 256 / VL;          // vertices per block (256 threads)
 
 template <class T>
 __device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
@@ -355,18 +380,18 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
     const int s0 = c.vptr[v], s1 = c.vptr[v + 1];
     for (int s = s0 + sub; s < s1; s += 2 * VL) {
       const int sb = (s + VL < s1) ? s + VL : s;
-      const int ua = c.vg[s], ub = c.vg[sb];
+      const int ua = ldc(c.vg + s), ub = ldc(c.vg + sb);
       T da[6], db[6], ka[5], kb[5];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        da[q] = c.dv[int64_t(6) * s + q];
-        db[q] = c.dv[int64_t(6) * sb + q];
+        da[q] = ldc(c.dv + int64_t(6) * s + q);
+        db[q] = ldc(c.dv + int64_t(6) * sb + q);
       }
       if (VISC) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          ka[q] = c.dvis[int64_t(5) * s + q];
-          kb[q] = c.dvis[int64_t(5) * sb + q];
+          ka[q] = ldc(c.dvis + int64_t(5) * s + q);
+          kb[q] = ldc(c.dvis + int64_t(5) * sb + q);
         }
       }
       const V4<T> A = Gv[ua], B = Gv[ub];
@@ -394,9 +419,9 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
       T d[4][3];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        m[k] = c.ve[j[k]];
+        m[k] = ldc(c.ve + j[k]);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) d[k][q] = c.de[int64_t(3) * j[k] + q];
+        for (int q = 0; q < 3; ++q) d[k][q] = ldc(c.de + int64_t(3) * j[k] + q);
       }
       V4<T> h[4];
 #pragma unroll

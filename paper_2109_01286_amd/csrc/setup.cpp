@@ -12,9 +12,9 @@
 //     (i+2, i+3); no candidate is a mesh error;
 //   - periodic displacement by the minimum image (d -= P if d > P/2,
 //     d += P if d < -P/2);
-//   - S(v) sorted by input id; M(v) = edges with both ends in S(v), sorted by
-//     (first, second) input id; an edge is active when some owned vertex
-//     uses it.
+//   - S(v) = v and its two rings; M(v) = edges with both ends in S(v); an edge
+//     is active when some owned vertex uses it.  The slots of S(v) and M(v)
+//     are stored in the order of the internal (Hilbert) numbering.
 #include "setup.h"
 
 #include <algorithm>
@@ -361,6 +361,22 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
   S.m_nrm.resize(2 * NES);
   S.v_h.resize(NO);
   S.v_hmin.resize(NO);
+  // Slot order inside a vertex: by gather row (vertex slots) and by internal
+  // edge index (edge slots), so that neighbouring lanes gather neighbouring
+  // addresses.  The stencil sets are those of the paper's rule; only the
+  // order of the terms of the dot products changes.
+  parallel_for(NO, [&](int64_t b0, int64_t b1, unsigned) {
+    for (int64_t k = b0; k < b1; ++k) {
+      std::vector<int32_t>& s = vn[k];
+      std::stable_sort(s.begin(), s.end(), [&](int32_t a, int32_t b) {
+        return S.gather[S.new_of_old[a]] < S.gather[S.new_of_old[b]] ||
+               (S.gather[S.new_of_old[a]] == S.gather[S.new_of_old[b]] &&
+                S.new_of_old[a] < S.new_of_old[b]);
+      });
+      std::vector<int32_t>& m = ve[k];
+      std::sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return e_int[a] < e_int[b]; });
+    }
+  });
   parallel_for(NO, [&](int64_t b0, int64_t b1, unsigned) {
     for (int64_t k = b0; k < b1; ++k) {
       int32_t v = order[k];

@@ -34,15 +34,24 @@ def oracle_weights_for_lib(S, sc):
     de = np.empty((eptr[-1], 3))
     dvis = np.empty((vptr[-1], 5)) if sc.vr.dvis[0] is not None else None
     for k in range(S.n_owned):
-        j = vindex[int(S.old_of_new[k])]
+        v = int(S.old_of_new[k])
+        j = vindex[v]
         d = sc.vr.d[j]
-        N = vptr[k + 1] - vptr[k]
-        dv[vptr[k]:vptr[k + 1]] = np.stack([d[0, 0:2 * N:2], d[0, 1:2 * N:2],
-                                            d[1, 0:2 * N:2], d[1, 1:2 * N:2],
-                                            d[2, 0:2 * N:2], d[2, 1:2 * N:2]], 1)
-        de[eptr[k]:eptr[k + 1]] = d[:, 2 * N:].T
+        Sv = sc.topo.vnodes[v]
+        Mv = sc.topo.vedges[v]
+        N = len(Sv)
+        # library slot -> oracle slot (same sets, possibly another order)
+        npos = {u: i for i, u in enumerate(Sv)}
+        epos = {e: i for i, e in enumerate(Mv)}
+        ns = np.array([npos[int(u)] for u in vn[vptr[k]:vptr[k + 1]]])
+        es = np.array([epos[int(emap[m])] for m in ve[eptr[k]:eptr[k + 1]]])
+        assert ns.size == N and es.size == len(Mv)
+        dv[vptr[k]:vptr[k + 1]] = np.stack([d[0, 2 * ns], d[0, 2 * ns + 1],
+                                            d[1, 2 * ns], d[1, 2 * ns + 1],
+                                            d[2, 2 * ns], d[2, 2 * ns + 1]], 1)
+        de[eptr[k]:eptr[k + 1]] = d[:, 2 * N + es].T
         if dvis is not None:
-            dvis[vptr[k]:vptr[k + 1]] = sc.vr.dvis[j].T
+            dvis[vptr[k]:vptr[k + 1]] = sc.vr.dvis[j][:, ns].T
     return dict(w5=w5, w3=w3, rank=rank, dv=dv, de=de, dvis=dvis, emap=emap, pos=pos)
 
 
