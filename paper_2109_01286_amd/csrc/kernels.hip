@@ -11,9 +11,10 @@
 // vertex-only rows; three-stage TVD Runge-Kutta): 16 lanes per owned vertex
 // stride over the vertex slots (analytic fluxes recomputed from the
 // gathered state, dotted with the coefficient record of the slot) and the
-// edge slots (gathered edge flux); a xor-shuffle reduction gives the twelve
-// right-hand sides, lane k < 12 applies the Runge-Kutta combination to
-// component k.  No atomics: every output has exactly one writer.
+// edge slots (gathered edge flux), all loads of a batch in flight together;
+// a transposed DPP reduction gives the twelve right-hand sides, staged in
+// LDS so that the float64 Runge-Kutta update is written row by row.  No
+// atomics: every output has exactly one writer.
 //
 // Two precisions share the code: float64 throughout, or float32 arithmetic
 // on a float32 perturbation state w' = w - w_ref (gradients unchanged) with
@@ -29,6 +30,9 @@
 #endif
 #ifndef HFD_NT_COEF
 #define HFD_NT_COEF 0         // 1: non-temporal loads for single-use coefficient streams
+#endif
+#ifndef HFD_EDGE_WAVES
+#define HFD_EDGE_WAVES 3      // waves per SIMD of the float32 edge kernel
 #endif
 #ifndef HFD_XCD_REMAP
 #define HFD_XCD_REMAP 1       // 1: contiguous block ranges per XCD
@@ -48,6 +52,27 @@ __device__ inline T ldc(const T* p) {
 #endif
 }
 
+// Division and square root.  float64 keeps the correctly rounded operations;
+// the float32 form uses the hardware reciprocal and square root (about 1 ulp,
+// far below the rounding of its float32 perturbation data) instead of the
+// much longer correctly rounded instruction sequences.
+template <class T>
+__device__ inline T fdiv(T a, T b) {
+  return a / b;
+}
+template <>
+__device__ inline float fdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+template <class T>
+__device__ inline T fsqrt(T x) {
+  return sqrt(x);
+}
+template <>
+__device__ inline float fsqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+
 // Fluxes minus the reference fluxes, from the perturbation w' and the full
 // density/momenta.  With a zero reference these are the plain fluxes.
 template <class T>
@@ -64,7 +89,7 @@ __device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
   const T rho = R.w[0] + wp[0];
   const T m = R.w[1] + wp[1];
   const T n = R.w[2] + wp[2];
-  const T ir = T(1) / rho;
+  const T ir = fdiv(T(1), rho);
   // m^2/rho - m_r u_r, m n/rho - m_r v_r, n^2/rho - n_r v_r
   const T amm = (wp[1] * (m + R.w[1]) - R.w[1] * R.u * wp[0]) * ir;
   const T amn = (wp[1] * n + R.w[1] * wp[2] - R.w[1] * R.v * wp[0]) * ir;
@@ -120,162 +145,114 @@ __device__ inline int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 // Edge pass
 // ---------------------------------------------------------------------------
-// LPE lanes per edge.  LPE = 2: lane side s = 0 interpolates the left state
-// from nodes (i-2 .. i+2), s = 1 the right state from (i+3 .. i-1); the pair
-// swaps states and both evaluate the flux (lane 0 stores it).  LPE = 1: one
-// lane does both sides in turn.
-// Waves per SIMD the edge pass is compiled for (register budget 512/waves).
-template <class T> struct EdgeWaves { static constexpr int value = 3; };
-template <> struct EdgeWaves<double> { static constexpr int value = 2; };
+// Roe average of the edge's end states (nodes i, i+1) and the eigenvector
+// matrices of the flux Jacobian along n: R (columns: right eigenvectors for
+// u.n - c, u.n, u.n + c, shear) and its inverse L (rows).
+template <class T>
+struct Frame {
+  T L[4][4], R[4][4];
+};
 
-template <class T, int LPE>
-__global__ void __launch_bounds__(256, EdgeWaves<T>::value)
-k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
-       const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
-       V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
-       uint8_t* __restrict__ mask) {
-  const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
-  const int s0 = LPE == 2 ? int(tid & 1) : 0;
-  const int64_t e = tid / LPE;
-  if (e >= ne) return;
-  const Ref<T> ref = make_ref<T>(gp);
-  const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
-  const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
-  const T nx = c.n[e], ny = c.n[ne + e];
-
-  // Roe average of the two end states (nodes i, i+1)
-  T u, v, hh, cc;
-  {
-    const V4<T> A = Gv[ia], B = Gv[ib];
-    T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
-    T ua = (ref.w[1] + A.y) / ra, ub = (ref.w[1] + B.y) / rb;
-    T va = (ref.w[2] + A.z) / ra, vb = (ref.w[2] + B.z) / rb;
-    T Ea = ref.w[3] + A.w, Eb = ref.w[3] + B.w;
-    T pa = gm1 * (Ea - T(0.5) * ra * (ua * ua + va * va));
-    T pb = gm1 * (Eb - T(0.5) * rb * (ub * ub + vb * vb));
-    T sa = sqrt(ra), sb = sqrt(rb);
-    T iw = T(1) / (sa + sb);
-    u = (sa * ua + sb * ub) * iw;
-    v = (sa * va + sb * vb) * iw;
-    hh = (sa * (Ea + pa) / ra + sb * (Eb + pb) / rb) * iw;
-    cc = sqrt(gm1 * (hh - T(0.5) * (u * u + v * v)));
-  }
+template <class T>
+__device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
+                                     const Ref<T>& ref, T gm1) {
+  const T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
+  const T ua = fdiv(ref.w[1] + A.y, ra), ub = fdiv(ref.w[1] + B.y, rb);
+  const T va = fdiv(ref.w[2] + A.z, ra), vb = fdiv(ref.w[2] + B.z, rb);
+  const T Ea = ref.w[3] + A.w, Eb = ref.w[3] + B.w;
+  const T pa = gm1 * (Ea - T(0.5) * ra * (ua * ua + va * va));
+  const T pb = gm1 * (Eb - T(0.5) * rb * (ub * ub + vb * vb));
+  const T sa = fsqrt(ra), sb = fsqrt(rb);
+  const T iw = fdiv(T(1), sa + sb);
+  const T u = (sa * ua + sb * ub) * iw;
+  const T v = (sa * va + sb * vb) * iw;
+  const T hh = (fdiv(sa * (Ea + pa), ra) + fdiv(sb * (Eb + pb), rb)) * iw;
+  const T cc = fsqrt(gm1 * (hh - T(0.5) * (u * u + v * v)));
   const T q2 = u * u + v * v;
   const T un = u * nx + v * ny, ut = -u * ny + v * nx;
-  const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1) / cc;
-  // left eigenvectors (rows), inverse of the right eigenvector matrix below
-  const T L[4][4] = {
-      {T(0.5) * (b2 + un * ic), T(-0.5) * (b1 * u + nx * ic), T(-0.5) * (b1 * v + ny * ic), T(0.5) * b1},
-      {T(1) - b2, b1 * u, b1 * v, -b1},
-      {T(0.5) * (b2 - un * ic), T(-0.5) * (b1 * u - nx * ic), T(-0.5) * (b1 * v - ny * ic), T(0.5) * b1},
-      {-ut, -ny, nx, T(0)}};
-  const T Rm[4][4] = {{T(1), T(1), T(1), T(0)},
-                      {u - cc * nx, u, u + cc * nx, -ny},
-                      {v - cc * ny, v, v + cc * ny, nx},
-                      {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}};
-  const uint8_t fm = force ? force[e] : uint8_t(0);
-  uint8_t bits = 0;
+  const T b1 = fdiv(gm1, cc * cc), b2 = T(0.5) * b1 * q2, ic = fdiv(T(1), cc);
+  return Frame<T>{
+      {{T(0.5) * (b2 + un * ic), T(-0.5) * (b1 * u + nx * ic), T(-0.5) * (b1 * v + ny * ic), T(0.5) * b1},
+       {T(1) - b2, b1 * u, b1 * v, -b1},
+       {T(0.5) * (b2 - un * ic), T(-0.5) * (b1 * u - nx * ic), T(-0.5) * (b1 * v - ny * ic), T(0.5) * b1},
+       {-ut, -ny, nx, T(0)}},
+      {{T(1), T(1), T(1), T(0)},
+       {u - cc * nx, u, u + cc * nx, -ny},
+       {v - cc * ny, v, v + cc * ny, nx},
+       {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}}};
+}
+
+// One side's interface state.  Per characteristic component q: the WENO5
+// smoothness indicators and weights (Jiang-Shu, linear weights 1/16, 10/16,
+// 5/16) of the five projected node values cv[q][0..4], the switch, then the
+// Hermite value L_q . hs (hs: the side's 5-node Hermite sum in physical
+// variables; the row is the same for all components) or the omega-weighted
+// 3-node values.  Back-projected with R into `out`; the WENO decisions go to
+// bits 4 s + q of `bits`.
+template <class T>
+__device__ inline void side_state(const T cv[4][5], const T hs[4], const T w3[9],
+                                  const Frame<T>& F, const GasParams& gp, int s,
+                                  bool forced, uint8_t fm, T out[4], uint8_t& bits) {
   const T eps = T(gp.eps), lo = T(gp.sw_lo), hi = T(gp.sw_hi);
   const T d1 = T(1.0 / 16.0), d2 = T(10.0 / 16.0), d3 = T(5.0 / 16.0);
+  T C[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T c0 = cv[q][0], c1 = cv[q][1], c2 = cv[q][2], c3 = cv[q][3], c4 = cv[q][4];
+    const T t1 = c0 - T(2) * c1 + c2, t2 = c0 - T(4) * c1 + T(3) * c2;
+    const T t3 = c1 - T(2) * c2 + c3, t4 = c1 - c3;
+    const T t5 = c2 - T(2) * c3 + c4, t6 = T(3) * c2 - T(4) * c3 + c4;
+    const T be1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
+    const T be2 = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
+    const T be3 = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
+    const T a1 = fdiv(d1, (eps + be1) * (eps + be1));
+    const T a2 = fdiv(d2, (eps + be2) * (eps + be2));
+    const T a3 = fdiv(d3, (eps + be3) * (eps + be3));
+    const T sa = a1 + a2 + a3;
+    const T o1 = fdiv(a1, sa), o2 = fdiv(a2, sa), o3 = fdiv(a3, sa);
+    bool weno;
+    if (forced) weno = (fm >> (4 * s + q)) & 1;
+    else if (gp.sw == HFD_SWITCH_PAPER) weno = !(o1 > lo && o1 < hi);
+    else weno = (gp.sw == HFD_SWITCH_WENO_ONLY);
+    T val;
+    if (weno) {
+      val = o1 * (w3[0] * c0 + w3[1] * c1 + w3[2] * c2) +
+            o2 * (w3[3] * c1 + w3[4] * c2 + w3[5] * c3) +
+            o3 * (w3[6] * c2 + w3[7] * c3 + w3[8] * c4);
+    } else {
+      val = F.L[q][0] * hs[0] + F.L[q][1] * hs[1] + F.L[q][2] * hs[2] + F.L[q][3] * hs[3];
+    }
+    C[q] = val;
+    bits |= uint8_t(weno ? 1 : 0) << (4 * s + q);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    out[r] = F.R[r][0] * C[0] + F.R[r][1] * C[1] + F.R[r][2] * C[2] + F.R[r][3] * C[3];
+}
 
-  T wm0[4], wm1[4];
-#pragma unroll 1
-  for (int k = 0; k < 3 - LPE; ++k) {
-    const int s = s0 + k;
-    int id[5];
-#pragma unroll
-    for (int t = 0; t < 5; ++t) id[t] = ldc(c.stg + (s == 0 ? t : 5 - t) * ne + e);
-    // The 5-node Hermite row is the same for the four characteristic
-    // components, so L (sum_t w5_t . data_t) is the projected Hermite value:
-    // only the node values need projecting (for the smoothness indicators
-    // and the 3-node values); the gradients enter through the physical sum.
-    T w5[15];
-#pragma unroll
-    for (int j = 0; j < 15; ++j) w5[j] = ldc(c.w5 + int64_t(s * 15 + j) * ne + e);
-    T cv[4][5], hs[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
-      const T w[4] = {a.x, a.y, a.z, a.w};
-      const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
-      const T wy[4] = {by.x, by.y, by.z, by.w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cv[q][j] = L[q][0] * w[0] + L[q][1] * w[1] + L[q][2] * w[2] + L[q][3] * w[3];
-        hs[q] += w5[3 * j] * w[q] + w5[3 * j + 1] * wx[q] + w5[3 * j + 2] * wy[q];
-      }
-    }
-    T w3[9];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) w3[j] = ldc(c.w3 + int64_t(s * 9 + j) * ne + e);
-    T C[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T c0 = cv[q][0], c1 = cv[q][1], c2 = cv[q][2], c3 = cv[q][3], c4 = cv[q][4];
-      const T t1 = c0 - T(2) * c1 + c2, t2 = c0 - T(4) * c1 + T(3) * c2;
-      const T t3 = c1 - T(2) * c2 + c3, t4 = c1 - c3;
-      const T t5 = c2 - T(2) * c3 + c4, t6 = T(3) * c2 - T(4) * c3 + c4;
-      const T be1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
-      const T be2 = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
-      const T be3 = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
-      const T a1 = d1 / ((eps + be1) * (eps + be1));
-      const T a2 = d2 / ((eps + be2) * (eps + be2));
-      const T a3 = d3 / ((eps + be3) * (eps + be3));
-      const T sa = a1 + a2 + a3;
-      const T o1 = a1 / sa, o2 = a2 / sa, o3 = a3 / sa;
-      bool weno;
-      if (force) weno = (fm >> (4 * s + q)) & 1;
-      else if (gp.sw == HFD_SWITCH_PAPER) weno = !(o1 > lo && o1 < hi);
-      else weno = (gp.sw == HFD_SWITCH_WENO_ONLY);
-      T val;
-      if (weno) {
-        val = o1 * (w3[0] * c0 + w3[1] * c1 + w3[2] * c2) +
-              o2 * (w3[3] * c1 + w3[4] * c2 + w3[5] * c3) +
-              o3 * (w3[6] * c2 + w3[7] * c3 + w3[8] * c4);
-      } else {
-        val = L[q][0] * hs[0] + L[q][1] * hs[1] + L[q][2] * hs[2] + L[q][3] * hs[3];
-      }
-      C[q] = val;
-      bits |= uint8_t(weno ? 1 : 0) << (4 * s + q);
-    }
-    // back-projection w' = R C of this side
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const T x = Rm[r][0] * C[0] + Rm[r][1] * C[1] + Rm[r][2] * C[2] + Rm[r][3] * C[3];
-      if (k == 0) wm0[r] = x;
-      else wm1[r] = x;
-    }
-  }
-  T wl[4], wr[4];
-  if (LPE == 1) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      wl[q] = wm0[q];
-      wr[q] = wm1[q];
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T o = __shfl_xor(wm0[q], 1);
-      wl[q] = s0 == 0 ? wm0[q] : o;
-      wr[q] = s0 == 0 ? o : wm0[q];
-    }
-    bits |= uint8_t(__shfl_xor(int(bits), 1));
-  }
-  // Rusanov flux along n (perturbation form)
+// Rusanov flux along n of the two interface states (perturbation form).
+template <class T>
+__device__ inline void rusanov(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                               T gam, T gm1, T h[4]) {
   T fl[4], gl[4], fr[4], gr[4], pl, rl, ul, vl, pr, rr, ur, vr;
   pert_flux<T>(wl, ref, gm1, fl, gl, &pl, &rl, &ul, &vl);
   pert_flux<T>(wr, ref, gm1, fr, gr, &pr, &rr, &ur, &vr);
-  const T sl = fabs(ul * nx + vl * ny) + sqrt(gam * pl / rl);
-  const T sr = fabs(ur * nx + vr * ny) + sqrt(gam * pr / rr);
+  const T sl = fabs(ul * nx + vl * ny) + fsqrt(fdiv(gam * pl, rl));
+  const T sr = fabs(ur * nx + vr * ny) + fsqrt(fdiv(gam * pr, rr));
   // NaN-propagating maximum: a non-physical state must not be hidden
   const T lam = (isnan(sl) || isnan(sr)) ? sl + sr : (sl > sr ? sl : sr);
-  T h[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
            T(0.5) * lam * (wr[q] - wl[q]);
-  if (s0 == 0) {
+}
+
+template <class T>
+__device__ inline void store_edge(int64_t ne, int64_t e, const T h[4], const T wl[4],
+                                  const T wr[4], uint8_t bits, const GasParams& gp,
+                                  V4<T>* H, double* hsoa, double* wlr, uint8_t* mask,
+                                  bool left, bool right) {
+  if (left) {
     H[e] = V4<T>{h[0], h[1], h[2], h[3]};
     if (mask) mask[e] = bits;
     if (hsoa) {
@@ -286,10 +263,150 @@ k_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   if (wlr) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (LPE == 1 || s0 == 0) wlr[q * ne + e] = double(wl[q]) + gp.wref[q];
-      if (LPE == 1 || s0 == 1) wlr[(4 + q) * ne + e] = double(wr[q]) + gp.wref[q];
+      if (left) wlr[q * ne + e] = double(wl[q]) + gp.wref[q];
+      if (right) wlr[(4 + q) * ne + e] = double(wr[q]) + gp.wref[q];
     }
   }
+}
+
+// Waves per SIMD each edge kernel is compiled for (register budget 512/waves).
+template <class T> struct EdgeWaves { static constexpr int value = 2; };
+template <> struct EdgeWaves<float> { static constexpr int value = HFD_EDGE_WAVES; };
+
+// One lane per edge.  The six stencil nodes are gathered and projected once
+// and serve both sides: the left state interpolates from nodes 0..4
+// (i-2 .. i+2), the right state from nodes 5..1 (i+3 .. i-1).  All loads of
+// an edge are issued before its arithmetic.
+template <class T>
+__global__ void __launch_bounds__(256, EdgeWaves<T>::value)
+k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
+        const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
+        V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
+        uint8_t* __restrict__ mask) {
+  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const Ref<T> ref = make_ref<T>(gp);
+  const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
+  int id[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) id[t] = ldc(c.stg + t * ne + e);
+  const T nx = ldc(c.n + e), ny = ldc(c.n + ne + e);
+  T w5[2][15], w3[2][9];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int j = 0; j < 15; ++j) w5[s][j] = ldc(c.w5 + int64_t(s * 15 + j) * ne + e);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) w3[s][j] = ldc(c.w3 + int64_t(s * 9 + j) * ne + e);
+  }
+  const uint8_t fm = force ? force[e] : uint8_t(0);
+  T w[6][4], wx[6][4], wy[6][4];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const V4<T> a = Gv[id[t]], bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
+    w[t][0] = a.x, w[t][1] = a.y, w[t][2] = a.z, w[t][3] = a.w;
+    wx[t][0] = bx.x, wx[t][1] = bx.y, wx[t][2] = bx.z, wx[t][3] = bx.w;
+    wy[t][0] = by.x, wy[t][1] = by.y, wy[t][2] = by.z, wy[t][3] = by.w;
+  }
+  const Frame<T> F = roe_frame<T>(V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]},
+                                  V4<T>{w[3][0], w[3][1], w[3][2], w[3][3]}, nx, ny, ref, gm1);
+  // Hermite sums in physical variables: the 5-node row is the same for the
+  // four characteristic components, so L (sum_t w5_t . data_t) is the
+  // projected Hermite value
+  T hs[2][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    hs[0][q] = T(0);
+    hs[1][q] = T(0);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      hs[0][q] += w5[0][3 * p] * w[p][q] + w5[0][3 * p + 1] * wx[p][q] + w5[0][3 * p + 2] * wy[p][q];
+      const int n = 5 - p;
+      hs[1][q] += w5[1][3 * p] * w[n][q] + w5[1][3 * p + 1] * wx[n][q] + w5[1][3 * p + 2] * wy[n][q];
+    }
+  }
+  // characteristic projection of the six node values
+  T cv[4][6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      cv[q][t] = F.L[q][0] * w[t][0] + F.L[q][1] * w[t][1] + F.L[q][2] * w[t][2] + F.L[q][3] * w[t][3];
+  }
+  uint8_t bits = 0;
+  T wl[4], wr[4], c5[4][5];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][p];
+  }
+  side_state<T>(c5, hs[0], w3[0], F, gp, 0, force != nullptr, fm, wl, bits);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][5 - p];
+  }
+  side_state<T>(c5, hs[1], w3[1], F, gp, 1, force != nullptr, fm, wr, bits);
+  T h[4];
+  rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+  store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, true, true);
+}
+
+// Two lanes per edge (lane side s = tid & 1 interpolates one state), for the
+// float64 form where one lane's registers cannot hold both sides: the pair
+// swaps states and both evaluate the flux (lane 0 stores it).
+template <class T>
+__global__ void __launch_bounds__(256, EdgeWaves<T>::value)
+k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
+        const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
+        V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
+        uint8_t* __restrict__ mask) {
+  const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
+  const int s = int(tid & 1);
+  const int64_t e = tid / 2;
+  if (e >= ne) return;
+  const Ref<T> ref = make_ref<T>(gp);
+  const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
+  const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
+  const T nx = c.n[e], ny = c.n[ne + e];
+  const Frame<T> F = roe_frame<T>(Gv[ia], Gv[ib], nx, ny, ref, gm1);
+  const uint8_t fm = force ? force[e] : uint8_t(0);
+  int id[5];
+#pragma unroll
+  for (int t = 0; t < 5; ++t) id[t] = ldc(c.stg + (s == 0 ? t : 5 - t) * ne + e);
+  T w5[15];
+#pragma unroll
+  for (int j = 0; j < 15; ++j) w5[j] = ldc(c.w5 + int64_t(s * 15 + j) * ne + e);
+  T cv[4][5], hs[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
+    const T w[4] = {a.x, a.y, a.z, a.w};
+    const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
+    const T wy[4] = {by.x, by.y, by.z, by.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cv[q][j] = F.L[q][0] * w[0] + F.L[q][1] * w[1] + F.L[q][2] * w[2] + F.L[q][3] * w[3];
+      hs[q] += w5[3 * j] * w[q] + w5[3 * j + 1] * wx[q] + w5[3 * j + 2] * wy[q];
+    }
+  }
+  T w3[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) w3[j] = ldc(c.w3 + int64_t(s * 9 + j) * ne + e);
+  uint8_t bits = 0;
+  T wm[4];
+  side_state<T>(cv, hs, w3, F, gp, s, force != nullptr, fm, wm, bits);
+  T wl[4], wr[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T o = __shfl_xor(wm[q], 1);
+    wl[q] = s == 0 ? wm[q] : o;
+    wr[q] = s == 0 ? o : wm[q];
+  }
+  bits |= uint8_t(__shfl_xor(int(bits), 1));
+  T h[4];
+  rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+  store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, s == 0, s == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,7 +419,7 @@ template <class T>
 __device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
                                     const GasParams& gp, T fv[4], T gv[4]) {
   const T gm1 = T(gp.gamma - 1.0);
-  const T rho = w[0], ir = T(1) / rho;
+  const T rho = w[0], ir = fdiv(T(1), rho);
   const T u = w[1] * ir, v = w[2] * ir;
   const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
   const T iR = T(1.0 / gp.gas_R);
@@ -358,6 +475,45 @@ __device__ inline void vslot(const V4<T>& a, const V4<T>* gx, const T* d, const 
   }
 }
 
+// Lane exchange through DPP (a VALU move, no LDS traffic).  0x140 mirrors a
+// row of 16 lanes (the partner differs in bit 3 of the lane index), 0x141
+// mirrors each half row (bit 2), the quad permutations 0x4E and 0xB1 swap
+// lanes differing in bit 1 and in bit 0.
+template <int CTRL>
+__device__ inline float dpp_mov(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32));
+}
+
+// One stage of the transposed lane reduction: of its N values the lane keeps
+// the half selected by bit B of its index and adds the partner's copy of that
+// half.  The four partner maps above pair disjoint lane sets at every stage,
+// so after the stages for bits log2(VL)-1 .. 0 each value is a sum over all
+// VL lanes, and lane `sub` holds accumulators (16/VL) sub + i.
+template <int B, int N, class T>
+__device__ inline void reduce_stage(T* a, int sub) {
+  constexpr int CTRL = B == 3 ? 0x140 : B == 2 ? 0x141 : B == 1 ? 0x4E : 0xB1;
+  const bool hi = (sub >> B) & 1;
+#pragma unroll
+  for (int j = 0; j < N / 2; ++j) {
+    const T send = hi ? a[j] : a[N / 2 + j];
+    const T keep = hi ? a[N / 2 + j] : a[j];
+    a[j] = keep + dpp_mov<CTRL>(send);
+  }
+}
+
+// Slots per lane and iteration: every load of a batch is issued before any
+// of its data is used.
+constexpr int NVS = VL == 16 ? 2 : 3;   // vertex slots
+constexpr int NES = VL == 16 ? 4 : 6;   // edge slots
+
 template <class T, bool VISC>
 __global__ void __launch_bounds__(256)
 k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
@@ -365,117 +521,139 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
          const V4<T>* __restrict__ H, int mode, double* __restrict__ dU, RkArgs rk,
          V4<T>* __restrict__ Gv_new, V4<T>* __restrict__ Gg_new,
          int32_t* __restrict__ flag) {
+  static_assert(VL == 8 || VL == 16, "8 or 16 lanes per vertex");
   __shared__ double sres[VPB][13];
-  const int vl = threadIdx.x / VL, sub = threadIdx.x & (VL - 1);
+  const int t = threadIdx.x;
+  const int vl = t / VL, sub = t & (VL - 1);
   const int64_t v0 = xcd_block() * VPB;
   const int64_t v = v0 + vl;
+
+  // The epilogue gives thread t component cmp of vertex v0 + vl2 (consecutive
+  // vertices in consecutive lanes, so every component row is written in
+  // VPB-wide runs).  Its Runge-Kutta operands are loaded first, so that their
+  // latency overlaps the slot loads.
+  const int cmp = t / VPB, vl2 = t % VPB;
+  const int64_t vv = v0 + vl2;
+  const bool ep = t < 12 * VPB && vv < nowned;
+  const int64_t o = int64_t(cmp) * nv + vv;
+  double un = 0.0, uk = 0.0, dt = 0.0;
+  if (mode == 1 && ep) {
+    un = rk.Un[o];
+    uk = rk.Uk[o];
+    dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
+  }
+
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = T(gp.gamma - 1.0);
-  T acc[12];
+  T acc[16];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = T(0);
+  for (int k = 0; k < 16; ++k) acc[k] = T(0);
 
   if (v < nowned) {
-    // vertex slots, two per lane and iteration (all loads issued first)
+    // S(v) holds v itself and M(v) at least one edge of v (the setup rejects
+    // meshes where the rows cannot be built), so s1 - 1 and e1 - 1 are slots
+    // of v: lanes past the end load them again and give them zero weight.
     const int s0 = c.vptr[v], s1 = c.vptr[v + 1];
-    for (int s = s0 + sub; s < s1; s += 2 * VL) {
-      const int sb = (s + VL < s1) ? s + VL : s;
-      const int ua = ldc(c.vg + s), ub = ldc(c.vg + sb);
-      T da[6], db[6], ka[5], kb[5];
+    const int e0 = c.eptr[v], e1 = c.eptr[v + 1];
+    for (int bs = s0 + sub, be = e0 + sub; bs < s1 || be < e1;
+         bs += NVS * VL, be += NES * VL) {
+      int js[NVS], je[NES];
+      bool oks[NVS], oke[NES];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        da[q] = ldc(c.dv + int64_t(6) * s + q);
-        db[q] = ldc(c.dv + int64_t(6) * sb + q);
+      for (int k = 0; k < NVS; ++k) {
+        oks[k] = bs + k * VL < s1;
+        js[k] = oks[k] ? bs + k * VL : s1 - 1;
       }
-      if (VISC) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          ka[q] = ldc(c.dvis + int64_t(5) * s + q);
-          kb[q] = ldc(c.dvis + int64_t(5) * sb + q);
+      for (int k = 0; k < NES; ++k) {
+        oke[k] = be + k * VL < e1;
+        je[k] = oke[k] ? be + k * VL : e1 - 1;
+      }
+      int u[NVS], m[NES];
+      T d[NVS][6], kv[NVS][5], de[NES][3];
+#pragma unroll
+      for (int k = 0; k < NVS; ++k) {
+        u[k] = ldc(c.vg + js[k]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) d[k][q] = ldc(c.dv + int64_t(6) * js[k] + q);
+        if (VISC) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) kv[k][q] = ldc(c.dvis + int64_t(5) * js[k] + q);
         }
       }
-      const V4<T> A = Gv[ua], B = Gv[ub];
-      V4<T> gA[2], gB[2];
-      if (VISC) {
-        gA[0] = Gg[2 * int64_t(ua)];
-        gA[1] = Gg[2 * int64_t(ua) + 1];
-        gB[0] = Gg[2 * int64_t(ub)];
-        gB[1] = Gg[2 * int64_t(ub) + 1];
+#pragma unroll
+      for (int k = 0; k < NES; ++k) {
+        m[k] = ldc(c.ve + je[k]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) de[k][q] = ldc(c.de + int64_t(3) * je[k] + q);
       }
-      vslot<T, VISC>(A, gA, da, ka, ref, gm1, gp, acc);
-      if (sb != s) vslot<T, VISC>(B, gB, db, kb, ref, gm1, gp, acc);
-    }
-    // edge slots, four per lane and iteration
-    const int e0 = c.eptr[v], e1 = c.eptr[v + 1];
-    for (int s = e0 + sub; s < e1; s += 4 * VL) {
-      int j[4];
-      bool ok[4];
+      V4<T> A[NVS], G[NVS][2], Hh[NES];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        ok[k] = s + k * VL < e1;
-        j[k] = ok[k] ? s + k * VL : s;
+      for (int k = 0; k < NVS; ++k) {
+        A[k] = Gv[u[k]];
+        if (VISC) {
+          G[k][0] = Gg[2 * int64_t(u[k])];
+          G[k][1] = Gg[2 * int64_t(u[k]) + 1];
+        }
       }
-      int m[4];
-      T d[4][3];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        m[k] = ldc(c.ve + j[k]);
+      for (int k = 0; k < NES; ++k) Hh[k] = H[m[k]];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) d[k][q] = ldc(c.de + int64_t(3) * j[k] + q);
+      for (int k = 0; k < NVS; ++k) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) d[k][q] = oks[k] ? d[k][q] : T(0);
+        if (VISC) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) kv[k][q] = oks[k] ? kv[k][q] : T(0);
+        }
+        vslot<T, VISC>(A[k], G[k], d[k], kv[k], ref, gm1, gp, acc);
       }
-      V4<T> h[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) h[k] = H[m[k]];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (!ok[k]) continue;
-        const T hq[4] = {h[k].x, h[k].y, h[k].z, h[k].w};
+      for (int k = 0; k < NES; ++k) {
+        const T w0 = oke[k] ? de[k][0] : T(0), w1 = oke[k] ? de[k][1] : T(0),
+                w2 = oke[k] ? de[k][2] : T(0);
+        const T hq[4] = {Hh[k].x, Hh[k].y, Hh[k].z, Hh[k].w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          acc[q] -= d[k][0] * hq[q];
-          acc[4 + q] -= d[k][1] * hq[q];
-          acc[8 + q] -= d[k][2] * hq[q];
+          acc[q] -= w0 * hq[q];
+          acc[4 + q] -= w1 * hq[q];
+          acc[8 + q] -= w2 * hq[q];
         }
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-#pragma unroll
-    for (int o = VL / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+  if constexpr (VL == 16) {
+    reduce_stage<3, 16>(acc, sub);
+    reduce_stage<2, 8>(acc, sub);
+    reduce_stage<1, 4>(acc, sub);
+    reduce_stage<0, 2>(acc, sub);
+  } else {
+    reduce_stage<2, 16>(acc, sub);
+    reduce_stage<1, 8>(acc, sub);
+    reduce_stage<0, 4>(acc, sub);
   }
-  T r = acc[0];
+  constexpr int CPL = 16 / VL;
 #pragma unroll
-  for (int k = 1; k < 12; ++k)
-    if (sub == k) r = acc[k];
-  if (sub < 12) sres[vl][sub] = double(r);
+  for (int i = 0; i < CPL; ++i)
+    if (CPL * sub + i < 12) sres[vl][CPL * sub + i] = double(acc[i]);
   __syncthreads();
 
-  // epilogue: thread (component cmp, vertex vl2), consecutive vertices in
-  // consecutive lanes so every component row is written in 16-wide runs
-  const int t = threadIdx.x;
   bool bad = false;
-  if (t < 12 * VPB) {
-    const int cmp = t / VPB, vl2 = t % VPB;
-    const int64_t vv = v0 + vl2;
-    if (vv < nowned) {
-      const double rv = sres[vl2][cmp];
-      const int64_t o = int64_t(cmp) * nv + vv;
-      if (mode == 0) {
-        dU[o] = rv;
-        bad = !isfinite(rv);
-      } else {
-        const double dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
-        const double out = rk.a * rk.Un[o] + rk.b * (rk.Uk[o] + dt * rv);
-        rk.Unew[o] = out;
-        if (Gv_new) {
-          const T g = T(out - (cmp < 4 ? gp.wref[cmp] : 0.0));
-          if (cmp < 4) reinterpret_cast<T*>(Gv_new)[4 * vv + cmp] = g;
-          else reinterpret_cast<T*>(Gg_new)[8 * vv + (cmp - 4)] = g;
-        }
-        bad = !isfinite(out);
-        if (cmp < 4) sres[vl2][cmp] = out;
+  if (ep) {
+    const double rv = sres[vl2][cmp];
+    if (mode == 0) {
+      dU[o] = rv;
+      bad = !isfinite(rv);
+    } else {
+      const double out = rk.a * un + rk.b * (uk + dt * rv);
+      rk.Unew[o] = out;
+      if (Gv_new) {
+        const T g = T(out - (cmp < 4 ? gp.wref[cmp] : 0.0));
+        if (cmp < 4) reinterpret_cast<T*>(Gv_new)[4 * vv + cmp] = g;
+        else reinterpret_cast<T*>(Gg_new)[8 * vv + (cmp - 4)] = g;
       }
+      bad = !isfinite(out);
+      if (cmp < 4) sres[vl2][cmp] = out;
     }
   }
   __syncthreads();
@@ -625,9 +803,12 @@ hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
                        double* hsoa, double* wlr, uint8_t* mask, hipStream_t st) {
   if (ne == 0) return hipSuccess;
   // float: one lane per edge; double: two (one per side), register budget
-  constexpr int lpe = sizeof(T) == 8 ? 2 : 1;
-  hipLaunchKernelGGL((k_edge<T, lpe>), dim3(nblocks(lpe * ne, 256)), dim3(256), 0, st, ne, c,
-                     gp, Gv, Gg, force, H, hsoa, wlr, mask);
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL(k_edge2<T>, dim3(nblocks(2 * ne, 256)), dim3(256), 0, st, ne, c, gp,
+                       Gv, Gg, force, H, hsoa, wlr, mask);
+  else
+    hipLaunchKernelGGL(k_edge1<T>, dim3(nblocks(ne, 256)), dim3(256), 0, st, ne, c, gp, Gv,
+                       Gg, force, H, hsoa, wlr, mask);
   return hipGetLastError();
 }
 template hipError_t launch_edge<double>(int64_t, const EdgeCoef<double>&, const GasParams&,
