@@ -25,11 +25,17 @@
 #include "kernels.h"
 
 // Tuning parameters (compile-time).
-#ifndef HFD_VERTEX_LANES
-#define HFD_VERTEX_LANES 16   // lanes per vertex in the vertex pass
+#ifndef HFD_VERTEX_LANES32
+#define HFD_VERTEX_LANES32 16 // lanes per vertex in the float32 vertex pass
+#endif
+#ifndef HFD_VERTEX_LANES64
+#define HFD_VERTEX_LANES64 16 // lanes per vertex in the float64 vertex pass
 #endif
 #ifndef HFD_NT_COEF
 #define HFD_NT_COEF 0         // 1: non-temporal loads for single-use coefficient streams
+#endif
+#ifndef HFD_VERTEX_WAVES
+#define HFD_VERTEX_WAVES 4    // waves per SIMD of the float32 vertex kernel
 #endif
 #ifndef HFD_EDGE_WAVES
 #define HFD_EDGE_WAVES 3      // waves per SIMD of the float32 edge kernel
@@ -71,6 +77,18 @@ __device__ inline T fsqrt(T x) {
 template <>
 __device__ inline float fsqrt<float>(float x) {
   return __builtin_amdgcn_sqrtf(x);
+}
+
+// base[uoff] plus a per-lane byte offset, with the wave-uniform element
+// offset pinned in scalar registers: the load then takes a scalar base and
+// one 32-bit vector register for its address.
+template <class P>
+__device__ inline const P* at(const P* base, int64_t uoff, uint32_t byte_off) {
+  const uint64_t u = uint64_t(uoff) * sizeof(P);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+  const char* b = reinterpret_cast<const char*>(base) + (uint64_t(lo) | (uint64_t(hi) << 32));
+  return reinterpret_cast<const P*>(b + byte_off);
 }
 
 // Fluxes minus the reference fluxes, from the perturbation w' and the full
@@ -283,21 +301,28 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
         V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
         uint8_t* __restrict__ mask) {
-  const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t e0 = xcd_block() * blockDim.x;
+  const int64_t e = e0 + threadIdx.x;
   if (e >= ne) return;
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
+  // Row r of a [rows][ne] coefficient array at this edge: the row base of the
+  // block is uniform, the lane adds a 32-bit byte offset (one register for
+  // all rows).
+  const uint32_t lo = threadIdx.x * uint32_t(sizeof(T));
+  const uint32_t li = threadIdx.x * 4u;
+  auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
   int id[6];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) id[t] = ldc(c.stg + t * ne + e);
-  const T nx = ldc(c.n + e), ny = ldc(c.n + ne + e);
+  for (int t = 0; t < 6; ++t) id[t] = *at(c.stg, t * ne + e0, li);
+  const T nx = row(c.n, 0), ny = row(c.n, 1);
   T w5[2][15], w3[2][9];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
 #pragma unroll
-    for (int j = 0; j < 15; ++j) w5[s][j] = ldc(c.w5 + int64_t(s * 15 + j) * ne + e);
+    for (int j = 0; j < 15; ++j) w5[s][j] = row(c.w5, s * 15 + j);
 #pragma unroll
-    for (int j = 0; j < 9; ++j) w3[s][j] = ldc(c.w3 + int64_t(s * 9 + j) * ne + e);
+    for (int j = 0; j < 9; ++j) w3[s][j] = row(c.w3, s * 9 + j);
   }
   const uint8_t fm = force ? force[e] : uint8_t(0);
   T w[6][4], wx[6][4], wy[6][4];
@@ -361,22 +386,27 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
         V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
         uint8_t* __restrict__ mask) {
-  const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
-  const int s = int(tid & 1);
-  const int64_t e = tid / 2;
+  const int64_t e0 = xcd_block() * (blockDim.x / 2);
+  const int s = int(threadIdx.x & 1);
+  const int64_t e = e0 + threadIdx.x / 2;
   if (e >= ne) return;
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
-  const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
-  const T nx = c.n[e], ny = c.n[ne + e];
+  // coefficient rows as in k_edge1, the pair of lanes sharing the edge
+  const uint32_t lo = (threadIdx.x / 2) * uint32_t(sizeof(T));
+  const uint32_t li = (threadIdx.x / 2) * 4u;
+  auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
+  const int ia = *at(c.stg, 2 * ne + e0, li), ib = *at(c.stg, 3 * ne + e0, li);
+  const T nx = row(c.n, 0), ny = row(c.n, 1);
   const Frame<T> F = roe_frame<T>(Gv[ia], Gv[ib], nx, ny, ref, gm1);
   const uint8_t fm = force ? force[e] : uint8_t(0);
   int id[5];
 #pragma unroll
-  for (int t = 0; t < 5; ++t) id[t] = ldc(c.stg + (s == 0 ? t : 5 - t) * ne + e);
+  for (int t = 0; t < 5; ++t)  // (the row offset given to at() must be wave-uniform)
+    id[t] = s == 0 ? *at(c.stg, t * ne + e0, li) : *at(c.stg, (5 - t) * ne + e0, li);
   T w5[15];
 #pragma unroll
-  for (int j = 0; j < 15; ++j) w5[j] = ldc(c.w5 + int64_t(s * 15 + j) * ne + e);
+  for (int j = 0; j < 15; ++j) w5[j] = s == 0 ? row(c.w5, j) : row(c.w5, 15 + j);
   T cv[4][5], hs[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
@@ -392,7 +422,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   }
   T w3[9];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) w3[j] = ldc(c.w3 + int64_t(s * 9 + j) * ne + e);
+  for (int j = 0; j < 9; ++j) w3[j] = s == 0 ? row(c.w3, j) : row(c.w3, 9 + j);
   uint8_t bits = 0;
   T wm[4];
   side_state<T>(cv, hs, w3, F, gp, s, force != nullptr, fm, wm, bits);
@@ -412,8 +442,9 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 // ---------------------------------------------------------------------------
 // Vertex pass
 // ---------------------------------------------------------------------------
-constexpr int VL = HFD_VERTEX_LANES;   // lanes per vertex
-constexpr int VPB = 256 / VL;          // vertices per block (256 threads)
+// Lanes per vertex (8 or 16) and vertices per 256-thread block, per precision.
+template <class T> struct VertexLanes { static constexpr int value = HFD_VERTEX_LANES64; };
+template <> struct VertexLanes<float> { static constexpr int value = HFD_VERTEX_LANES32; };
 
 template <class T>
 __device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
@@ -509,39 +540,56 @@ __device__ inline void reduce_stage(T* a, int sub) {
   }
 }
 
-// Slots per lane and iteration: every load of a batch is issued before any
-// of its data is used.
-constexpr int NVS = VL == 16 ? 2 : 3;   // vertex slots
-constexpr int NES = VL == 16 ? 4 : 6;   // edge slots
+// A coefficient record of N values (loaded as one aggregate).
+template <class T, int N>
+struct Rec {
+  T v[N];
+};
+
+
+// Waves per SIMD the vertex kernel is compiled for (register budget 512/waves).
+template <class T> struct VertexWaves { static constexpr int value = 2; };
+template <> struct VertexWaves<float> { static constexpr int value = HFD_VERTEX_WAVES; };
 
 template <class T, bool VISC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, VISC ? 2 : VertexWaves<T>::value)
 k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
          const V4<T>* __restrict__ Gv, const V4<T>* __restrict__ Gg,
          const V4<T>* __restrict__ H, int mode, double* __restrict__ dU, RkArgs rk,
          V4<T>* __restrict__ Gv_new, V4<T>* __restrict__ Gg_new,
          int32_t* __restrict__ flag) {
+  constexpr int VL = VertexLanes<T>::value, VPB = 256 / VL;
   static_assert(VL == 8 || VL == 16, "8 or 16 lanes per vertex");
+  // slots per lane and iteration: every load of a batch is issued before any
+  // of its data is used
+  constexpr int NVS = VL == 16 ? 2 : 3;   // vertex slots
+  constexpr int NES = VL == 16 ? 4 : 6;   // edge slots
   __shared__ double sres[VPB][13];
   const int t = threadIdx.x;
   const int vl = t / VL, sub = t & (VL - 1);
   const int64_t v0 = xcd_block() * VPB;
   const int64_t v = v0 + vl;
 
-  // The epilogue gives thread t component cmp of vertex v0 + vl2 (consecutive
-  // vertices in consecutive lanes, so every component row is written in
-  // VPB-wide runs).  Its Runge-Kutta operands are loaded first, so that their
-  // latency overlaps the slot loads.
-  const int cmp = t / VPB, vl2 = t % VPB;
-  const int64_t vv = v0 + vl2;
-  const bool ep = t < 12 * VPB && vv < nowned;
-  const int64_t o = int64_t(cmp) * nv + vv;
-  double un = 0.0, uk = 0.0, dt = 0.0;
-  if (mode == 1 && ep) {
-    un = rk.Un[o];
-    uk = rk.Uk[o];
-    dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
+  // The epilogue gives element p = t + 256 i (i < NEP) of the block's
+  // 12 x VPB results to thread t: component p / VPB of vertex v0 + p % VPB,
+  // consecutive vertices in consecutive lanes so that every component row is
+  // written in VPB-wide runs.  Its Runge-Kutta operands are loaded first, so
+  // that their latency overlaps the slot loads.
+  constexpr int NEP = (12 * VPB + 255) / 256;
+  double un[NEP], uk[NEP];
+  double dt = 0.0;
+#pragma unroll
+  for (int i = 0; i < NEP; ++i) {
+    const int p = t + 256 * i;
+    const int64_t vv = v0 + p % VPB;
+    un[i] = uk[i] = 0.0;
+    if (mode == 1 && p < 12 * VPB && vv < nowned) {
+      const int64_t o = int64_t(p / VPB) * nv + vv;
+      un[i] = rk.Un[o];
+      uk[i] = rk.Uk[o];
+    }
   }
+  if (mode == 1) dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
 
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = T(gp.gamma - 1.0);
@@ -555,6 +603,14 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
     // of v: lanes past the end load them again and give them zero weight.
     const int s0 = c.vptr[v], s1 = c.vptr[v + 1];
     const int e0 = c.eptr[v], e1 = c.eptr[v + 1];
+    // The coefficient streams are addressed from the block's first slots
+    // (uniform) with 32-bit byte offsets: one register per address.
+    const int sb = c.vptr[v0], eb = c.eptr[v0];
+    const char* vgb = reinterpret_cast<const char*>(c.vg + sb);
+    const char* dvb = reinterpret_cast<const char*>(c.dv + int64_t(6) * sb);
+    const char* dkb = VISC ? reinterpret_cast<const char*>(c.dvis + int64_t(5) * sb) : nullptr;
+    const char* veb = reinterpret_cast<const char*>(c.ve + eb);
+    const char* deb = reinterpret_cast<const char*>(c.de + int64_t(3) * eb);
     for (int bs = s0 + sub, be = e0 + sub; bs < s1 || be < e1;
          bs += NVS * VL, be += NES * VL) {
       int js[NVS], je[NES];
@@ -573,19 +629,24 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
       T d[NVS][6], kv[NVS][5], de[NES][3];
 #pragma unroll
       for (int k = 0; k < NVS; ++k) {
-        u[k] = ldc(c.vg + js[k]);
+        const uint32_t r = uint32_t(js[k] - sb);
+        u[k] = *reinterpret_cast<const int32_t*>(vgb + 4u * r);
+        const Rec<T, 6> dr = *reinterpret_cast<const Rec<T, 6>*>(dvb + uint32_t(6 * sizeof(T)) * r);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) d[k][q] = ldc(c.dv + int64_t(6) * js[k] + q);
+        for (int q = 0; q < 6; ++q) d[k][q] = dr.v[q];
         if (VISC) {
+          const Rec<T, 5> kr = *reinterpret_cast<const Rec<T, 5>*>(dkb + uint32_t(5 * sizeof(T)) * r);
 #pragma unroll
-          for (int q = 0; q < 5; ++q) kv[k][q] = ldc(c.dvis + int64_t(5) * js[k] + q);
+          for (int q = 0; q < 5; ++q) kv[k][q] = kr.v[q];
         }
       }
 #pragma unroll
       for (int k = 0; k < NES; ++k) {
-        m[k] = ldc(c.ve + je[k]);
+        const uint32_t r = uint32_t(je[k] - eb);
+        m[k] = *reinterpret_cast<const int32_t*>(veb + 4u * r);
+        const Rec<T, 3> er = *reinterpret_cast<const Rec<T, 3>*>(deb + uint32_t(3 * sizeof(T)) * r);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) de[k][q] = ldc(c.de + int64_t(3) * je[k] + q);
+        for (int q = 0; q < 3; ++q) de[k][q] = er.v[q];
       }
       V4<T> A[NVS], G[NVS][2], Hh[NES];
 #pragma unroll
@@ -639,20 +700,26 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
   __syncthreads();
 
   bool bad = false;
-  if (ep) {
+#pragma unroll
+  for (int i = 0; i < NEP; ++i) {
+    const int p = t + 256 * i;
+    const int cmp = p / VPB, vl2 = p % VPB;
+    const int64_t vv = v0 + vl2;
+    if (p >= 12 * VPB || vv >= nowned) continue;
+    const int64_t o = int64_t(cmp) * nv + vv;
     const double rv = sres[vl2][cmp];
     if (mode == 0) {
       dU[o] = rv;
-      bad = !isfinite(rv);
+      bad = bad || !isfinite(rv);
     } else {
-      const double out = rk.a * un + rk.b * (uk + dt * rv);
+      const double out = rk.a * un[i] + rk.b * (uk[i] + dt * rv);
       rk.Unew[o] = out;
       if (Gv_new) {
         const T g = T(out - (cmp < 4 ? gp.wref[cmp] : 0.0));
         if (cmp < 4) reinterpret_cast<T*>(Gv_new)[4 * vv + cmp] = g;
         else reinterpret_cast<T*>(Gg_new)[8 * vv + (cmp - 4)] = g;
       }
-      bad = !isfinite(out);
+      bad = bad || !isfinite(out);
       if (cmp < 4) sres[vl2][cmp] = out;
     }
   }
@@ -824,12 +891,13 @@ hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
                          const V4<T>* H, int mode, double* dU, const RkArgs& rk,
                          V4<T>* Gv_new, V4<T>* Gg_new, int32_t* flag, hipStream_t st) {
   if (nowned == 0) return hipSuccess;
+  constexpr int VPB = 256 / VertexLanes<T>::value;
   const unsigned nb = nblocks(nowned, VPB);
   if (c.dvis)
-    hipLaunchKernelGGL((k_vertex<T, true>), dim3(nb), dim3(VL * VPB), 0, st, nowned, nv, c,
+    hipLaunchKernelGGL((k_vertex<T, true>), dim3(nb), dim3(256), 0, st, nowned, nv, c,
                        gp, Gv, Gg, H, mode, dU, rk, Gv_new, Gg_new, flag);
   else
-    hipLaunchKernelGGL((k_vertex<T, false>), dim3(nb), dim3(VL * VPB), 0, st, nowned, nv, c,
+    hipLaunchKernelGGL((k_vertex<T, false>), dim3(nb), dim3(256), 0, st, nowned, nv, c,
                        gp, Gv, Gg, H, mode, dU, rk, Gv_new, Gg_new, flag);
   return hipGetLastError();
 }
