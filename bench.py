@@ -78,8 +78,17 @@ def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
         done += n
     e_ms, n_e, v_ms, n_v = S.kernel_times()
     info = S.refresh_info()
+    # the float32 edge pass reads a side's 3-node rows only where that side
+    # takes the 3-node branch: count those sides at the initial state
+    bytes_edge = info["bytes_edge_launch"]
+    w3_sides = None
+    if info["bytes_edge_w3_side"] > 0:
+        _, mask, _ = S.edge_states(U0d, want_mask=True, want_flux=False)
+        mask = mask.to(torch.int32)
+        w3_sides = int(((mask & 0xF) != 0).sum().item() + ((mask >> 4) != 0).sum().item())
+        bytes_edge += w3_sides * info["bytes_edge_w3_side"]
     return dict(U=U, wall=wall, edge_ms=e_ms / max(n_e, 1), vertex_ms=v_ms / max(n_v, 1),
-                n_edge=n_e, n_vertex=n_v, bytes_edge=info["bytes_edge_launch"],
+                n_edge=n_e, n_vertex=n_v, bytes_edge=bytes_edge, w3_sides=w3_sides,
                 bytes_vertex=info["bytes_vertex_launch"])
 
 
@@ -283,7 +292,7 @@ def main():
                      "achieved": kern[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": kern[dom]["frac"],
                      "traffic": (measured_traffic(a.workload, "k_vertex<float" if dom == "vertex"
-                                                  else "k_edge<float")
+                                                  else "k_edge1<float")
                                  if main_prec == "fp32" else None)},
         "kernels": kern,
     }

@@ -38,7 +38,7 @@
 #define HFD_VERTEX_WAVES 4    // waves per SIMD of the float32 vertex kernel
 #endif
 #ifndef HFD_EDGE_WAVES
-#define HFD_EDGE_WAVES 3      // waves per SIMD of the float32 edge kernel
+#define HFD_EDGE_WAVES 2      // waves per SIMD of the float32 edge kernel
 #endif
 #ifndef HFD_XCD_REMAP
 #define HFD_XCD_REMAP 1       // 1: contiguous block ranges per XCD
@@ -200,52 +200,93 @@ __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
        {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}}};
 }
 
-// One side's interface state.  Per characteristic component q: the WENO5
-// smoothness indicators and weights (Jiang-Shu, linear weights 1/16, 10/16,
-// 5/16) of the five projected node values cv[q][0..4], the switch, then the
-// Hermite value L_q . hs (hs: the side's 5-node Hermite sum in physical
-// variables; the row is the same for all components) or the omega-weighted
-// 3-node values.  Back-projected with R into `out`; the WENO decisions go to
-// bits 4 s + q of `bits`.
+// Switch of one characteristic component q of side s: the WENO5 smoothness
+// indicators and weights o (Jiang-Shu, linear weights 1/16, 10/16, 5/16) of
+// the five projected node values c[0..4], and the decision: true for the
+// omega-weighted 3-node values, false for the 5-node Hermite value.
 template <class T>
-__device__ inline void side_state(const T cv[4][5], const T hs[4], const T w3[9],
-                                  const Frame<T>& F, const GasParams& gp, int s,
-                                  bool forced, uint8_t fm, T out[4], uint8_t& bits) {
+__device__ inline bool comp_switch(const T c[5], const GasParams& gp, int s, int q,
+                                   bool forced, uint8_t fm, T o[3]) {
   const T eps = T(gp.eps), lo = T(gp.sw_lo), hi = T(gp.sw_hi);
   const T d1 = T(1.0 / 16.0), d2 = T(10.0 / 16.0), d3 = T(5.0 / 16.0);
-  T C[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const T c0 = cv[q][0], c1 = cv[q][1], c2 = cv[q][2], c3 = cv[q][3], c4 = cv[q][4];
-    const T t1 = c0 - T(2) * c1 + c2, t2 = c0 - T(4) * c1 + T(3) * c2;
-    const T t3 = c1 - T(2) * c2 + c3, t4 = c1 - c3;
-    const T t5 = c2 - T(2) * c3 + c4, t6 = T(3) * c2 - T(4) * c3 + c4;
-    const T be1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
-    const T be2 = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
-    const T be3 = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
-    const T a1 = fdiv(d1, (eps + be1) * (eps + be1));
-    const T a2 = fdiv(d2, (eps + be2) * (eps + be2));
-    const T a3 = fdiv(d3, (eps + be3) * (eps + be3));
-    const T sa = a1 + a2 + a3;
-    const T o1 = fdiv(a1, sa), o2 = fdiv(a2, sa), o3 = fdiv(a3, sa);
-    bool weno;
-    if (forced) weno = (fm >> (4 * s + q)) & 1;
-    else if (gp.sw == HFD_SWITCH_PAPER) weno = !(o1 > lo && o1 < hi);
-    else weno = (gp.sw == HFD_SWITCH_WENO_ONLY);
-    T val;
-    if (weno) {
-      val = o1 * (w3[0] * c0 + w3[1] * c1 + w3[2] * c2) +
-            o2 * (w3[3] * c1 + w3[4] * c2 + w3[5] * c3) +
-            o3 * (w3[6] * c2 + w3[7] * c3 + w3[8] * c4);
-    } else {
-      val = F.L[q][0] * hs[0] + F.L[q][1] * hs[1] + F.L[q][2] * hs[2] + F.L[q][3] * hs[3];
-    }
-    C[q] = val;
-    bits |= uint8_t(weno ? 1 : 0) << (4 * s + q);
-  }
+  const T t1 = c[0] - T(2) * c[1] + c[2], t2 = c[0] - T(4) * c[1] + T(3) * c[2];
+  const T t3 = c[1] - T(2) * c[2] + c[3], t4 = c[1] - c[3];
+  const T t5 = c[2] - T(2) * c[3] + c[4], t6 = T(3) * c[2] - T(4) * c[3] + c[4];
+  const T be1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
+  const T be2 = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
+  const T be3 = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
+  const T a1 = fdiv(d1, (eps + be1) * (eps + be1));
+  const T a2 = fdiv(d2, (eps + be2) * (eps + be2));
+  const T a3 = fdiv(d3, (eps + be3) * (eps + be3));
+  const T sa = a1 + a2 + a3;
+  o[0] = fdiv(a1, sa);
+  o[1] = fdiv(a2, sa);
+  o[2] = fdiv(a3, sa);
+  if (forced) return (fm >> (4 * s + q)) & 1;
+  if (gp.sw == HFD_SWITCH_PAPER) return !(o[0] > lo && o[0] < hi);
+  return gp.sw == HFD_SWITCH_WENO_ONLY;
+}
+
+// Interface value of one characteristic component: the omega-weighted 3-node
+// values (w3: the side's three 3-node rows) or the Hermite value L_q . hs
+// (hs: the side's 5-node Hermite sum in physical variables; the row is the
+// same for all components).
+template <class T>
+__device__ inline T comp_value(bool weno, const T c[5], const T o[3], const T w3[9],
+                               const T Lq[4], const T hs[4]) {
+  if (weno)
+    return o[0] * (w3[0] * c[0] + w3[1] * c[1] + w3[2] * c[2]) +
+           o[1] * (w3[3] * c[1] + w3[4] * c[2] + w3[5] * c[3]) +
+           o[2] * (w3[6] * c[2] + w3[7] * c[3] + w3[8] * c[4]);
+  return Lq[0] * hs[0] + Lq[1] * hs[1] + Lq[2] * hs[2] + Lq[3] * hs[3];
+}
+
+template <class T>
+__device__ inline void back_project(const Frame<T>& F, const T C[4], T out[4]) {
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     out[r] = F.R[r][0] * C[0] + F.R[r][1] * C[1] + F.R[r][2] * C[2] + F.R[r][3] * C[3];
+}
+
+// One side's decisions (bits 4 s + q) and weights, for a state finished by
+// side_finish once the side's 3-node rows are known to be needed.
+template <class T>
+__device__ inline uint8_t side_weights(const T cv[4][5], const GasParams& gp, int s,
+                                       bool forced, uint8_t fm, T o[4][3]) {
+  uint8_t bits = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    bits |= uint8_t(comp_switch<T>(cv[q], gp, s, q, forced, fm, o[q]) ? 1 : 0) << (4 * s + q);
+  return bits;
+}
+
+template <class T>
+__device__ inline void side_finish(const T cv[4][5], const T hs[4], const T w3[9],
+                                   const T o[4][3], uint8_t bits, int s, const Frame<T>& F,
+                                   T out[4]) {
+  T C[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    C[q] = comp_value<T>((bits >> (4 * s + q)) & 1, cv[q], o[q], w3, F.L[q], hs);
+  back_project<T>(F, C, out);
+}
+
+// Both in one pass per component (fewer live values; w3 already loaded).
+template <class T>
+__device__ inline uint8_t side_state(const T cv[4][5], const T hs[4], const T w3[9],
+                                     const Frame<T>& F, const GasParams& gp, int s,
+                                     bool forced, uint8_t fm, T out[4]) {
+  uint8_t bits = 0;
+  T C[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T o[3];
+    const bool weno = comp_switch<T>(cv[q], gp, s, q, forced, fm, o);
+    C[q] = comp_value<T>(weno, cv[q], o, w3, F.L[q], hs);
+    bits |= uint8_t(weno ? 1 : 0) << (4 * s + q);
+  }
+  back_project<T>(F, C, out);
+  return bits;
 }
 
 // Rusanov flux along n of the two interface states (perturbation form).
@@ -316,15 +357,14 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
   for (int t = 0; t < 6; ++t) id[t] = *at(c.stg, t * ne + e0, li);
   const T nx = row(c.n, 0), ny = row(c.n, 1);
-  T w5[2][15], w3[2][9];
+  const bool forced = force != nullptr;
+  T w5[2][15];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
 #pragma unroll
     for (int j = 0; j < 15; ++j) w5[s][j] = row(c.w5, s * 15 + j);
-#pragma unroll
-    for (int j = 0; j < 9; ++j) w3[s][j] = row(c.w3, s * 9 + j);
   }
-  const uint8_t fm = force ? force[e] : uint8_t(0);
+  const uint8_t fm = forced ? force[e] : uint8_t(0);
   T w[6][4], wx[6][4], wy[6][4];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
@@ -350,7 +390,8 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
       hs[1][q] += w5[1][3 * p] * w[n][q] + w5[1][3 * p + 1] * wx[n][q] + w5[1][3 * p + 2] * wy[n][q];
     }
   }
-  // characteristic projection of the six node values
+  // characteristic projection of the six node values; side 0 takes nodes
+  // 0..4, side 1 nodes 5..1
   T cv[4][6];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
@@ -358,20 +399,28 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     for (int q = 0; q < 4; ++q)
       cv[q][t] = F.L[q][0] * w[t][0] + F.L[q][1] * w[t][1] + F.L[q][2] * w[t][2] + F.L[q][3] * w[t][3];
   }
+  // per side: decisions, then the 3-node rows only if some component takes
+  // that branch, then the interface state
   uint8_t bits = 0;
-  T wl[4], wr[4], c5[4][5];
+  T wl[4], wr[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int s = 0; s < 2; ++s) {
+    T c5[4][5], o[4][3], w3[9];
 #pragma unroll
-    for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][p];
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][s == 0 ? p : 5 - p];
+    }
+    const uint8_t b = side_weights<T>(c5, gp, s, forced, fm, o);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) w3[j] = T(0);
+    if (b) {
+#pragma unroll
+      for (int j = 0; j < 9; ++j) w3[j] = row(c.w3, s * 9 + j);
+    }
+    side_finish<T>(c5, hs[s], w3, o, b, s, F, s == 0 ? wl : wr);
+    bits |= b;
   }
-  side_state<T>(c5, hs[0], w3[0], F, gp, 0, force != nullptr, fm, wl, bits);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-#pragma unroll
-    for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][5 - p];
-  }
-  side_state<T>(c5, hs[1], w3[1], F, gp, 1, force != nullptr, fm, wr, bits);
   T h[4];
   rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, true, true);
@@ -404,6 +453,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
   for (int t = 0; t < 5; ++t)  // (the row offset given to at() must be wave-uniform)
     id[t] = s == 0 ? *at(c.stg, t * ne + e0, li) : *at(c.stg, (5 - t) * ne + e0, li);
+  const bool forced = force != nullptr;
   T w5[15];
 #pragma unroll
   for (int j = 0; j < 15; ++j) w5[j] = s == 0 ? row(c.w5, j) : row(c.w5, 15 + j);
@@ -420,12 +470,13 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
       hs[q] += w5[3 * j] * w[q] + w5[3 * j + 1] * wx[q] + w5[3 * j + 2] * wy[q];
     }
   }
+  // (unconditional here: a late conditional load costs the float64 kernel
+  // more registers than its 2 waves per SIMD allow)
   T w3[9];
 #pragma unroll
   for (int j = 0; j < 9; ++j) w3[j] = s == 0 ? row(c.w3, j) : row(c.w3, 9 + j);
-  uint8_t bits = 0;
   T wm[4];
-  side_state<T>(cv, hs, w3, F, gp, s, force != nullptr, fm, wm, bits);
+  uint8_t bits = side_state<T>(cv, hs, w3, F, gp, s, forced, fm, wm);
   T wl[4], wr[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {

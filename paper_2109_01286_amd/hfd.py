@@ -48,6 +48,7 @@ class Info(ctypes.Structure):
                 ("rank_hist", ctypes.c_int64 * 16), ("w3_truncated", ctypes.c_int64),
                 ("bytes_edge_launch", ctypes.c_double),
                 ("bytes_vertex_launch", ctypes.c_double),
+                ("bytes_edge_w3_side", ctypes.c_double),
                 ("setup_ms", ctypes.c_double * 4)]
 
     def as_dict(self):

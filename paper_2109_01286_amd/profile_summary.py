@@ -53,7 +53,7 @@ def main(stats_dir, fetch_dir, write_dir, out, command):
               "| kernel | launches | fetch (GB) | write (GB) | total (GB) |", "|---|---|---|---|---|"]
     traffic = {}
     for k in sorted(F, key=lambda k: -sum(F[k])):
-        if k[0].startswith(("k_vertex", "k_edge<", "k_to_gather")):
+        if k[0].startswith(("k_vertex", "k_edge1<", "k_edge2<", "k_to_gather")):
             f = sum(F[k]) / len(F[k]) * 1024 * ff
             w = sum(W[k]) / len(W[k]) * 1024 * fw
             lines.append(f"| `{k[0]}` | {len(F[k])} | {f / 1e9:.3f} | {w / 1e9:.3f} | {(f + w) / 1e9:.3f} |")

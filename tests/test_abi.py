@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     # hfd_opts: 14 doubles + 8 int32; hfd_info: 8 int64 + 2 int32 + 17 int64 + 6 double
     assert ctypes.sizeof(hfd.Opts) == 14 * 8 + 8 * 4
-    assert ctypes.sizeof(hfd.Info) == 8 * 8 + 2 * 4 + 17 * 8 + 6 * 8
+    assert ctypes.sizeof(hfd.Info) == 8 * 8 + 2 * 4 + 17 * 8 + 7 * 8
 
 
 def test_default_opts():
