@@ -35,7 +35,8 @@ def _agg(path):
 def main(stats_dir, fetch_dir, write_dir, out, command):
     lines = ["# rocprofv3 summary: shock-vortex 2049 x 1025 (2.1 M owned vertices, 6.33 M active edges)", "",
              "Commands (on the MI355X box, from the repository root, `export TMPDIR=/tmp`):", "",
-             "    " + command, "", "## Kernel statistics (`--kernel-trace --stats`)", "",
+             *["    " + c.strip() for c in command.splitlines() if c.strip()], "",
+             "## Kernel statistics (`--kernel-trace --stats`)", "",
              "| kernel | calls | average (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
     rows = list(csv.DictReader(open(os.path.join(stats_dir, "run_kernel_stats.csv"))))
     for r in rows[:14]:
