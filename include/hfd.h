@@ -246,6 +246,21 @@ hfd_status hfd_adjoint_residual(hfd_ctx* ctx, const double* U, const double* lam
 hfd_status hfd_rk_step_adjoint(hfd_ctx* ctx, const double* U_n, double dt,
                                const double* lam_np1, double* lam_n, void* stream);
 
+/* One step of hfd_rk_step in float64 (whatever the context's precision)
+ * that also returns its two intermediate stages (end of Section 2.3):
+ * U1 = U + dt R(U), U2 = 3/4 U + 1/4 (U1 + dt R(U1)), device [12][nv]
+ * (owned rows; ghost rows unspecified).  For hfd_rk_step_adjoint_stages,
+ * which then need not recompute them. */
+hfd_status hfd_rk_step_stages(hfd_ctx* ctx, double* U, double dt, double* U1, double* U2,
+                              void* stream);
+
+/* hfd_rk_step_adjoint with the step's stages U1, U2 given (as returned by
+ * hfd_rk_step_stages from U_n) instead of recomputed.  Same result. */
+hfd_status hfd_rk_step_adjoint_stages(hfd_ctx* ctx, const double* U_n, const double* U1,
+                                      const double* U2, double dt, const double* lam_np1,
+                                      double* lam_n, void* stream);
+
+
 /* Per-kernel timing, for measurement.  With timing on, every edge pass and
  * every vertex pass launched by hfd_residual / hfd_rk_step* is bracketed by
  * two HIP events recorded on the call's stream.  hfd_kernel_times

@@ -4,9 +4,10 @@ whose backward runs the library's hand-written adjoint step
 
 Forward: ``nsteps`` steps of fixed size ``dt`` from U0, keeping the state
 every ``ckpt_every`` steps (float64, device).  Backward: segments in reverse;
-each segment is recomputed from its checkpoint (its step inputs are kept for
-the segment only), then its steps are reversed.  Memory: nsteps/ckpt_every +
-ckpt_every states; work: one extra forward pass.
+each segment is recomputed from its checkpoint, keeping every step's input
+and its two Runge-Kutta stages for the segment only, then its steps are
+reversed from those.  Memory: nsteps/ckpt_every + 3 ckpt_every states; work:
+one extra forward pass.
 """
 from __future__ import annotations
 
@@ -34,16 +35,19 @@ class RKSteps(torch.autograd.Function):
         S, dt, ce, n = ctx.solver, ctx.dt, ctx.ckpt_every, ctx.nsteps
         lam = gU.detach().contiguous().clone()
         nxt = torch.empty_like(lam)
+        # (input, stage 1, stage 2) of every step of a segment, one buffer
+        # for all segments
+        buf = torch.empty((min(ce, n), 3) + tuple(lam.shape), dtype=lam.dtype,
+                          device=lam.device)
         for seg in reversed(range(len(ctx.ckpts))):
             k0 = seg * ce
             k1 = min(n, k0 + ce)
-            states = [ctx.ckpts[seg].clone()]
-            for _ in range(k0, k1 - 1):
-                U = states[-1].clone()
-                S.rk_step(U, dt)
-                states.append(U)
-            for U in reversed(states):
-                S.rk_step_adjoint(U, dt, lam, out=nxt)
+            U = ctx.ckpts[seg].clone()
+            for i in range(k1 - k0):
+                buf[i, 0].copy_(U)
+                S.rk_step_stages(U, dt, buf[i, 1], buf[i, 2])
+            for i in reversed(range(k1 - k0)):
+                S.rk_step_adjoint_stages(buf[i, 0], buf[i, 1], buf[i, 2], dt, lam, out=nxt)
                 lam, nxt = nxt, lam
         ctx.ckpts = None
         return lam, None, None, None, None

@@ -9,6 +9,7 @@
 // Its transpose applied to lambda is computed in three deterministic
 // gathers (no atomics), using transposed maps built at first use:
 //   k_adj_edge_flux:  lambda_h(m) = -sum_{(v,s): m in M(v)} de[s] . lambda(v)
+//                     (de and dv are read from copies in the transposed order)
 //   k_adj_edge:       recompute the edge pass and run it backwards, giving
 //                     the contribution of h_e to the 72 data (w, w_x, w_y at
 //                     the six stencil nodes) of edge e
@@ -22,6 +23,10 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+
+#ifndef ADJ_EDGE_WAVES
+#define ADJ_EDGE_WAVES 2  // waves per SIMD of the edge reverse (register budget)
+#endif
 
 namespace hfd {
 namespace {
@@ -77,336 +82,553 @@ __device__ inline void cart_flux_n(const double w[4], double nx, double ny, doub
   *sp = fabs(un) + sqrt(gam * p * ir);
 }
 
+// x, opaque to the optimiser (no code): values derived from it after this
+// point are recomputed rather than reused from before.
+template <class T>
+__device__ inline T launder(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // lambda_h(m) = - sum over (v, s) of de[s] . lambda(v)
 // ---------------------------------------------------------------------------
-__global__ void k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr,
-                                const int32_t* __restrict__ tv, const int32_t* __restrict__ ts,
-                                const double* __restrict__ de, const V4<double>* __restrict__ Lv,
-                                const V4<double>* __restrict__ Lg, V4<double>* __restrict__ lh) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= ne) return;
+// Sum over the 8 lanes of a group, every lane gets it: the half-row mirror
+// and the two quad swaps pair disjoint lane sets at each stage.
+__device__ inline double sum8(double x) {
+  x += dpp_mov<0x141>(x);
+  x += dpp_mov<0x4E>(x);
+  x += dpp_mov<0xB1>(x);
+  return x;
+}
+
+// 8 lanes per edge stride over the edge's (v, s) entries, two per lane and
+// batch with all loads in flight; the coefficients are in the transposed
+// order (de_t, contiguous per edge).  Every active edge has an entry, so
+// k1 - 1 is one: lanes past the end load it again with zero weight.
+__global__ void __launch_bounds__(256)
+k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __restrict__ tv,
+                const double* __restrict__ de_t, const V4<double>* __restrict__ Lv,
+                const V4<double>* __restrict__ Lg, V4<double>* __restrict__ lh) {
+  const int64_t m = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 8;
+  const int sub = threadIdx.x & 7;
   double a[4] = {0, 0, 0, 0};
-  for (int k = tptr[m]; k < tptr[m + 1]; ++k) {
-    const int64_t v = tv[k];
-    const int64_t s = ts[k];
-    const double d0 = de[3 * s], dx = de[3 * s + 1], dy = de[3 * s + 2];
-    const V4<double> l0 = Lv[v], lx = Lg[2 * v], ly = Lg[2 * v + 1];
-    a[0] -= d0 * l0.x + dx * lx.x + dy * ly.x;
-    a[1] -= d0 * l0.y + dx * lx.y + dy * ly.y;
-    a[2] -= d0 * l0.z + dx * lx.z + dy * ly.z;
-    a[3] -= d0 * l0.w + dx * lx.w + dy * ly.w;
+  if (m < ne) {
+    const int k0 = tptr[m], k1 = tptr[m + 1];
+    for (int b = k0 + sub; b < k1; b += 16) {
+      int kk[2];
+      bool ok[2];
+      for (int i = 0; i < 2; ++i) {
+        ok[i] = b + 8 * i < k1;
+        kk[i] = ok[i] ? b + 8 * i : k1 - 1;
+      }
+      int v[2];
+      double d[2][3];
+      for (int i = 0; i < 2; ++i) {
+        v[i] = tv[kk[i]];
+        for (int q = 0; q < 3; ++q) d[i][q] = de_t[3 * int64_t(kk[i]) + q];
+      }
+      V4<double> l0[2], lx[2], ly[2];
+      for (int i = 0; i < 2; ++i) {
+        l0[i] = Lv[v[i]];
+        lx[i] = Lg[2 * int64_t(v[i])];
+        ly[i] = Lg[2 * int64_t(v[i]) + 1];
+      }
+      for (int i = 0; i < 2; ++i) {
+        const double d0 = ok[i] ? d[i][0] : 0.0, dx = ok[i] ? d[i][1] : 0.0,
+                     dy = ok[i] ? d[i][2] : 0.0;
+        a[0] -= d0 * l0[i].x + dx * lx[i].x + dy * ly[i].x;
+        a[1] -= d0 * l0[i].y + dx * lx[i].y + dy * ly[i].y;
+        a[2] -= d0 * l0[i].z + dx * lx[i].z + dy * ly[i].z;
+        a[3] -= d0 * l0[i].w + dx * lx[i].w + dy * ly[i].w;
+      }
+    }
   }
-  lh[m] = V4<double>{a[0], a[1], a[2], a[3]};
+  for (int q = 0; q < 4; ++q) a[q] = sum8(a[q]);
+  if (m < ne && sub == 0) lh[m] = V4<double>{a[0], a[1], a[2], a[3]};
 }
 
 // ---------------------------------------------------------------------------
 // Edge pass forward + reverse: out[e][j][12] = d h_e / d(data of node j)^T lh
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256, 1)
+// Two lanes per edge: lane s recomputes side s (left: nodes 0..4, right:
+// nodes 5..1, at positions t = 0..4) and runs it backwards; both lanes hold
+// the Roe average and the flux.  The pair exchanges the interface states,
+// the four scalar gradients of the Roe state (u, v, H, c) and the
+// contributions to the nodes both sides share, then lane 0 writes nodes
+// 0, 1, 2 and lane 1 nodes 5, 4, 3 (positions 0, 1, 2 of each lane).
+__global__ void __launch_bounds__(256, ADJ_EDGE_WAVES)
 k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __restrict__ Gv,
            const V4<double>* __restrict__ Gg, const uint8_t* __restrict__ force,
            const V4<double>* __restrict__ lh, double* __restrict__ out) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+  const int s = threadIdx.x & 1;
+  const int64_t e = int64_t(blockIdx.x) * (blockDim.x / 2) + threadIdx.x / 2;
+  if (e >= ne) return;  // both lanes of a pair leave together
   const double gam = gp.gamma, gm1 = gam - 1.0;
-  int id[6];
-  for (int t = 0; t < 6; ++t) id[t] = c.stg[t * ne + e];
   const double nx = c.n[e], ny = c.n[ne + e];
-  double W[6][4], X[6][4], Y[6][4];
-  for (int j = 0; j < 6; ++j) {
-    const V4<double> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
-    W[j][0] = a.x; W[j][1] = a.y; W[j][2] = a.z; W[j][3] = a.w;
-    X[j][0] = bx.x; X[j][1] = bx.y; X[j][2] = bx.z; X[j][3] = bx.w;
-    Y[j][0] = by.x; Y[j][1] = by.y; Y[j][2] = by.z; Y[j][3] = by.w;
-  }
-  // ---- forward: Roe average --------------------------------------------------
-  const double* A = W[2];
-  const double* B = W[3];
-  const double ra = A[0], rb = B[0];
-  const double sa = sqrt(ra), sb = sqrt(rb), D = sa + sb;
-  const double pa = gm1 * (A[3] - 0.5 * (A[1] * A[1] + A[2] * A[2]) / ra);
-  const double pb = gm1 * (B[3] - 0.5 * (B[1] * B[1] + B[2] * B[2]) / rb);
-  const double Pa = A[1] / sa, Pb = B[1] / sb, Qa = A[2] / sa, Qb = B[2] / sb;
-  const double Ka = (A[3] + pa) / sa, Kb = (B[3] + pb) / sb;
-  const double u = (Pa + Pb) / D, v = (Qa + Qb) / D, H = (Ka + Kb) / D;
-  const double q2 = u * u + v * v;
-  const double cc = sqrt(gm1 * (H - 0.5 * q2));
-  const double un = u * nx + v * ny, ut = -u * ny + v * nx;
-  const double b1 = gm1 / (cc * cc), b2 = 0.5 * b1 * q2, ic = 1.0 / cc;
-  const double L[4][4] = {
-      {0.5 * (b2 + un * ic), -0.5 * (b1 * u + nx * ic), -0.5 * (b1 * v + ny * ic), 0.5 * b1},
-      {1.0 - b2, b1 * u, b1 * v, -b1},
-      {0.5 * (b2 - un * ic), -0.5 * (b1 * u - nx * ic), -0.5 * (b1 * v - ny * ic), 0.5 * b1},
-      {-ut, -ny, nx, 0.0}};
-  const double R[4][4] = {{1.0, 1.0, 1.0, 0.0},
-                          {u - cc * nx, u, u + cc * nx, -ny},
-                          {v - cc * ny, v, v + cc * ny, nx},
-                          {H - un * cc, 0.5 * q2, H + un * cc, ut}};
+  const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
+  int id[5];
+  for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
   const double eps = gp.eps;
   const double dw[3] = {1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0};
   const uint8_t fm = force ? force[e] : uint8_t(0);
-  double wm[2][4], C[2][4], hs[2][4];
-  double cv[2][4][5];
-  bool weno[2][4];
-  double om[2][4][3], Sk[2][4][3];
-  for (int s = 0; s < 2; ++s) {
-    int ix[5];
-    for (int t = 0; t < 5; ++t) ix[t] = s == 0 ? t : 5 - t;
-    for (int q = 0; q < 4; ++q) hs[s][q] = 0.0;
-    for (int t = 0; t < 5; ++t) {
-      const double w0 = c.w5[int64_t(s * 15 + 3 * t) * ne + e];
-      const double w1 = c.w5[int64_t(s * 15 + 3 * t + 1) * ne + e];
-      const double w2 = c.w5[int64_t(s * 15 + 3 * t + 2) * ne + e];
-      for (int q = 0; q < 4; ++q) {
-        cv[s][q][t] = L[q][0] * W[ix[t]][0] + L[q][1] * W[ix[t]][1] + L[q][2] * W[ix[t]][2] +
-                      L[q][3] * W[ix[t]][3];
-        hs[s][q] += w0 * W[ix[t]][q] + w1 * X[ix[t]][q] + w2 * Y[ix[t]][q];
+  // Roe average of nodes 2 and 3 and the eigenvector matrices L (rows), R
+  auto roe = [&](double A[4], double B[4], double& sa, double& sb, double& D, double& pa,
+                 double& pb, double& u, double& v, double& H, double& cc) {
+    const V4<double> a = Gv[launder(ia)], b = Gv[launder(ib)];
+    A[0] = a.x; A[1] = a.y; A[2] = a.z; A[3] = a.w;
+    B[0] = b.x; B[1] = b.y; B[2] = b.z; B[3] = b.w;
+    const double ra = A[0], rb = B[0];
+    sa = sqrt(ra);
+    sb = sqrt(rb);
+    D = sa + sb;
+    pa = gm1 * (A[3] - 0.5 * (A[1] * A[1] + A[2] * A[2]) / ra);
+    pb = gm1 * (B[3] - 0.5 * (B[1] * B[1] + B[2] * B[2]) / rb);
+    const double Pa = A[1] / sa, Pb = B[1] / sb, Qa = A[2] / sa, Qb = B[2] / sb;
+    const double Ka = (A[3] + pa) / sa, Kb = (B[3] + pb) / sb;
+    u = (Pa + Pb) / D;
+    v = (Qa + Qb) / D;
+    H = (Ka + Kb) / D;
+    cc = sqrt(gm1 * (H - 0.5 * (u * u + v * v)));
+  };
+  auto eig = [&](double u, double v, double H, double cc, double L[4][4], double R[4][4]) {
+    const double q2 = u * u + v * v;
+    const double un = u * nx + v * ny, ut = -u * ny + v * nx;
+    const double b1 = gm1 / (cc * cc), b2 = 0.5 * b1 * q2, ic = 1.0 / cc;
+    const double Lv[4][4] = {
+        {0.5 * (b2 + un * ic), -0.5 * (b1 * u + nx * ic), -0.5 * (b1 * v + ny * ic), 0.5 * b1},
+        {1.0 - b2, b1 * u, b1 * v, -b1},
+        {0.5 * (b2 - un * ic), -0.5 * (b1 * u - nx * ic), -0.5 * (b1 * v - ny * ic), 0.5 * b1},
+        {-ut, -ny, nx, 0.0}};
+    const double Rv[4][4] = {{1.0, 1.0, 1.0, 0.0},
+                             {u - cc * nx, u, u + cc * nx, -ny},
+                             {v - cc * ny, v, v + cc * ny, nx},
+                             {H - un * cc, 0.5 * q2, H + un * cc, ut}};
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        L[i][j] = Lv[i][j];
+        R[i][j] = Rv[i][j];
       }
+  };
+  // this side's node values and coefficient rows.  The indices and the base
+  // pointers pass through launder() at every use, so that the compiler
+  // recomputes the addresses there instead of keeping them in registers.
+  const double* w5p = c.w5 + int64_t(s * 15) * ne + e;
+  const double* w3p = c.w3 + int64_t(s * 9) * ne + e;
+  auto load_W = [&](double W[5][4]) {
+    for (int t = 0; t < 5; ++t) {
+      const V4<double> a = Gv[launder(id[t])];
+      W[t][0] = a.x; W[t][1] = a.y; W[t][2] = a.z; W[t][3] = a.w;
+    }
+  };
+  auto load_w5 = [&](double w5[5][3]) {
+    const double* b = launder(w5p);
+    for (int t = 0; t < 5; ++t)
+      for (int k = 0; k < 3; ++k) w5[t][k] = b[int64_t(3 * t + k) * ne];
+  };
+  auto load_w3 = [&](double w3[9]) {
+    const double* b = launder(w3p);
+    for (int j = 0; j < 9; ++j) w3[j] = b[int64_t(j) * ne];
+  };
+  // projected node values of component q
+  auto proj = [&](const double L[4][4], const double W[5][4], int q, double cq[5]) {
+    for (int t = 0; t < 5; ++t)
+      cq[t] = L[q][0] * W[t][0] + L[q][1] * W[t][1] + L[q][2] * W[t][2] + L[q][3] * W[t][3];
+  };
+  // smoothness indicators, WENO weights and 3-node values of component q
+  auto weno_parts = [&](const double w3[9], const double cq[5], double be[3], double al[3],
+                        double& sal, double om[3], double Sk[3]) {
+    const double t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
+    const double t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
+    const double t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
+    be[0] = 13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2;
+    be[1] = 13.0 / 12.0 * t3 * t3 + 0.25 * t4 * t4;
+    be[2] = 13.0 / 12.0 * t5 * t5 + 0.25 * t6 * t6;
+    sal = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      al[k] = dw[k] / ((eps + be[k]) * (eps + be[k]));
+      sal += al[k];
+    }
+    for (int k = 0; k < 3; ++k) om[k] = al[k] / sal;
+    for (int k = 0; k < 3; ++k) {
+      double sk = 0.0;
+      for (int t = 0; t < 3; ++t) sk += w3[3 * k + t] * cq[k + t];
+      Sk[k] = sk;
+    }
+  };
+
+  // ---- forward ---------------------------------------------------------------------
+  bool weno[4];
+  double hs[4] = {0, 0, 0, 0}, C[4], wm[4], wl[4], wr[4], sl, sr, lam;
+  {
+    double A[4], B[4], sa, sb, D, pa, pb, u, v, H, cc, L[4][4], R[4][4];
+    roe(A, B, sa, sb, D, pa, pb, u, v, H, cc);
+    eig(u, v, H, cc, L, R);
+    double W[5][4], w5[5][3], w3[9];
+    load_W(W);
+    load_w5(w5);
+    load_w3(w3);
+    for (int t = 0; t < 5; ++t) {
+      const V4<double> bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
+      const double X[4] = {bx.x, bx.y, bx.z, bx.w}, Y[4] = {by.x, by.y, by.z, by.w};
+      for (int q = 0; q < 4; ++q) hs[q] += w5[t][0] * W[t][q] + w5[t][1] * X[q] + w5[t][2] * Y[q];
     }
     for (int q = 0; q < 4; ++q) {
-      const double* cq = cv[s][q];
-      const double t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
-      const double t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
-      const double t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
-      const double be[3] = {13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2,
-                            13.0 / 12.0 * t3 * t3 + 0.25 * t4 * t4,
-                            13.0 / 12.0 * t5 * t5 + 0.25 * t6 * t6};
-      double al[3], sal = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        al[k] = dw[k] / ((eps + be[k]) * (eps + be[k]));
-        sal += al[k];
-      }
-      for (int k = 0; k < 3; ++k) om[s][q][k] = al[k] / sal;
+      double cq[5], be[3], al[3], sal, om[3], Sk[3];
+      proj(L, W, q, cq);
+      weno_parts(w3, cq, be, al, sal, om, Sk);
       bool wq;
       if (force) wq = (fm >> (4 * s + q)) & 1;
-      else if (gp.sw == HFD_SWITCH_PAPER) wq = !(om[s][q][0] > gp.sw_lo && om[s][q][0] < gp.sw_hi);
+      else if (gp.sw == HFD_SWITCH_PAPER) wq = !(om[0] > gp.sw_lo && om[0] < gp.sw_hi);
       else wq = (gp.sw == HFD_SWITCH_WENO_ONLY);
-      weno[s][q] = wq;
-      for (int k = 0; k < 3; ++k) {
-        double sk = 0.0;
-        for (int t = 0; t < 3; ++t) sk += c.w3[int64_t(s * 9 + 3 * k + t) * ne + e] * cq[k + t];
-        Sk[s][q][k] = sk;
-      }
-      C[s][q] = wq ? om[s][q][0] * Sk[s][q][0] + om[s][q][1] * Sk[s][q][1] + om[s][q][2] * Sk[s][q][2]
-                   : L[q][0] * hs[s][0] + L[q][1] * hs[s][1] + L[q][2] * hs[s][2] + L[q][3] * hs[s][3];
+      weno[q] = wq;
+      C[q] = wq ? om[0] * Sk[0] + om[1] * Sk[1] + om[2] * Sk[2]
+                : L[q][0] * hs[0] + L[q][1] * hs[1] + L[q][2] * hs[2] + L[q][3] * hs[3];
     }
-    for (int r = 0; r < 4; ++r)
-      wm[s][r] = R[r][0] * C[s][0] + R[r][1] * C[s][1] + R[r][2] * C[s][2] + R[r][3] * C[s][3];
+    for (int r = 0; r < 4; ++r) wm[r] = R[r][0] * C[0] + R[r][1] * C[1] + R[r][2] * C[2] + R[r][3] * C[3];
+    for (int r = 0; r < 4; ++r) {
+      const double o = dpp_mov<0xB1>(wm[r]);  // the partner lane's state
+      wl[r] = s == 0 ? wm[r] : o;
+      wr[r] = s == 0 ? o : wm[r];
+    }
+    double fl[4], fr[4];
+    cart_flux_n(wl, nx, ny, gm1, fl, &sl, gam);
+    cart_flux_n(wr, nx, ny, gm1, fr, &sr, gam);
+    lam = sl >= sr ? sl : sr;
   }
-  double fl[4], fr[4], sl, sr;
-  cart_flux_n(wm[0], nx, ny, gm1, fl, &sl, gam);
-  cart_flux_n(wm[1], nx, ny, gm1, fr, &sr, gam);
-  const double lam = sl >= sr ? sl : sr;
+  // The reverse reads the node values and coefficient rows again (cache hits)
+  // and recomputes the Roe state where it needs them, instead of holding
+  // them in registers through the forward pass: the compiler barriers keep
+  // it from reusing the forward's copies.
+  asm volatile("" ::: "memory");
+  double u, v, H, cc, L[4][4], R[4][4];
+  {
+    double A[4], B[4], sa, sb, D, pa, pb;
+    roe(A, B, sa, sb, D, pa, pb, u, v, H, cc);
+  }
+  eig(u, v, H, cc, L, R);
+  const double q2 = u * u + v * v;
+  const double un = u * nx + v * ny;
+  const double b1 = gm1 / (cc * cc), b2 = 0.5 * b1 * q2, ic = 1.0 / cc;
 
-  // ---- reverse ---------------------------------------------------------------
+  // ---- reverse: Rusanov flux -> this side's state ------------------------------------
   const V4<double> g4 = lh[e];
   const double gh[4] = {g4.x, g4.y, g4.z, g4.w};
-  double gw[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  double glam = 0.0;
+  double glam = 0.0, gw[4];
   for (int q = 0; q < 4; ++q) {
-    glam -= 0.5 * gh[q] * (wm[1][q] - wm[0][q]);
-    gw[0][q] += 0.5 * lam * gh[q];
-    gw[1][q] -= 0.5 * lam * gh[q];
+    glam -= 0.5 * gh[q] * (wr[q] - wl[q]);
+    gw[q] = (s == 0 ? 0.5 : -0.5) * lam * gh[q];
   }
   const double half[4] = {0.5 * gh[0], 0.5 * gh[1], 0.5 * gh[2], 0.5 * gh[3]};
-  flux_jac_t(wm[0], nx, ny, gm1, half, gw[0]);
-  flux_jac_t(wm[1], nx, ny, gm1, half, gw[1]);
-  {
+  flux_jac_t(wm, nx, ny, gm1, half, gw);
+  if ((sl >= sr ? 0 : 1) == s) {
     double ds[4];
-    const int act = sl >= sr ? 0 : 1;
-    speed_grad(wm[act], nx, ny, gam, ds);
-    for (int k = 0; k < 4; ++k) gw[act][k] += glam * ds[k];
+    speed_grad(wm, nx, ny, gam, ds);
+    for (int k = 0; k < 4; ++k) gw[k] += glam * ds[k];
   }
-  double gL[4][4] = {}, gR[4][4] = {};
-  double gW[6][4] = {}, gX[6][4] = {}, gY[6][4] = {};
-  for (int s = 0; s < 2; ++s) {
-    int ix[5];
-    for (int t = 0; t < 5; ++t) ix[t] = s == 0 ? t : 5 - t;
-    double gC[4];
-    for (int q = 0; q < 4; ++q) {
-      gC[q] = R[0][q] * gw[s][0] + R[1][q] * gw[s][1] + R[2][q] * gw[s][2] + R[3][q] * gw[s][3];
-      for (int r = 0; r < 4; ++r) gR[r][q] += gw[s][r] * C[s][q];
-    }
-    double ghs[4] = {0, 0, 0, 0};
-    double gcv[4][5] = {};
-    for (int q = 0; q < 4; ++q) {
-      if (!weno[s][q]) {
-        for (int k = 0; k < 4; ++k) {
-          gL[q][k] += gC[q] * hs[s][k];
-          ghs[k] += gC[q] * L[q][k];
-        }
-        continue;
-      }
-      const double* cq = cv[s][q];
-      double gS[3], gom[3];
-      for (int k = 0; k < 3; ++k) {
-        gS[k] = gC[q] * om[s][q][k];
-        gom[k] = gC[q] * Sk[s][q][k];
-      }
-      for (int k = 0; k < 3; ++k)
-        for (int t = 0; t < 3; ++t)
-          gcv[q][k + t] += gS[k] * c.w3[int64_t(s * 9 + 3 * k + t) * ne + e];
-      // omega = alpha / sum(alpha), alpha = d / (eps + beta)^2
-      const double t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
-      const double t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
-      const double t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
-      const double be[3] = {13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2,
-                            13.0 / 12.0 * t3 * t3 + 0.25 * t4 * t4,
-                            13.0 / 12.0 * t5 * t5 + 0.25 * t6 * t6};
-      double al[3], sal = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        al[k] = dw[k] / ((eps + be[k]) * (eps + be[k]));
-        sal += al[k];
-      }
-      double dot = 0.0;
-      for (int k = 0; k < 3; ++k) dot += gom[k] * om[s][q][k];
-      double gbe[3];
-      for (int k = 0; k < 3; ++k) {
-        const double gal = (gom[k] - dot) / sal;
-        gbe[k] = -2.0 * gal * al[k] / (eps + be[k]);
-      }
-      const double gt1 = gbe[0] * (13.0 / 6.0) * t1, gt2 = gbe[0] * 0.5 * t2;
-      const double gt3 = gbe[1] * (13.0 / 6.0) * t3, gt4 = gbe[1] * 0.5 * t4;
-      const double gt5 = gbe[2] * (13.0 / 6.0) * t5, gt6 = gbe[2] * 0.5 * t6;
-      gcv[q][0] += gt1 + gt2;
-      gcv[q][1] += -2.0 * gt1 - 4.0 * gt2 + gt3 + gt4;
-      gcv[q][2] += gt1 + 3.0 * gt2 - 2.0 * gt3 + gt5 + 3.0 * gt6;
-      gcv[q][3] += gt3 - gt4 - 2.0 * gt5 - 4.0 * gt6;
-      gcv[q][4] += gt5 + gt6;
-    }
-    // hs = sum_t w5 . data ; cv[q][t] = L[q] . W_t
-    for (int t = 0; t < 5; ++t) {
-      const double w0 = c.w5[int64_t(s * 15 + 3 * t) * ne + e];
-      const double w1 = c.w5[int64_t(s * 15 + 3 * t + 1) * ne + e];
-      const double w2 = c.w5[int64_t(s * 15 + 3 * t + 2) * ne + e];
-      for (int k = 0; k < 4; ++k) {
-        gW[ix[t]][k] += w0 * ghs[k];
-        gX[ix[t]][k] += w1 * ghs[k];
-        gY[ix[t]][k] += w2 * ghs[k];
-      }
-      for (int q = 0; q < 4; ++q) {
-        if (gcv[q][t] == 0.0) continue;
-        for (int k = 0; k < 4; ++k) {
-          gL[q][k] += gcv[q][t] * W[ix[t]][k];
-          gW[ix[t]][k] += gcv[q][t] * L[q][k];
-        }
-      }
-    }
-  }
-  // ---- L, R -> (u, v, H, c) ----------------------------------------------------
-  double gu = 0, gv = 0, gH = 0, gc = 0;
-  // R
-  gu += gR[1][0] + gR[1][1] + gR[1][2] + gR[3][0] * (-nx * cc) + gR[3][1] * u +
-        gR[3][2] * (nx * cc) + gR[3][3] * (-ny);
-  gv += gR[2][0] + gR[2][1] + gR[2][2] + gR[3][0] * (-ny * cc) + gR[3][1] * v +
-        gR[3][2] * (ny * cc) + gR[3][3] * nx;
-  gH += gR[3][0] + gR[3][2];
-  gc += gR[1][0] * (-nx) + gR[1][2] * nx + gR[2][0] * (-ny) + gR[2][2] * ny +
-        gR[3][0] * (-un) + gR[3][2] * un;
-  // L (b1 = gm1/c^2, b2 = b1 q2/2, ic = 1/c)
+  // ---- reverse: this side's reconstruction ----------------------------------------------
+  // Gradients of R and L are folded into those of the Roe state (u, v, H, c)
+  // as they arise (this side's part; the pair's parts are summed below).
   const double ic2 = ic * ic;
-  gu += gL[0][0] * 0.5 * (b1 * u + nx * ic) + gL[0][1] * (-0.5 * b1) +
-        gL[1][0] * (-b1 * u) + gL[1][1] * b1 + gL[2][0] * 0.5 * (b1 * u - nx * ic) +
-        gL[2][1] * (-0.5 * b1) + gL[3][0] * ny;
-  gv += gL[0][0] * 0.5 * (b1 * v + ny * ic) + gL[0][2] * (-0.5 * b1) +
-        gL[1][0] * (-b1 * v) + gL[1][2] * b1 + gL[2][0] * 0.5 * (b1 * v - ny * ic) +
-        gL[2][2] * (-0.5 * b1) + gL[3][0] * (-nx);
-  gc += gL[0][0] * 0.5 * (-2.0 * b2 * ic - un * ic2) + gL[0][1] * 0.5 * (2.0 * b1 * u * ic + nx * ic2) +
-        gL[0][2] * 0.5 * (2.0 * b1 * v * ic + ny * ic2) + gL[0][3] * (-b1 * ic) +
-        gL[1][0] * (2.0 * b2 * ic) + gL[1][1] * (-2.0 * b1 * u * ic) +
-        gL[1][2] * (-2.0 * b1 * v * ic) + gL[1][3] * (2.0 * b1 * ic) +
-        gL[2][0] * 0.5 * (-2.0 * b2 * ic + un * ic2) + gL[2][1] * 0.5 * (2.0 * b1 * u * ic - nx * ic2) +
-        gL[2][2] * 0.5 * (2.0 * b1 * v * ic - ny * ic2) + gL[2][3] * (-b1 * ic);
+  double gu = 0, gv = 0, gH = 0, gc = 0;
+  auto foldL = [&](int q, const double z[4]) {  // z = gradient of row q of L
+    if (q == 0) {
+      gu += z[0] * 0.5 * (b1 * u + nx * ic) + z[1] * (-0.5 * b1);
+      gv += z[0] * 0.5 * (b1 * v + ny * ic) + z[2] * (-0.5 * b1);
+      gc += z[0] * 0.5 * (-2.0 * b2 * ic - un * ic2) + z[1] * 0.5 * (2.0 * b1 * u * ic + nx * ic2) +
+            z[2] * 0.5 * (2.0 * b1 * v * ic + ny * ic2) + z[3] * (-b1 * ic);
+    } else if (q == 1) {
+      gu += z[0] * (-b1 * u) + z[1] * b1;
+      gv += z[0] * (-b1 * v) + z[2] * b1;
+      gc += z[0] * (2.0 * b2 * ic) + z[1] * (-2.0 * b1 * u * ic) + z[2] * (-2.0 * b1 * v * ic) +
+            z[3] * (2.0 * b1 * ic);
+    } else if (q == 2) {
+      gu += z[0] * 0.5 * (b1 * u - nx * ic) + z[1] * (-0.5 * b1);
+      gv += z[0] * 0.5 * (b1 * v - ny * ic) + z[2] * (-0.5 * b1);
+      gc += z[0] * 0.5 * (-2.0 * b2 * ic + un * ic2) + z[1] * 0.5 * (2.0 * b1 * u * ic - nx * ic2) +
+            z[2] * 0.5 * (2.0 * b1 * v * ic - ny * ic2) + z[3] * (-b1 * ic);
+    } else {
+      gu += z[0] * ny;
+      gv += z[0] * (-nx);
+    }
+  };
+  {
+    double gR[4][4];
+    for (int r = 0; r < 4; ++r)
+      for (int q = 0; q < 4; ++q) gR[r][q] = gw[r] * C[q];
+    gu += gR[1][0] + gR[1][1] + gR[1][2] + gR[3][0] * (-nx * cc) + gR[3][1] * u +
+          gR[3][2] * (nx * cc) + gR[3][3] * (-ny);
+    gv += gR[2][0] + gR[2][1] + gR[2][2] + gR[3][0] * (-ny * cc) + gR[3][1] * v +
+          gR[3][2] * (ny * cc) + gR[3][3] * nx;
+    gH += gR[3][0] + gR[3][2];
+    gc += gR[1][0] * (-nx) + gR[1][2] * nx + gR[2][0] * (-ny) + gR[2][2] * ny +
+          gR[3][0] * (-un) + gR[3][2] * un;
+  }
+  double gC[4];
+  for (int q = 0; q < 4; ++q)
+    gC[q] = R[0][q] * gw[0] + R[1][q] * gw[1] + R[2][q] * gw[2] + R[3][q] * gw[3];
+  double W[5][4], w3[9];
+  load_W(W);
+  load_w3(w3);
+  double gW[5][4] = {}, ghs[4] = {0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) {
+    const double gCq = gC[q];
+    double z[4];
+    if (!weno[q]) {
+      // C_q = L_q . hs
+      for (int k = 0; k < 4; ++k) {
+        z[k] = gCq * hs[k];
+        ghs[k] += gCq * L[q][k];
+      }
+      foldL(q, z);
+      continue;
+    }
+    double cq[5], be[3], al[3], sal, om[3], Sk[3];
+    proj(L, W, q, cq);
+    weno_parts(w3, cq, be, al, sal, om, Sk);
+    double gcv[5] = {0, 0, 0, 0, 0}, gS[3], gom[3];
+    for (int k = 0; k < 3; ++k) {
+      gS[k] = gCq * om[k];
+      gom[k] = gCq * Sk[k];
+    }
+    for (int k = 0; k < 3; ++k)
+      for (int t = 0; t < 3; ++t) gcv[k + t] += gS[k] * w3[3 * k + t];
+    // omega = alpha / sum(alpha), alpha = d / (eps + beta)^2
+    double dot = 0.0;
+    for (int k = 0; k < 3; ++k) dot += gom[k] * om[k];
+    double gbe[3];
+    for (int k = 0; k < 3; ++k) {
+      const double gal = (gom[k] - dot) / sal;
+      gbe[k] = -2.0 * gal * al[k] / (eps + be[k]);
+    }
+    const double t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
+    const double t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
+    const double t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
+    const double gt1 = gbe[0] * (13.0 / 6.0) * t1, gt2 = gbe[0] * 0.5 * t2;
+    const double gt3 = gbe[1] * (13.0 / 6.0) * t3, gt4 = gbe[1] * 0.5 * t4;
+    const double gt5 = gbe[2] * (13.0 / 6.0) * t5, gt6 = gbe[2] * 0.5 * t6;
+    gcv[0] += gt1 + gt2;
+    gcv[1] += -2.0 * gt1 - 4.0 * gt2 + gt3 + gt4;
+    gcv[2] += gt1 + 3.0 * gt2 - 2.0 * gt3 + gt5 + 3.0 * gt6;
+    gcv[3] += gt3 - gt4 - 2.0 * gt5 - 4.0 * gt6;
+    gcv[4] += gt5 + gt6;
+    // cv[q][t] = L[q] . W_t
+    for (int k = 0; k < 4; ++k) z[k] = 0.0;
+    for (int t = 0; t < 5; ++t)
+      for (int k = 0; k < 4; ++k) {
+        z[k] += gcv[t] * W[t][k];
+        gW[t][k] += gcv[t] * L[q][k];
+      }
+    foldL(q, z);
+  }
+  // hs = sum_t w5 . data: the value part here, the gradient parts at output
+  asm volatile("" ::: "memory");
+  double w5[5][3];
+  load_w5(w5);
+  for (int t = 0; t < 5; ++t)
+    for (int k = 0; k < 4; ++k) gW[t][k] += w5[t][0] * ghs[k];
+  // sum over the pair in a fixed order (left part + right part)
+  {
+    const double ou = dpp_mov<0xB1>(gu), ov = dpp_mov<0xB1>(gv), oH = dpp_mov<0xB1>(gH),
+                 oc = dpp_mov<0xB1>(gc);
+    gu = s == 0 ? gu + ou : ou + gu;
+    gv = s == 0 ? gv + ov : ov + gv;
+    gH = s == 0 ? gH + oH : oH + gH;
+    gc = s == 0 ? gc + oc : oc + gc;
+  }
   // c = sqrt(gm1 (H - q2/2))
   gH += gc * gm1 / (2.0 * cc);
   gu += gc * (-gm1 * u / (2.0 * cc));
   gv += gc * (-gm1 * v / (2.0 * cc));
-  // ---- Roe average -> end states -------------------------------------------------
-  const double gP = gu / D, gQ = gv / D, gK = gH / D;
-  const double gD = -(gu * u + gv * v + gH * H) / D;
-  for (int side = 0; side < 2; ++side) {
-    const double* S = side == 0 ? A : B;
-    double* g = gW[side == 0 ? 2 : 3];
-    const double r = S[0], s_ = side == 0 ? sa : sb, p = side == 0 ? pa : pb;
+  // ---- Roe average -> this lane's end state (node 2 or 3, position 2) ---------------
+  {
+    double A[4], B[4], sa, sb, D, pa, pb, u_, v_, H_, cc_;
+    roe(A, B, sa, sb, D, pa, pb, u_, v_, H_, cc_);
+    const double gP = gu / D, gQ = gv / D, gK = gH / D;
+    const double gD = -(gu * u + gv * v + gH * H) / D;
+    const double* S = s == 0 ? A : B;
+    double* g = gW[2];
+    const double r = S[0], s_ = s == 0 ? sa : sb, p = s == 0 ? pa : pb;
     double gs = gD;
     // P = m/s, Q = n/s, K = (E + p)/s
     g[1] += gP / s_;
     g[2] += gQ / s_;
     gs += -(gP * S[1] + gQ * S[2] + gK * (S[3] + p)) / (s_ * s_);
-    const double gE = gK / s_, gp = gK / s_;
+    const double gE = gK / s_, gp_ = gK / s_;
     g[3] += gE;
     // p = gm1 (E - (m^2 + n^2) / (2 r))
-    g[3] += gm1 * gp;
-    g[1] += -gm1 * gp * S[1] / r;
-    g[2] += -gm1 * gp * S[2] / r;
-    g[0] += gm1 * gp * 0.5 * (S[1] * S[1] + S[2] * S[2]) / (r * r);
+    g[3] += gm1 * gp_;
+    g[1] += -gm1 * gp_ * S[1] / r;
+    g[2] += -gm1 * gp_ * S[2] / r;
+    g[0] += gm1 * gp_ * 0.5 * (S[1] * S[1] + S[2] * S[2]) / (r * r);
     // s = sqrt(r)
     g[0] += gs / (2.0 * s_);
   }
+  // ---- shared nodes: position p (1, 2) of one lane is position 5 - p of the
+  // other; each lane adds the partner's contribution to its positions 1, 2.
+  // The gradient parts are w5[t][1] ghs and w5[t][2] ghs.
+  double pghs[4], pw5[3][2];
+  for (int k = 0; k < 4; ++k) pghs[k] = dpp_mov<0xB1>(ghs[k]);
+  for (int p = 1; p <= 2; ++p) {
+    pw5[p][0] = dpp_mov<0xB1>(w5[5 - p][1]);
+    pw5[p][1] = dpp_mov<0xB1>(w5[5 - p][2]);
+    for (int k = 0; k < 4; ++k) gW[p][k] += dpp_mov<0xB1>(gW[5 - p][k]);
+  }
   double* o = out + int64_t(e) * 72;
-  for (int j = 0; j < 6; ++j)
+  for (int p = 0; p < 3; ++p) {
+    const int j = s == 0 ? p : 5 - p;
     for (int k = 0; k < 4; ++k) {
-      o[12 * j + k] = gW[j][k];
-      o[12 * j + 4 + k] = gX[j][k];
-      o[12 * j + 8 + k] = gY[j][k];
+      double gx = w5[p][1] * ghs[k], gy = w5[p][2] * ghs[k];
+      if (p > 0) {
+        gx += pw5[p][0] * pghs[k];
+        gy += pw5[p][1] * pghs[k];
+      }
+      o[12 * j + k] = gW[p][k];
+      o[12 * j + 4 + k] = gx;
+      o[12 * j + 8 + k] = gy;
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // lambda_U(u) for owned u
 // ---------------------------------------------------------------------------
-__global__ void k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict__ U,
-                             const int32_t* __restrict__ vtp, const int32_t* __restrict__ vtv,
-                             const int32_t* __restrict__ vts, const double* __restrict__ dv,
-                             const int32_t* __restrict__ ntp, const int32_t* __restrict__ nte,
-                             const int8_t* __restrict__ ntj, const double* __restrict__ bnode,
-                             const V4<double>* __restrict__ Lv, const V4<double>* __restrict__ Lg,
-                             double* __restrict__ out) {
-  const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (u >= nowned) return;
-  const double gm1 = gp.gamma - 1.0;
-  double acc[12] = {};
-  // edge-pass contributions
-  for (int k = ntp[u]; k < ntp[u + 1]; ++k) {
-    const double* b = bnode + int64_t(nte[k]) * 72 + 12 * ntj[k];
-    for (int q = 0; q < 12; ++q) acc[q] += b[q];
-  }
-  // vertex fluxes: lambda_f, lambda_g from the rows containing u
-  double lf[4] = {0, 0, 0, 0}, lg[4] = {0, 0, 0, 0};
-  for (int k = vtp[u]; k < vtp[u + 1]; ++k) {
-    const int64_t v = vtv[k], s = vts[k];
-    const double* d = dv + 6 * s;
-    const V4<double> l0 = Lv[v], lx = Lg[2 * v], ly = Lg[2 * v + 1];
-    const double a0[4] = {l0.x, l0.y, l0.z, l0.w};
-    const double ax[4] = {lx.x, lx.y, lx.z, lx.w};
-    const double ay[4] = {ly.x, ly.y, ly.z, ly.w};
-    for (int q = 0; q < 4; ++q) {
-      lf[q] -= d[0] * a0[q] + d[2] * ax[q] + d[4] * ay[q];
-      lg[q] -= d[1] * a0[q] + d[3] * ax[q] + d[5] * ay[q];
+// 16 lanes per vertex, 16 vertices per block.  Lanes stride over (1) the
+// (edge, position) entries of u, summing the 12 edge-pass contributions, and
+// (2) the (v, s) entries with u in S(v), summing lambda_f and lambda_g from
+// the transposed rows dv_t (contiguous per u), two entries per lane and
+// batch.  A transposed DPP reduction leaves the 20 sums in LDS; one lane per
+// vertex applies the flux Jacobians, and the 12 output rows are written in
+// 16-wide runs.
+__global__ void __launch_bounds__(256)
+k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict__ U,
+             const int32_t* __restrict__ vtp, const int32_t* __restrict__ vtv,
+             const double* __restrict__ dv_t, const int32_t* __restrict__ ntp,
+             const int32_t* __restrict__ nte, const int8_t* __restrict__ ntj,
+             const double* __restrict__ bnode, const V4<double>* __restrict__ Lv,
+             const V4<double>* __restrict__ Lg, double* __restrict__ out) {
+  constexpr int VPB = 16;
+  __shared__ double sres[VPB][21];
+  const int t = threadIdx.x, vl = t / 16, sub = t & 15;
+  const int64_t u0 = int64_t(blockIdx.x) * VPB, u = u0 + vl;
+  double acc[32];
+  for (int k = 0; k < 32; ++k) acc[k] = 0.0;
+  if (u < nowned) {
+    // (1) edge-pass contributions; every owned vertex is a stencil node of
+    // some edge and lies in its own S(u), so k1 - 1 is an entry in both loops
+    {
+      const int k0 = ntp[u], k1 = ntp[u + 1];
+      for (int b = k0 + sub; b < k1; b += 32) {
+        int kk[2];
+        bool ok[2];
+        for (int i = 0; i < 2; ++i) {
+          ok[i] = b + 16 * i < k1;
+          kk[i] = ok[i] ? b + 16 * i : k1 - 1;
+        }
+        const double* src[2];
+        for (int i = 0; i < 2; ++i) src[i] = bnode + int64_t(nte[kk[i]]) * 72 + 12 * ntj[kk[i]];
+        double x[2][12];
+        for (int i = 0; i < 2; ++i)
+          for (int q = 0; q < 12; ++q) x[i][q] = src[i][q];
+        for (int i = 0; i < 2; ++i)
+          for (int q = 0; q < 12; ++q) acc[q] += ok[i] ? x[i][q] : 0.0;
+      }
+    }
+    // (2) lambda_f (12..15), lambda_g (16..19)
+    {
+      const int k0 = vtp[u], k1 = vtp[u + 1];
+      for (int b = k0 + sub; b < k1; b += 32) {
+        int kk[2];
+        bool ok[2];
+        for (int i = 0; i < 2; ++i) {
+          ok[i] = b + 16 * i < k1;
+          kk[i] = ok[i] ? b + 16 * i : k1 - 1;
+        }
+        int v[2];
+        double d[2][6];
+        for (int i = 0; i < 2; ++i) {
+          v[i] = vtv[kk[i]];
+          for (int q = 0; q < 6; ++q) d[i][q] = dv_t[6 * int64_t(kk[i]) + q];
+        }
+        V4<double> l0[2], lx[2], ly[2];
+        for (int i = 0; i < 2; ++i) {
+          l0[i] = Lv[v[i]];
+          lx[i] = Lg[2 * int64_t(v[i])];
+          ly[i] = Lg[2 * int64_t(v[i]) + 1];
+        }
+        for (int i = 0; i < 2; ++i) {
+          double dd[6];
+          for (int q = 0; q < 6; ++q) dd[q] = ok[i] ? d[i][q] : 0.0;
+          const double a0[4] = {l0[i].x, l0[i].y, l0[i].z, l0[i].w};
+          const double ax[4] = {lx[i].x, lx[i].y, lx[i].z, lx[i].w};
+          const double ay[4] = {ly[i].x, ly[i].y, ly[i].z, ly[i].w};
+          for (int q = 0; q < 4; ++q) {
+            acc[12 + q] -= dd[0] * a0[q] + dd[2] * ax[q] + dd[4] * ay[q];
+            acc[16 + q] -= dd[1] * a0[q] + dd[3] * ax[q] + dd[5] * ay[q];
+          }
+        }
+      }
     }
   }
-  double w[4];
-  for (int q = 0; q < 4; ++q) w[q] = U[q * nv + u];
-  // A_f^T lf + A_g^T lg = A_n^T with n = (1,0) and (0,1)
-  flux_jac_t(w, 1.0, 0.0, gm1, lf, acc);
-  flux_jac_t(w, 0.0, 1.0, gm1, lg, acc);
-  for (int q = 0; q < 12; ++q) out[q * nv + u] = acc[q];
+  reduce_stage<3, 32>(acc, sub);
+  reduce_stage<2, 16>(acc, sub);
+  reduce_stage<1, 8>(acc, sub);
+  reduce_stage<0, 4>(acc, sub);
+  // lane sub holds sums 2 sub and 2 sub + 1
+  for (int i = 0; i < 2; ++i)
+    if (2 * sub + i < 20) sres[vl][2 * sub + i] = acc[i];
+  __syncthreads();
+  if (t < VPB && u0 + t < nowned) {
+    // A_f^T lambda_f + A_g^T lambda_g at w_u (n = (1, 0) and (0, 1))
+    const int64_t uu = u0 + t;
+    const double gm1 = gp.gamma - 1.0;
+    double w[4], lf[4], lg[4], o[4] = {0, 0, 0, 0};
+    for (int q = 0; q < 4; ++q) {
+      w[q] = U[q * nv + uu];
+      lf[q] = sres[t][12 + q];
+      lg[q] = sres[t][16 + q];
+    }
+    flux_jac_t(w, 1.0, 0.0, gm1, lf, o);
+    flux_jac_t(w, 0.0, 1.0, gm1, lg, o);
+    for (int q = 0; q < 4; ++q) sres[t][q] += o[q];
+  }
+  __syncthreads();
+  if (t < 12 * VPB) {
+    const int q = t / VPB, vl2 = t % VPB;
+    if (u0 + vl2 < nowned) out[q * nv + u0 + vl2] = sres[vl2][q];
+  }
+}
+
+// dst[i][0..w) = src[idx[i]][0..w), i < n
+__global__ void k_take_rows(int64_t n, int w, const int32_t* __restrict__ idx,
+                            const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * w) return;
+  const int64_t r = i / w, q = i % w;
+  dst[i] = src[int64_t(idx[r]) * w + q];
 }
 
 hipError_t launch_adjoint_residual(const AdjointArgs& a, hipStream_t st) {
   if (a.ne > 0) {
-    hipLaunchKernelGGL(k_adj_edge_flux, dim3(unsigned((a.ne + 255) / 256)), dim3(256), 0, st,
-                       a.ne, a.etp, a.etv, a.ets, a.de, a.Lv, a.Lg, a.lh);
-    hipLaunchKernelGGL(k_adj_edge, dim3(unsigned((a.ne + 255) / 256)), dim3(256), 0, st, a.ne,
+    hipLaunchKernelGGL(k_adj_edge_flux, dim3(unsigned((8 * a.ne + 255) / 256)), dim3(256), 0, st,
+                       a.ne, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lh);
+    hipLaunchKernelGGL(k_adj_edge, dim3(unsigned((2 * a.ne + 255) / 256)), dim3(256), 0, st, a.ne,
                        a.ec, a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
   }
   if (a.nowned > 0)
-    hipLaunchKernelGGL(k_adj_vertex, dim3(unsigned((a.nowned + 255) / 256)), dim3(256), 0, st,
-                       a.nowned, a.nv, a.gp, a.U, a.vtp, a.vtv, a.vts, a.dv, a.ntp, a.nte,
-                       a.ntj, a.bnode, a.Lv, a.Lg, a.out);
+    hipLaunchKernelGGL(k_adj_vertex, dim3(unsigned((a.nowned + 15) / 16)), dim3(256), 0, st,
+                       a.nowned, a.nv, a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.ntp, a.nte, a.ntj,
+                       a.bnode, a.Lv, a.Lg, a.out);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_rows(int64_t n, int w, const int32_t* idx, const double* src,
+                            double* dst, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_take_rows, dim3(unsigned((n * w + 255) / 256)), dim3(256), 0, st, n, w,
+                     idx, src, dst);
   return hipGetLastError();
 }
 

@@ -52,6 +52,7 @@ struct hfd_ctx {
   const uint8_t* force = nullptr;
   // adjoint: transposed maps and work buffers (built at first use)
   bool adj_ready = false;
+  bool adj_coef_ready = false;  // de_t, dv_t match the current coefficients
   int32_t *etp = nullptr, *etv = nullptr, *ets = nullptr;
   int32_t *vtp = nullptr, *vtv = nullptr, *vts = nullptr;
   int32_t *ntp = nullptr, *nte = nullptr;
@@ -59,6 +60,7 @@ struct hfd_ctx {
   int32_t *gsp = nullptr, *gsr = nullptr, *gsg = nullptr;  // copy source -> ghosts
   int64_t n_gsrc = 0;
   double *bnode = nullptr, *AL1 = nullptr, *AL2 = nullptr, *AL3 = nullptr, *AB = nullptr;
+  double *de_t = nullptr, *dv_t = nullptr;  // coefficient rows in transposed order
   hfd::V4<double>* lh = nullptr;
   hfd::V4<double>* LGv = nullptr;
   hfd::V4<double>* LGg = nullptr;
@@ -231,7 +233,11 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 template <class T>
 hfd_status rk_step_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
                      const hfd::VertexCoef<T>& vc, bool mx, double* U, double dt,
-                     const double* dt_dev, hipStream_t st) {
+                     const double* dt_dev, hipStream_t st, double* S1 = nullptr,
+                     double* S2 = nullptr) {
+  // S1, S2: where the two intermediate stages go (work buffers by default)
+  if (!S1) S1 = c->U1;
+  if (!S2) S2 = c->U2;
   const hfd::HostSetup& h = c->hs;
   const int64_t nv = h.nv, ne = h.ne, no = h.n_owned;
   const GasParams gp = gas_params(c, mx);
@@ -241,8 +247,8 @@ hfd_status rk_step_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec
   for (int k = 1; k < 3; ++k)
     HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
                                               B.Gg[k], st));
-  const double* in[3] = {U, c->U1, c->U2};
-  double* outp[3] = {c->U1, c->U2, U};
+  const double* in[3] = {U, S1, S2};
+  double* outp[3] = {S1, S2, U};
   for (int k = 0; k < 3; ++k) {
     {
       PassTimer t(c, 0, st);
@@ -313,8 +319,23 @@ void transpose(int64_t nrows, const std::vector<int32_t>& key, std::vector<int32
   for (size_t i = 0; i < key.size(); ++i) pos[fill[key[i]]++] = int32_t(i);
 }
 
+// Coefficient rows in the order of the transposed maps (rebuilt after an
+// import of weights).
+hfd_status ensure_adjoint_coefs(hfd_ctx* c) {
+  if (c->adj_coef_ready) return HFD_OK;
+  const int64_t nes = c->info.n_eslots, nvs = c->info.n_vslots;
+  hfd_status s;
+  if (!c->de_t && ((s = dalloc(c, &c->de_t, 3 * nes)) || (s = dalloc(c, &c->dv_t, 6 * nvs))))
+    return s;
+  HIPCHK(c, hfd::launch_take_rows(nes, 3, c->ets, c->de, c->de_t, nullptr));
+  HIPCHK(c, hfd::launch_take_rows(nvs, 6, c->vts, c->dv, c->dv_t, nullptr));
+  HIPCHK(c, hipStreamSynchronize(nullptr));
+  c->adj_coef_ready = true;
+  return HFD_OK;
+}
+
 hfd_status ensure_adjoint(hfd_ctx* c) {
-  if (c->adj_ready) return HFD_OK;
+  if (c->adj_ready) return ensure_adjoint_coefs(c);
   const hfd::HostSetup& h = c->hs;
   const int64_t ne = h.ne, nv = h.nv, no = h.n_owned;
   hfd_status s;
@@ -388,7 +409,7 @@ hfd_status ensure_adjoint(hfd_ctx* c) {
       (s = dalloc(c, &c->LGv, nv)) || (s = dalloc(c, &c->LGg, 2 * nv)))
     return s;
   c->adj_ready = true;
-  return HFD_OK;
+  return ensure_adjoint_coefs(c);
 }
 
 // out = J(U)^T lam, U given in both layouts (SoA U, gather Gv/Gg)
@@ -402,8 +423,8 @@ hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<double>* Gv,
   a.ne = h.ne;
   a.nowned = h.n_owned;
   a.nv = h.nv;
-  a.etp = c->etp; a.etv = c->etv; a.ets = c->ets;
-  a.de = c->de;
+  a.etp = c->etp; a.etv = c->etv;
+  a.de_t = c->de_t;
   a.Lv = c->LGv; a.Lg = c->LGg;
   a.lh = c->lh;
   a.ec = ecoef64(c);
@@ -412,8 +433,8 @@ hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<double>* Gv,
   a.force = c->force;
   a.bnode = c->bnode;
   a.U = U;
-  a.vtp = c->vtp; a.vtv = c->vtv; a.vts = c->vts;
-  a.dv = c->dv;
+  a.vtp = c->vtp; a.vtv = c->vtv;
+  a.dv_t = c->dv_t;
   a.ntp = c->ntp; a.nte = c->nte; a.ntj = c->ntj;
   a.out = out;
   HIPCHK(c, hfd::launch_adjoint_residual(a, st));
@@ -704,6 +725,7 @@ hfd_status hfd_import_weights(hfd_ctx* c, const double* w5, const double* w3,
   if (w3 && (s = aos_to_soa(w3, 18, c->w3))) return s;
   if (dv) HIPCHK(c, hipMemcpy(c->dv, dv, 6 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
   if (de) HIPCHK(c, hipMemcpy(c->de, de, 3 * c->info.n_eslots * 8, hipMemcpyHostToDevice));
+  if (dv || de) c->adj_coef_ready = false;
   if (dvis) {
     if (!c->dvis) return fail(c, HFD_E_STATE, "no viscous rows (mu == 0)");
     HIPCHK(c, hipMemcpy(c->dvis, dvis, 5 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
@@ -815,46 +837,62 @@ hfd_status hfd_adjoint_residual(hfd_ctx* c, const double* U, const double* lam, 
   return adjoint_apply(c, U, B.Gv[0], B.Gg[0], lam, out, st);
 }
 
-hfd_status hfd_rk_step_adjoint(hfd_ctx* c, const double* U, double dt, const double* lam_np1,
-                               double* lam_n, void* stream) {
+namespace {
+
+// Adjoint of one RK3 step from U with stages U1, U2 (recomputed into the
+// work buffers when null).
+hfd_status rk_step_adjoint_impl(hfd_ctx* c, const double* U, const double* U1in,
+                                const double* U2in, double dt, const double* lam_np1,
+                                double* lam_n, hipStream_t st) {
   hfd_status s = need_device(c);
   if (s) return s;
   if (!U || !lam_np1 || !lam_n) return fail(c, HFD_E_INVAL, "null pointer");
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
   if ((s = ensure_adjoint(c))) return s;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   const hfd::HostSetup& h = c->hs;
   const int64_t nv = h.nv, ne = h.ne, no = h.n_owned, n12 = 12 * nv;
   const int64_t nd = int64_t(h.dir_rows.size());
   auto& B = c->b64;
   const GasParams gp = gas_params(c, false);
-  // forward stages 1 and 2 (float64): U1, U2 and their gather copies
+  const double* Us[3] = {U, U1in, U2in};
   HIPCHK(c, hfd::launch_to_gather<double>(nv, U, gp, B.Gv[0], B.Gg[0], st));
-  for (int k = 1; k < 3; ++k)
-    HIPCHK(c, hfd::launch_copy_gather_rows<double>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
-                                                   B.Gg[k], st));
-  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
-  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
-  const double a[2] = {0.0, 0.75}, b[2] = {1.0, 0.25};
-  const double* in[2] = {U, c->U1};
-  double* outp[2] = {c->U1, c->U2};
-  for (int k = 0; k < 2; ++k) {
-    HIPCHK(c, hfd::launch_edge<double>(ne, ecoef64(c), gp, B.Gv[k], B.Gg[k], c->force, B.H,
-                                       nullptr, nullptr, nullptr, st));
-    hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, nullptr};
-    HIPCHK(c, hfd::launch_vertex<double>(no, nv, vcoef64(c), gp, B.Gv[k], B.Gg[k], B.H, 1,
-                                         nullptr, rk, B.Gv[k + 1], B.Gg[k + 1], c->flag, st));
+  if (U1in) {
+    // the given stages in gather layout, Dirichlet rows from U
+    for (int k = 1; k < 3; ++k) {
+      HIPCHK(c, hfd::launch_to_gather<double>(nv, Us[k], gp, B.Gv[k], B.Gg[k], st));
+      HIPCHK(c, hfd::launch_copy_gather_rows<double>(nd, c->dir_rows, B.Gv[0], B.Gg[0],
+                                                     B.Gv[k], B.Gg[k], st));
+    }
+  } else {
+    // forward stages 1 and 2 (float64): U1, U2 and their gather copies
+    for (int k = 1; k < 3; ++k)
+      HIPCHK(c, hfd::launch_copy_gather_rows<double>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
+                                                     B.Gg[k], st));
+    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
+    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
+    const double a[2] = {0.0, 0.75}, b[2] = {1.0, 0.25};
+    const double* in[2] = {U, c->U1};
+    double* outp[2] = {c->U1, c->U2};
+    for (int k = 0; k < 2; ++k) {
+      HIPCHK(c, hfd::launch_edge<double>(ne, ecoef64(c), gp, B.Gv[k], B.Gg[k], c->force, B.H,
+                                         nullptr, nullptr, nullptr, st));
+      hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, nullptr};
+      HIPCHK(c, hfd::launch_vertex<double>(no, nv, vcoef64(c), gp, B.Gv[k], B.Gg[k], B.H, 1,
+                                           nullptr, rk, B.Gv[k + 1], B.Gg[k + 1], c->flag, st));
+    }
+    Us[1] = c->U1;
+    Us[2] = c->U2;
   }
   // reverse.  A3 = lam_{n+1} with the final ghost fill transposed
   double *A3 = c->AL3, *L2 = c->AL2, *L1 = c->AL1, *Bt = c->AB;
   HIPCHK(c, hipMemcpyAsync(A3, lam_np1, n12 * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(c, hfd::launch_adj_copy_ghosts(c->n_gsrc, c->gsp, c->gsr, c->gsg, nv, A3, st));
   // stage 3: U3 = U/3 + 2/3 (U2 + dt R(U2))
-  if ((s = adjoint_apply(c, c->U2, B.Gv[2], B.Gg[2], A3, Bt, st))) return s;
+  if ((s = adjoint_apply(c, Us[2], B.Gv[2], B.Gg[2], A3, Bt, st))) return s;
   HIPCHK(c, hfd::launch_axpbypcz(n12, 2.0 / 3.0, A3, 2.0 / 3.0 * dt, Bt, 0.0, nullptr, L2, st));
   HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0 / 3.0, A3, 0.0, A3, 0.0, nullptr, lam_n, st));
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
-  if ((s = adjoint_apply(c, c->U1, B.Gv[1], B.Gg[1], L2, Bt, st))) return s;
+  if ((s = adjoint_apply(c, Us[1], B.Gv[1], B.Gg[1], L2, Bt, st))) return s;
   HIPCHK(c, hfd::launch_axpbypcz(n12, 0.25, L2, 0.25 * dt, Bt, 0.0, nullptr, L1, st));
   HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0, lam_n, 0.75, L2, 0.0, nullptr, lam_n, st));
   // stage 1: U1 = U + dt R(U)
@@ -864,6 +902,31 @@ hfd_status hfd_rk_step_adjoint(hfd_ctx* c, const double* U, double dt, const dou
   HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, A3, lam_n, st));
   HIPCHK(c, hfd::launch_zero_ghost_rows(no + nd, nv, lam_n, st));
   return HFD_OK;
+}
+
+}  // namespace
+
+hfd_status hfd_rk_step_adjoint(hfd_ctx* c, const double* U, double dt, const double* lam_np1,
+                               double* lam_n, void* stream) {
+  return rk_step_adjoint_impl(c, U, nullptr, nullptr, dt, lam_np1, lam_n,
+                              static_cast<hipStream_t>(stream));
+}
+
+hfd_status hfd_rk_step_adjoint_stages(hfd_ctx* c, const double* U, const double* U1,
+                                      const double* U2, double dt, const double* lam_np1,
+                                      double* lam_n, void* stream) {
+  if (!U1 || !U2) return fail(c, HFD_E_INVAL, "null stage state");
+  return rk_step_adjoint_impl(c, U, U1, U2, dt, lam_np1, lam_n,
+                              static_cast<hipStream_t>(stream));
+}
+
+hfd_status hfd_rk_step_stages(hfd_ctx* c, double* U, double dt, double* U1, double* U2,
+                              void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !U1 || !U2) return fail(c, HFD_E_INVAL, "null state");
+  return rk_step_t<double>(c, c->b64, ecoef64(c), vcoef64(c), false, U, dt, nullptr,
+                           static_cast<hipStream_t>(stream), U1, U2);
 }
 
 hfd_status hfd_set_timing(hfd_ctx* c, int32_t on) {

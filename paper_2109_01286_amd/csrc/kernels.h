@@ -9,6 +9,41 @@
 
 namespace hfd {
 
+// ---- lane primitives (device) -----------------------------------------------
+// Lane exchange through DPP (a VALU move, no LDS traffic).  0x140 mirrors a
+// row of 16 lanes (the partner differs in bit 3 of the lane index), 0x141
+// mirrors each half row (bit 2), the quad permutations 0x4E and 0xB1 swap
+// lanes differing in bit 1 and in bit 0.
+template <int CTRL>
+__device__ inline float dpp_mov(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32));
+}
+
+// One stage of the transposed lane reduction: of its N values the lane keeps
+// the half selected by bit B of its index and adds the partner's copy of that
+// half.  The four partner maps above pair disjoint lane sets at every stage,
+// so after the stages for bits log2(VL)-1 .. 0 each value is a sum over all
+// VL lanes, and lane `sub` holds accumulators (16/VL) sub + i.
+template <int B, int N, class T>
+__device__ inline void reduce_stage(T* a, int sub) {
+  constexpr int CTRL = B == 3 ? 0x140 : B == 2 ? 0x141 : B == 1 ? 0x4E : 0xB1;
+  const bool hi = (sub >> B) & 1;
+#pragma unroll
+  for (int j = 0; j < N / 2; ++j) {
+    const T send = hi ? a[j] : a[N / 2 + j];
+    const T keep = hi ? a[N / 2 + j] : a[j];
+    a[j] = keep + dpp_mov<CTRL>(send);
+  }
+}
+
 // ---- geometric precompute (float64) ----------------------------------------
 hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
                                double w3_cap, double* w5, double* w3,
@@ -104,8 +139,8 @@ hipError_t launch_widen(int64_t n, const float* a, double* b, hipStream_t st);
 // ---- adjoint (float64, Euler) ---------------------------------------------------
 struct AdjointArgs {
   int64_t ne, nowned, nv;
-  const int32_t *etp, *etv, *ets;   // edge m <- (owner vertex, edge slot)
-  const double* de;
+  const int32_t *etp, *etv;         // edge m <- (owner vertex, edge slot)
+  const double* de_t;               // de rows in the order of etv
   const V4<double>* Lv;             // lambda in gather layout
   const V4<double>* Lg;
   V4<double>* lh;                   // [ne] flux adjoint
@@ -116,13 +151,16 @@ struct AdjointArgs {
   const uint8_t* force;
   double* bnode;                    // [ne][6][12] edge-pass contributions
   const double* U;                  // state [12][nv]
-  const int32_t *vtp, *vtv, *vts;   // gather row <- (owner vertex, vertex slot)
-  const double* dv;
+  const int32_t *vtp, *vtv;         // gather row <- (owner vertex, vertex slot)
+  const double* dv_t;               // dv rows in the order of vtv
   const int32_t *ntp, *nte;         // gather row <- (edge, stencil position)
   const int8_t* ntj;
   double* out;                      // [12][nv], owned rows written
 };
 hipError_t launch_adjoint_residual(const AdjointArgs& a, hipStream_t st);
+// dst[i][0..w) = src[idx[i]][0..w), i < n (transposed coefficient copies)
+hipError_t launch_take_rows(int64_t n, int w, const int32_t* idx, const double* src,
+                            double* dst, hipStream_t st);
 
 // out[i] = a x[i] + b y[i] (+ c z[i] if z), i < n
 hipError_t launch_axpbypcz(int64_t n, double a, const double* x, double b, const double* y,

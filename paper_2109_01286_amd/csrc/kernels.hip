@@ -557,40 +557,6 @@ __device__ inline void vslot(const V4<T>& a, const V4<T>* gx, const T* d, const 
   }
 }
 
-// Lane exchange through DPP (a VALU move, no LDS traffic).  0x140 mirrors a
-// row of 16 lanes (the partner differs in bit 3 of the lane index), 0x141
-// mirrors each half row (bit 2), the quad permutations 0x4E and 0xB1 swap
-// lanes differing in bit 1 and in bit 0.
-template <int CTRL>
-__device__ inline float dpp_mov(float x) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ inline double dpp_mov(double x) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32));
-}
-
-// One stage of the transposed lane reduction: of its N values the lane keeps
-// the half selected by bit B of its index and adds the partner's copy of that
-// half.  The four partner maps above pair disjoint lane sets at every stage,
-// so after the stages for bits log2(VL)-1 .. 0 each value is a sum over all
-// VL lanes, and lane `sub` holds accumulators (16/VL) sub + i.
-template <int B, int N, class T>
-__device__ inline void reduce_stage(T* a, int sub) {
-  constexpr int CTRL = B == 3 ? 0x140 : B == 2 ? 0x141 : B == 1 ? 0x4E : 0xB1;
-  const bool hi = (sub >> B) & 1;
-#pragma unroll
-  for (int j = 0; j < N / 2; ++j) {
-    const T send = hi ? a[j] : a[N / 2 + j];
-    const T keep = hi ? a[N / 2 + j] : a[j];
-    a[j] = keep + dpp_mov<CTRL>(send);
-  }
-}
-
 // A coefficient record of N values (loaded as one aggregate).
 template <class T, int N>
 struct Rec {

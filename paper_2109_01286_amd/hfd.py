@@ -88,6 +88,8 @@ SIGNATURES = {
     "hfd_check": (ctypes.c_int, [_P, _P]),
     "hfd_adjoint_residual": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "hfd_rk_step_adjoint": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
+    "hfd_rk_step_stages": (ctypes.c_int, [_P, _P, _D, _P, _P, _P]),
+    "hfd_rk_step_adjoint_stages": (ctypes.c_int, [_P, _P, _P, _P, _D, _P, _P, _P]),
     "hfd_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "hfd_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, _P]),
 }
@@ -327,6 +329,23 @@ class Solver:
             out = torch.empty_like(U_n)
         self._chk(lib().hfd_rk_step_adjoint(self._h, _dptr(U_n), float(dt), _dptr(lam_np1),
                                             _dptr(out), _stream()))
+        return out
+
+    def rk_step_stages(self, U, dt, U1, U2):
+        """One float64 RK3 step in place that also writes its intermediate
+        stages into U1, U2 (device tensors shaped like U)."""
+        self._chk(lib().hfd_rk_step_stages(self._h, _dptr(U), float(dt), _dptr(U1), _dptr(U2),
+                                           _stream()))
+        return U
+
+    def rk_step_adjoint_stages(self, U_n, U1, U2, dt, lam_np1, out=None):
+        """rk_step_adjoint with the step's stages (from rk_step_stages) given."""
+        import torch
+        if out is None:
+            out = torch.empty_like(U_n)
+        self._chk(lib().hfd_rk_step_adjoint_stages(self._h, _dptr(U_n), _dptr(U1), _dptr(U2),
+                                                   float(dt), _dptr(lam_np1), _dptr(out),
+                                                   _stream()))
         return out
 
     def fill_ghosts(self, U):
