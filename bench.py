@@ -152,6 +152,61 @@ def cpu_baseline(m, U0, prm, kw, budget_s):
                        f"evaluations in {el:.1f} s; oracle setup {setup:.1f} s not timed")
 
 
+def accuracy_runs():
+    """Errors against closed-form solutions, float32 (mixed) and float64, on
+    the cases that stay finite under the readings (the shock-vortex has no
+    closed form; its float32-float64 difference is reported with the
+    throughput):
+      - the vortex on the 21 x 21 lattice, 20 steps at CFL 0.3, paper switch
+        with the 3-node cap 2 (without it the run fails), against the exactly
+        advected vortex;
+      - the Taylor-Green vortex on the 129 x 129 lattice, 20 steps at CFL 0.3,
+        smooth switch, against the incompressible decay exp(-2 nu t) (the
+        513 x 513 lattice of the same recipe is unstable after two steps).
+    L2 (root mean square over owned vertices) and max errors of rho and of
+    the momentum rho u."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+    cases = {"vortex21": ("vortex21", None, {"switch": "paper", "w3_cap": 2.0}),
+             "tgv129": ("tgv513", 129, None)}
+    out = {}
+    for key, (name, scale, over) in cases.items():
+        m, U0, prm = inputs.workload(name, scale)
+        kw = workload_options(name, prm)
+        if over:
+            kw.update(over)
+        S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, **kw)
+        wref = U0[0:4, m.ghost_src == -1].mean(axis=1)
+        owned = m.ghost_src == -1
+        res = {}
+        for prec in ("fp64", "fp32"):
+            S.set_precision(prec, wref)
+            U = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+            dt = torch.empty(1, dtype=torch.float64, device="cuda:0")
+            t = 0.0
+            for _ in range(prm["steps"] if key == "vortex21" else 20):
+                S.stable_dt(U, 0.3, out=dt)
+                t += dt.item()
+                S.rk_step(U, dt)
+            S.check()
+            Uh = S.to_input(U.cpu().numpy())
+            if key == "vortex21":
+                Ue = inputs.isentropic_vortex(m, center=(5.0, 5.0), beta=5.0, t=t)
+            else:
+                Ue = inputs.taylor_green(m, t=t, nu=prm["mu"])
+            e = {}
+            for q, nm in ((0, "rho"), (1, "rho_u")):
+                d = Uh[q, owned] - Ue[q, owned]
+                e[nm] = {"l2": float(np.sqrt(np.mean(d * d))), "max": float(np.abs(d).max())}
+            res[prec] = dict(t=t, **e)
+        res["fp32_over_fp64_l2_rho"] = res["fp32"]["rho"]["l2"] / res["fp64"]["rho"]["l2"]
+        out[key] = res
+        del S
+    return out
+
+
 def adjoint_ratio(steps=200, ckpt=20):
     """Adjoint/forward time of the isentropic vortex on the 257 x 257 periodic
     jittered lattice: gradient of J = sum A_v [|x - (7,7)| < 1] p^2 after
@@ -223,6 +278,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (a "
                          "known-size kernel for calibrating HBM byte counters)")
@@ -312,6 +368,11 @@ def main():
                        "ms_per_step": res["fp64"]["wall"] / a.steps * 1e3,
                        "kernels": res["fp64"]["kern"]}
         out["fp32_vs_fp64_rho_rel_l2"] = diff
+    if not a.no_accuracy:
+        out["accuracy"] = accuracy_runs()
+        log("[bench] accuracy: " + ", ".join(
+            f"{k} rho L2 fp64 {v['fp64']['rho']['l2']:.3e} fp32 {v['fp32']['rho']['l2']:.3e}"
+            for k, v in out["accuracy"].items()))
     if not a.no_adjoint:
         del S
         torch.cuda.empty_cache()
