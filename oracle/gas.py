@@ -9,7 +9,10 @@ gives no viscous constitutive law):
 
 * Riemann flux: Rusanov (local Lax-Friedrichs),
   h = (F(wL).n + F(wR).n)/2 - lam_max (wR - wL)/2,
-  lam_max = max(|u_n| + c) over the two states.
+  lam_max = max(|u_n| + c) over the two states.  The paper admits any
+  Riemann solver; two variants are provided as options: Roe's flux with
+  Harten's entropy fix on the acoustic waves, and the HLLC flux (Toro) with
+  the Davis-Einfeldt wave-speed estimates.
 * Characteristic projection (Algorithm 1): Roe average of the two end
   states of the edge, right eigenvectors of the flux Jacobian along the edge
   direction n as columns of R in the order (u_n - c, u_n, u_n + c, u_n),
@@ -54,9 +57,8 @@ def sound_speed(w, gamma):
     return torch.sqrt(gamma * p / rho)
 
 
-def roe_eigenvectors(wa, wb, n, gamma):
-    """Right eigenvectors (columns) of the flux Jacobian along n at the Roe
-    average of wa and wb; shape [..., 4, 4]."""
+def roe_average(wa, wb, gamma):
+    """Roe-averaged velocity, total enthalpy and sound speed of wa, wb."""
     ra, ua, va, pa = primitives(wa, gamma)
     rb, ub, vb, pb = primitives(wb, gamma)
     sa, sb = torch.sqrt(ra), torch.sqrt(rb)
@@ -65,8 +67,15 @@ def roe_eigenvectors(wa, wb, n, gamma):
     u = (sa * ua + sb * ub) / (sa + sb)
     v = (sa * va + sb * vb) / (sa + sb)
     H = (sa * Ha + sb * Hb) / (sa + sb)
+    c = torch.sqrt((gamma - 1.0) * (H - 0.5 * (u * u + v * v)))
+    return u, v, H, c
+
+
+def roe_eigenvectors(wa, wb, n, gamma):
+    """Right eigenvectors (columns) of the flux Jacobian along n at the Roe
+    average of wa and wb; shape [..., 4, 4]."""
+    u, v, H, c = roe_average(wa, wb, gamma)
     q2 = u * u + v * v
-    c = torch.sqrt((gamma - 1.0) * (H - 0.5 * q2))
     nx, ny = n[..., 0], n[..., 1]
     un = u * nx + v * ny
     ut = -u * ny + v * nx
@@ -90,6 +99,72 @@ def rusanov(wl, wr, n, gamma):
     sr = torch.abs(ur * n[..., 0] + vr * n[..., 1]) + sound_speed(wr, gamma)
     lam = torch.maximum(sl, sr)
     return 0.5 * (fl + fr) - 0.5 * lam[..., None] * (wr - wl)
+
+
+def roe_flux(wl, wr, n, gamma, delta=0.1):
+    """Roe's flux h = (F(wL).n + F(wR).n)/2 - R |Lambda| R^-1 (wR - wL)/2 at
+    the Roe average, eigenvalues (u_n - c, u_n, u_n + c, u_n) in the column
+    order of roe_eigenvectors.  Harten's entropy fix on the two acoustic
+    waves: |lambda| < d is replaced by (lambda^2 + d^2) / (2 d), with
+    d = delta (|u_n| + c) of the Roe state (delta = 0: no fix)."""
+    u, v, H, c = roe_average(wl, wr, gamma)
+    un = u * n[..., 0] + v * n[..., 1]
+    lam = torch.stack([un - c, un, un + c, un], dim=-1)
+    alam = torch.abs(lam)
+    if delta > 0:
+        d = (delta * (torch.abs(un) + c))[..., None]
+        fixed = torch.where(alam < d, (lam * lam + d * d) / (2.0 * d), alam)
+        acoustic = torch.tensor([True, False, True, False])
+        alam = torch.where(acoustic, fixed, alam)
+    R = roe_eigenvectors(wl, wr, n, gamma)
+    alpha = torch.linalg.solve(R, (wr - wl)[..., None])[..., 0]
+    diss = (R @ (alam * alpha)[..., None])[..., 0]
+    return 0.5 * (normal_flux(wl, n, gamma) + normal_flux(wr, n, gamma)) - 0.5 * diss
+
+
+def hllc_flux(wl, wr, n, gamma):
+    """Toro's HLLC flux.  Wave speeds S_L = min(u_nL - c_L, u_n - c),
+    S_R = max(u_nR + c_R, u_n + c) (Roe state on the right of each), contact
+    speed S_M from the two momentum balances; star states
+    U*_K = rho_K (S_K - u_nK)/(S_K - S_M) (1, u_K + (S_M - u_nK) n,
+    E_K/rho_K + (S_M - u_nK)(S_M + p_K/(rho_K (S_K - u_nK)))), and
+    F*_K = F_K + S_K (U*_K - U_K); the flux is F_L, F*_L, F*_R or F_R as
+    0 lies left of S_L, between S_L and S_M, between S_M and S_R, or right
+    of S_R."""
+    nx, ny = n[..., 0], n[..., 1]
+    rl, ul, vl, pl = primitives(wl, gamma)
+    rr, ur, vr, pr = primitives(wr, gamma)
+    unl, unr = ul * nx + vl * ny, ur * nx + vr * ny
+    cl, cr = sound_speed(wl, gamma), sound_speed(wr, gamma)
+    u, v, H, c = roe_average(wl, wr, gamma)
+    un = u * nx + v * ny
+    sl = torch.minimum(unl - cl, un - c)
+    sr = torch.maximum(unr + cr, un + c)
+    sm = (pr - pl + rl * unl * (sl - unl) - rr * unr * (sr - unr)) / (
+        rl * (sl - unl) - rr * (sr - unr))
+
+    def star(w, rho, uu, vv, p, unk, sk):
+        f = rho * (sk - unk) / (sk - sm)
+        return torch.stack([f, f * (uu + (sm - unk) * nx), f * (vv + (sm - unk) * ny),
+                            f * (w[..., 3] / rho + (sm - unk) * (sm + p / (rho * (sk - unk))))],
+                           dim=-1)
+
+    fl, fr = normal_flux(wl, n, gamma), normal_flux(wr, n, gamma)
+    fsl = fl + sl[..., None] * (star(wl, rl, ul, vl, pl, unl, sl) - wl)
+    fsr = fr + sr[..., None] * (star(wr, rr, ur, vr, pr, unr, sr) - wr)
+    return torch.where((sl >= 0)[..., None], fl,
+                       torch.where((sm >= 0)[..., None], fsl,
+                                   torch.where((sr >= 0)[..., None], fsr, fr)))
+
+
+def riemann_flux(kind, wl, wr, n, gamma):
+    if kind == "rusanov":
+        return rusanov(wl, wr, n, gamma)
+    if kind == "roe":
+        return roe_flux(wl, wr, n, gamma)
+    if kind == "hllc":
+        return hllc_flux(wl, wr, n, gamma)
+    raise ValueError(kind)
 
 
 def viscous_flux(w, wx, wy, gamma, mu, prandtl, gas_R):

@@ -63,6 +63,7 @@ class Options:
     sw_hi: float = 0.79
     switch: object = "paper"
     w3_cap: float = 0.0     # 0: no dropping rule for the 3-node systems
+    flux: str = "rusanov"   # Riemann flux: "rusanov", "roe" or "hllc"
 
 
 def weno_omega(c, eps):
@@ -203,7 +204,7 @@ class Scheme:
             C = torch.where(use, weno, smooth)
             out.append(torch.einsum("eqr,er->eq", R, C))
         wl, wr = out
-        h = gas.rusanov(wl, wr, self.n, o.gamma)
+        h = gas.riemann_flux(o.flux, wl, wr, self.n, o.gamma)
         return wl, wr, mask, h
 
     # -- step 3 -------------------------------------------------------------
