@@ -279,6 +279,7 @@ def main():
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-flux-variants", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (a "
                          "known-size kernel for calibrating HBM byte counters)")
@@ -330,6 +331,25 @@ def main():
             f"{r['rate'] / 1e9:.3f} G vertex-stage/s; edge {kern['edge']['avg_ms']:.3f} ms "
             f"({kern['edge']['achieved_gbs']:.0f} GB/s), vertex {kern['vertex']['avg_ms']:.3f} ms "
             f"({kern['vertex']['achieved_gbs']:.0f} GB/s)")
+    # Riemann-flux variants: the same steps with Roe's and the HLLC flux
+    # (edge-pass arithmetic only; the bytes are those of the Rusanov run)
+    variants = {}
+    if not a.no_flux_variants:
+        for prec in res:
+            variants[prec] = {"rusanov": {"edge_ms": res[prec]["edge_ms"],
+                                          "ms_per_step": res[prec]["wall"] / a.steps * 1e3}}
+            for fx in ("roe", "hllc"):
+                S.set_flux(fx)
+                try:
+                    r = time_precision(S, U0d, prec, wref, a.chunk, 2, a.cfl, a.chunk)
+                    variants[prec][fx] = {"edge_ms": r["edge_ms"],
+                                          "ms_per_step": r["wall"] / a.chunk * 1e3}
+                except hfd.HfdError as e:
+                    variants[prec][fx] = {"error": str(e)}
+                finally:
+                    S.set_flux("rusanov")
+            log(f"[bench] {prec} edge pass by flux: " + ", ".join(
+                f"{k} {v.get('edge_ms', float('nan')):.3f} ms" for k, v in variants[prec].items()))
     main_prec = "fp32" if "fp32" in res else "fp64"
     r = res[main_prec]
     dom, kern = r["dom"], r["kern"]
@@ -363,6 +383,8 @@ def main():
                                  if main_prec == "fp32" else None)},
         "kernels": kern,
     }
+    if variants:
+        out["flux_variants"] = variants
     if "fp64" in res and main_prec == "fp32":
         out["fp64"] = {"value": res["fp64"]["rate"],
                        "ms_per_step": res["fp64"]["wall"] / a.steps * 1e3,

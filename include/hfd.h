@@ -64,6 +64,13 @@ typedef enum {
 
 typedef enum { HFD_ORDER_NONE = 0, HFD_ORDER_HILBERT = 1 } hfd_order;
 
+/* Riemann flux along the edge (the paper leaves the solver open):
+ * RUSANOV = local Lax-Friedrichs; ROE = Roe's flux at the Roe average of the
+ * two interface states with Harten's entropy fix on the acoustic waves
+ * (|lambda| < d -> (lambda^2 + d^2)/(2 d), d = 0.1 (|u.n| + c)); HLLC = Toro's
+ * HLLC flux with the Davis-Einfeldt wave speeds (Roe state). */
+typedef enum { HFD_FLUX_RUSANOV = 0, HFD_FLUX_ROE = 1, HFD_FLUX_HLLC = 2 } hfd_flux;
+
 typedef struct hfd_opts {
   double gamma;        /* ratio of specific heats                         */
   double gas_R;        /* gas constant (viscous heat flux only)           */
@@ -78,7 +85,8 @@ typedef struct hfd_opts {
   int32_t switch_mode; /* hfd_switch                                      */
   int32_t precision;   /* hfd_precision                                   */
   int32_t order;       /* hfd_order: vertex renumbering                   */
-  int32_t reserved[5];
+  int32_t flux;        /* hfd_flux                                        */
+  int32_t reserved[4];
 } hfd_opts;
 
 typedef struct hfd_info {
@@ -108,7 +116,8 @@ typedef struct hfd_info {
 } hfd_info;
 
 /* Default options: gamma 1.4, R 1, mu 0, Pr 0.72, eps 1e-6, (0.01, 0.79),
- * no 3-node cap, not periodic, w_ref 0, PAPER switch, FP64, Hilbert order. */
+ * no 3-node cap, not periodic, w_ref 0, PAPER switch, FP64, Hilbert order,
+ * Rusanov flux. */
 void hfd_default_opts(hfd_opts* o);
 
 const char* hfd_status_string(hfd_status s);
@@ -186,6 +195,11 @@ hfd_status hfd_import_weights(hfd_ctx* ctx, const double* w5, const double* w3,
  * first use; synchronises. */
 hfd_status hfd_set_precision(hfd_ctx* ctx, int32_t precision,
                              const double* w_ref);
+
+/* Riemann flux (hfd_flux) of later residual and step calls; the weights do
+ * not depend on it.  Errors: HFD_E_INVAL for another value.  The adjoint
+ * entry points require HFD_FLUX_RUSANOV (HFD_E_STATE otherwise). */
+hfd_status hfd_set_flux(hfd_ctx* ctx, int32_t flux);
 
 /* dU = right-hand side of eq. HWENO at state U (device, [12][nv] float64
  * both).  Rows of ghost vertices of dU are set to zero.  Rows of ghost

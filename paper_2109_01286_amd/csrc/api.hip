@@ -126,6 +126,7 @@ GasParams gas_params(const hfd_ctx* c, bool mixed) {
   g.sw_hi = c->o.sw_hi;
   for (int q = 0; q < 4; ++q) g.wref[q] = mixed ? c->o.w_ref[q] : 0.0;
   g.sw = c->o.switch_mode;
+  g.flux = c->o.flux;
   return g;
 }
 
@@ -511,6 +512,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   const hfd_opts& op = c->o;
   if (!(op.gamma > 1.0) || op.mu < 0.0 || !(op.weno_eps > 0.0) || op.w3_cap < 0.0 ||
       op.switch_mode < 0 || op.switch_mode > 2 || op.precision < 0 || op.precision > 1 ||
+      op.flux < HFD_FLUX_RUSANOV || op.flux > HFD_FLUX_HLLC ||
       op.period[0] < 0.0 || op.period[1] < 0.0 ||
       (op.mu > 0.0 && (!(op.prandtl > 0.0) || !(op.gas_R > 0.0)))) {
     c->err = "invalid options";
@@ -748,6 +750,15 @@ hfd_status hfd_set_precision(hfd_ctx* c, int32_t precision, const double* w_ref)
   return HFD_OK;
 }
 
+hfd_status hfd_set_flux(hfd_ctx* c, int32_t flux) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (flux < HFD_FLUX_RUSANOV || flux > HFD_FLUX_HLLC)
+    return fail(c, HFD_E_INVAL, "flux must be HFD_FLUX_RUSANOV, HFD_FLUX_ROE or HFD_FLUX_HLLC");
+  c->o.flux = flux;
+  return HFD_OK;
+}
+
 hfd_status hfd_residual(hfd_ctx* c, const double* U, double* dU, void* stream) {
   hfd_status s = need_device(c);
   if (s) return s;
@@ -830,6 +841,8 @@ hfd_status hfd_adjoint_residual(hfd_ctx* c, const double* U, const double* lam, 
   if (s) return s;
   if (!U || !lam || !out) return fail(c, HFD_E_INVAL, "null pointer");
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
+  if (c->o.flux != HFD_FLUX_RUSANOV)
+    return fail(c, HFD_E_STATE, "the adjoint covers the Rusanov flux only");
   if ((s = ensure_adjoint(c))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto& B = c->b64;
@@ -848,6 +861,8 @@ hfd_status rk_step_adjoint_impl(hfd_ctx* c, const double* U, const double* U1in,
   if (s) return s;
   if (!U || !lam_np1 || !lam_n) return fail(c, HFD_E_INVAL, "null pointer");
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
+  if (c->o.flux != HFD_FLUX_RUSANOV)
+    return fail(c, HFD_E_STATE, "the adjoint covers the Rusanov flux only");
   if ((s = ensure_adjoint(c))) return s;
   const hfd::HostSetup& h = c->hs;
   const int64_t nv = h.nv, ne = h.ne, no = h.n_owned, n12 = 12 * nv;

@@ -63,6 +63,7 @@ struct GasParams {
   double eps, sw_lo, sw_hi;
   double wref[4];   // FP32 form: reference state (zero in the FP64 form)
   int sw;           // hfd_switch
+  int flux;         // hfd_flux
 };
 
 // Coefficients of the edge kernel, one precision.

@@ -103,7 +103,8 @@ struct Ref {
 template <class T>
 __device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
                                  T g[4], T* p_full = nullptr, T* rho_full = nullptr,
-                                 T* u_full = nullptr, T* v_full = nullptr) {
+                                 T* u_full = nullptr, T* v_full = nullptr,
+                                 T* p_pert = nullptr) {
   const T rho = R.w[0] + wp[0];
   const T m = R.w[1] + wp[1];
   const T n = R.w[2] + wp[2];
@@ -131,6 +132,7 @@ __device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
     *u_full = u;
     *v_full = v;
   }
+  if (p_pert) *p_pert = pp;
 }
 
 template <class T>
@@ -169,6 +171,7 @@ __device__ inline int64_t xcd_block() {
 template <class T>
 struct Frame {
   T L[4][4], R[4][4];
+  T un, c;  // normal velocity and sound speed of the Roe state
 };
 
 template <class T>
@@ -197,7 +200,8 @@ __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
       {{T(1), T(1), T(1), T(0)},
        {u - cc * nx, u, u + cc * nx, -ny},
        {v - cc * ny, v, v + cc * ny, nx},
-       {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}}};
+       {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}},
+      un, cc};
 }
 
 // Switch of one characteristic component q of side s: the WENO5 smoothness
@@ -304,6 +308,97 @@ __device__ inline void rusanov(const T wl[4], const T wr[4], T nx, T ny, const R
   for (int q = 0; q < 4; ++q)
     h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
            T(0.5) * lam * (wr[q] - wl[q]);
+}
+
+// Roe's flux at the Roe average of the two interface states, with Harten's
+// entropy fix on the acoustic waves (|lambda| < d -> (lambda^2 + d^2)/(2 d),
+// d = 0.1 (|u.n| + c)); the dissipation acts on w_R - w_L, which the
+// perturbation form gives exactly.
+template <class T>
+__device__ inline void roe_flux(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                                T gm1, T h[4]) {
+  T fl[4], gl[4], fr[4], gr[4];
+  pert_flux<T>(wl, ref, gm1, fl, gl);
+  pert_flux<T>(wr, ref, gm1, fr, gr);
+  const Frame<T> F = roe_frame<T>(V4<T>{wl[0], wl[1], wl[2], wl[3]},
+                                  V4<T>{wr[0], wr[1], wr[2], wr[3]}, nx, ny, ref, gm1);
+  const T d = T(0.1) * (fabs(F.un) + F.c);
+  const T lam[4] = {F.un - F.c, F.un, F.un + F.c, F.un};
+  T al[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    al[k] = fabs(lam[k]);
+    if ((k == 0 || k == 2) && al[k] < d) al[k] = fdiv(lam[k] * lam[k] + d * d, T(2) * d);
+  }
+  const T dw[4] = {wr[0] - wl[0], wr[1] - wl[1], wr[2] - wl[2], wr[3] - wl[3]};
+  T a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    a[k] = al[k] * (F.L[k][0] * dw[0] + F.L[k][1] * dw[1] + F.L[k][2] * dw[2] + F.L[k][3] * dw[3]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
+           T(0.5) * (F.R[q][0] * a[0] + F.R[q][1] * a[1] + F.R[q][2] * a[2] + F.R[q][3] * a[3]);
+}
+
+// Toro's HLLC flux with the Davis-Einfeldt wave speeds (Roe state).  In the
+// perturbation form the star-state jumps U*_K - U_K are written so that no
+// large terms cancel: with g = (S_M - u_nK)/(S_K - S_M) and f = 1 + g,
+//   rho* - rho = g rho,  m* - m = g m + f rho (S_M - u_nK) n,
+//   E* - E = g E + f rho (S_M - u_nK)(S_M + p/(rho (S_K - u_nK))),
+// and pressure differences are taken from the perturbations.
+template <class T>
+__device__ inline void hllc_flux(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                                 T gam, T gm1, T h[4]) {
+  T fl[4], gl[4], fr[4], gr[4], pl, rl, ul, vl, pr, rr, ur, vr, ppl, ppr;
+  pert_flux<T>(wl, ref, gm1, fl, gl, &pl, &rl, &ul, &vl, &ppl);
+  pert_flux<T>(wr, ref, gm1, fr, gr, &pr, &rr, &ur, &vr, &ppr);
+  const Frame<T> F = roe_frame<T>(V4<T>{wl[0], wl[1], wl[2], wl[3]},
+                                  V4<T>{wr[0], wr[1], wr[2], wr[3]}, nx, ny, ref, gm1);
+  const T unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
+  const T cl = fsqrt(fdiv(gam * pl, rl)), cr = fsqrt(fdiv(gam * pr, rr));
+  const T sl = fmin(unl - cl, F.un - F.c), sr = fmax(unr + cr, F.un + F.c);
+  const T sm = fdiv((ppr - ppl) + rl * unl * (sl - unl) - rr * unr * (sr - unr),
+                    rl * (sl - unl) - rr * (sr - unr));
+  T Fn[4];
+  const T* w;
+  T rho, u, v, p, un, sk;
+  // regions in the order: left of S_L, S_L..S_M, S_M..S_R, right of S_R
+  if (sl >= T(0)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = fl[q] * nx + gl[q] * ny;
+    return;
+  }
+  if (sm < T(0) && sr < T(0)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = fr[q] * nx + gr[q] * ny;
+    return;
+  }
+  if (sm >= T(0)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Fn[q] = fl[q] * nx + gl[q] * ny;
+    w = wl, rho = rl, u = ul, v = vl, p = pl, un = unl, sk = sl;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Fn[q] = fr[q] * nx + gr[q] * ny;
+    w = wr, rho = rr, u = ur, v = vr, p = pr, un = unr, sk = sr;
+  }
+  const T dm = sm - un;
+  const T g = fdiv(dm, sk - sm), f = T(1) + g;
+  const T E = ref.w[3] + w[3];
+  const T dU[4] = {g * rho, g * rho * u + f * rho * dm * nx, g * rho * v + f * rho * dm * ny,
+                   g * E + f * rho * dm * (sm + fdiv(p, rho * (sk - un)))};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) h[q] = Fn[q] + sk * dU[q];
+}
+
+// The configured Riemann flux (hfd_flux; uniform across the launch).
+template <class T>
+__device__ inline void riemann(int kind, const T wl[4], const T wr[4], T nx, T ny,
+                               const Ref<T>& ref, T gam, T gm1, T h[4]) {
+  if (kind == HFD_FLUX_ROE) roe_flux<T>(wl, wr, nx, ny, ref, gm1, h);
+  else if (kind == HFD_FLUX_HLLC) hllc_flux<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+  else rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
 }
 
 template <class T>
@@ -422,7 +517,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     bits |= b;
   }
   T h[4];
-  rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+  riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, true, true);
 }
 
@@ -486,7 +581,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   }
   bits |= uint8_t(__shfl_xor(int(bits), 1));
   T h[4];
-  rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+  riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, s == 0, s == 1);
 }
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhfd.so")
 
 HFD_FP64, HFD_FP32_MIXED = 0, 1
 SWITCH = {"paper": 0, "smooth": 1, "weno": 2}
+FLUX = {"rusanov": 0, "roe": 1, "hllc": 2}
 ORDER = {"none": 0, "hilbert": 1}
 STATUS = {0: "HFD_OK", 1: "HFD_E_INVAL", 2: "HFD_E_MESH", 3: "HFD_E_NOMEM",
           4: "HFD_E_DEVICE", 5: "HFD_E_NUMERIC", 6: "HFD_E_STATE"}
@@ -36,7 +37,8 @@ class Opts(ctypes.Structure):
                 ("sw_hi", ctypes.c_double), ("w3_cap", ctypes.c_double),
                 ("period", ctypes.c_double * 2), ("w_ref", ctypes.c_double * 4),
                 ("switch_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("order", ctypes.c_int32), ("flux", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +80,7 @@ SIGNATURES = {
     "hfd_export_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "hfd_import_weights": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "hfd_set_precision": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "hfd_set_flux": (ctypes.c_int, [_P, ctypes.c_int32]),
     "hfd_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "hfd_rk_step": (ctypes.c_int, [_P, _P, _D, _P]),
     "hfd_rk_step_dev": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -143,6 +146,8 @@ def default_opts(**kw):
             o.switch_mode = SWITCH[v] if isinstance(v, str) else int(v)
         elif k == "order":
             o.order = ORDER[v] if isinstance(v, str) else int(v)
+        elif k == "flux":
+            o.flux = FLUX[v] if isinstance(v, str) else int(v)
         elif k == "precision":
             o.precision = {"fp64": 0, "fp32": 1}[v] if isinstance(v, str) else int(v)
         elif k in ("period", "w_ref"):
@@ -271,6 +276,12 @@ class Solver:
         self._chk(lib().hfd_set_precision(self._h, int(p), _ptr(wr)))
         self.opts.precision = int(p)
         self.refresh_info()
+
+    def set_flux(self, flux):
+        """Riemann flux of later calls: "rusanov", "roe" or "hllc"."""
+        f = FLUX[flux] if isinstance(flux, str) else int(flux)
+        self._chk(lib().hfd_set_flux(self._h, f))
+        self.opts.flux = f
 
     # -- hot path -------------------------------------------------------------------
     def residual(self, U, out=None):
