@@ -257,7 +257,23 @@ def adjoint_ratio(steps=200, ckpt=20):
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     S.check()
+    # the binomial schedule with 10 snapshot slots (memory: 10 states and one
+    # step's stages, against 10 + 3 x 20 for the uniform schedule)
+    from paper_2109_01286_amd.adjoint import RKStepsRevolve
+    U0 = Ud.clone().requires_grad_(True)
+    Jr = pressure_disk_objective(rk_steps(U0, S, steps, dt, snapshots=10), xy, (7.0, 7.0), 1.0,
+                                 area)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    (gr,) = torch.autograd.grad(Jr, U0)
+    torch.cuda.synchronize()
+    t_rev = time.perf_counter() - t0
+    revolve = {"snapshots": 10, "backward_ms": t_rev * 1e3,
+               "adjoint_over_forward": t_rev / t_fwd,
+               "backward_forward_steps": RKStepsRevolve.last_stats["forward_steps"],
+               "grad_equal_to_uniform": bool(torch.equal(gr, g))}
     return {"workload": "vortex257", "steps": steps, "ckpt_every": ckpt, "dtype": "f64",
+            "binomial": revolve,
             "switch": "weno", "forward_ms": t_fwd * 1e3,
             "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
             "adjoint_setup_ms": t_setup * 1e3,

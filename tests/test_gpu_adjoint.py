@@ -140,6 +140,26 @@ def test_adjoint_from_saved_stages_equals_recompute():
     assert torch.equal(a, b)
 
 
+def test_binomial_checkpointing_equals_uniform():
+    """The binomial schedule (3 snapshot slots) and the uniform one run the
+    same float64 steps and adjoint steps: the gradients agree bit for bit."""
+    from paper_2109_01286_amd.adjoint import RKStepsRevolve, revolve_cost, revolve_spine, rk_steps
+    m, U, sc, S, sw = setup_case("vortex21", force=False, switch="smooth")
+    dt = 0.5 * sc.stable_dt(U, 0.3)
+    rng = np.random.default_rng(8)
+    lam = torch.as_tensor(S.to_internal(rng.standard_normal(U.shape)), device=DEV)
+    grads = []
+    for kw in (dict(ckpt_every=5), dict(snapshots=3)):
+        U0 = torch.as_tensor(S.to_internal(U), device=DEV).requires_grad_(True)
+        out = rk_steps(U0, S, 12, dt, **kw)
+        (g,) = torch.autograd.grad(out, U0, lam)
+        grads.append(g)
+    assert torch.equal(grads[0], grads[1])
+    st = RKStepsRevolve.last_stats
+    assert st["forward_steps"] == revolve_cost(12, 3) - revolve_spine(12, 3)[-1] + 12
+    assert st["peak_snapshots"] <= 3
+
+
 def test_viscous_adjoint_is_refused():
     m, _, _ = inputs.workload("tgv513", 9)
     S = lib_solver(m, 0, mu=0.01)
