@@ -5,9 +5,10 @@ callers.  It holds no arithmetic of the numerical method itself: it only
 generates meshes (jittered, randomly split lattices that stand in for the
 Delaunay meshes of the paper's test cases) and evaluates closed-form
 initial conditions (isentropic vortex of the paper's Section 3.1, a
-four-quadrant 2D Riemann problem, a decaying Taylor-Green vortex and a
-Mach 1.1 normal shock with an upstream vortex) together with their exact
-spatial derivatives, because the method evolves w, w_x and w_y.
+four-quadrant 2D Riemann problem, a decaying Taylor-Green vortex, a
+Mach 1.1 normal shock with an upstream vortex, and the steady Couette flow
+of Section 3.2) together with their exact spatial derivatives, because the
+method evolves w, w_x and w_y.
 
 State layout everywhere: ``U[12, V]`` float64, rows ``q + 4*k`` with
 ``q`` = (rho, rho*u, rho*v, E) and ``k`` = (value, d/dx, d/dy).
@@ -269,6 +270,29 @@ def taylor_green(mesh: Mesh, gamma=1.4, mach=0.1, rho0=1.0, U0=1.0, R=1.0,
     return prim_to_state(gamma, rho, u, v, p, drho, du, dv, dp)
 
 
+def couette(mesh: Mesh, L=10.0, y0=5.0, u0=0.5, T_top=1.5, T_bottom=1.0, p=1.0,
+            mu=0.1, K=0.01, cp=10.0, gamma=1.4):
+    """Steady compressible Couette flow between the planes y - y0 = -L/2 and
+    +L/2 (Section 3.2): u = 2 y' u0 / L, v = 0, constant p,
+    T = (1/K) (-2 mu u0^2 y'^2 / L^2 + C1 y' + C0) with C1 = K (T_top -
+    T_bottom)/L, C0 = (K (T_top + T_bottom) + mu u0^2)/2 (y' = y - y0; the
+    sign of the printed C1, C0 taken so that T takes the wall values), and
+    rho = gamma p / ((gamma - 1) cp T) = p / (R T).  Exact derivatives."""
+    R = cp * (gamma - 1.0) / gamma
+    y = mesh.xy[:, 1] - y0
+    C1 = K * (T_top - T_bottom) / L
+    C0 = 0.5 * (K * (T_top + T_bottom) + mu * u0 * u0)
+    T = (-2.0 * mu * u0 * u0 * y * y / (L * L) + C1 * y + C0) / K
+    Ty = (-4.0 * mu * u0 * u0 * y / (L * L) + C1) / K
+    rho = p / (R * T)
+    zero = np.zeros_like(y)
+    u = 2.0 * y * u0 / L
+    drho = (zero, -rho / T * Ty)
+    du = (zero, np.full_like(y, 2.0 * u0 / L))
+    return prim_to_state(gamma, rho, u, zero, np.full_like(y, p), drho, du, (zero, zero),
+                         (zero, zero))
+
+
 def normal_shock_states(mach, gamma=1.4, rho1=1.0, p1=1.0):
     """Upstream/downstream (rho, u, v, p) of a stationary normal shock
     (Rankine-Hugoniot relations)."""
@@ -367,6 +391,16 @@ def workload(name, scale=None):
                           dirichlet_sides=("xlo",))
         U = shock_vortex(m)
         prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=10)
+    elif name == "couette":
+        # x periodic on [0, 10), walls at y = 0 and 10 with Dirichlet ghost
+        # regions holding the exact solution (the paper's ghost regions)
+        n = scale or 141
+        m = jittered_grid(n, n, 10.0, 10.0, (True, False), 5, seed=6,
+                          dirichlet_sides=("ylo", "yhi"))
+        U = couette(m)
+        gamma, cp, K, mu = 1.4, 10.0, 0.01, 0.1
+        prm = dict(gamma=gamma, mu=mu, prandtl=mu * cp / K, gas_R=cp * (gamma - 1.0) / gamma,
+                   switch="smooth", cfl=0.3, steps=20)
     else:
         raise KeyError(name)
     return m, U, prm

@@ -27,6 +27,7 @@ CASES = {
     "riemann": ("riemann201", 25, {"w3_cap": 2.0}, "weno"),
     "shockvortex": ("shockvortex2049", 25, {"w3_cap": 2.0}, "paper"),
     "tgv": ("tgv513", 25, {"mu": 0.01}, "smooth"),
+    "couette": ("couette", 31, {"mu": 0.1, "prandtl": 100.0, "gas_R": 20.0 / 7.0}, "smooth"),
 }
 
 
@@ -137,8 +138,16 @@ def test_rk_step_fp64_with_oracle_weights(key):
     assert abs(gdt.item() - dt) <= 1e-14 * dt
     P.S.rk_step(Ud, gdt)
     got = P.host(Ud)
-    # state after one step: 1e-12 relative per block
-    assert block_rel_err(got, ref, P.owned) <= 1e-12
+    # state after one step: 1e-12 relative per block, for the blocks that are
+    # not identically zero at the start (such a block, e.g. the x-gradient of
+    # the Couette flow, which depends on y only, is one step's increment and
+    # is checked with the increment below)
+    for k in range(3):
+        x0 = P.U[4 * k:4 * k + 4][:, P.owned]
+        if np.any(x0 != 0.0):
+            x, y = got[4 * k:4 * k + 4][:, P.owned], ref[4 * k:4 * k + 4][:, P.owned]
+            f = same_nans(x, y)
+            assert np.linalg.norm((x - y)[f]) <= 1e-12 * np.linalg.norm(y[f])
     # the increment dt * R itself, with the rounding scale of the residual
     scale = dt * cancellation_scale(P.sc, P.U, P.sw)
     q = residual_within(got - P.U, ref - P.U, scale, P.owned, rel=1e-11)
@@ -161,13 +170,13 @@ def test_residual_with_gpu_weights_close_to_oracle():
     assert block_rel_err(got, ref, P.owned) <= 1e-7
 
 
-# Euler configurations: 1e-5 relative.  The low-Mach viscous case is bounded
-# by float32 rounding of the energy flux (E + p) u ~ 250 u, whose divergence
-# is nearly zero: relative error ~ eps32 * 250 |u| * sum|d0| / |dE/dt| ~ 1e-3.
-MIXED_TOL = {"vortex21": 1e-5, "shockvortex": 1e-5, "riemann": 1e-5, "tgv": 2e-3}
-
-
-@pytest.mark.parametrize("key", ["vortex21", "shockvortex", "riemann", "tgv"])
+# 1e-5 relative, or float32 rounding of the divergence dot products where
+# large fluxes nearly cancel: the low-Mach viscous Taylor-Green vortex (energy
+# flux (E + p) u ~ 250 u with a nearly zero divergence) and the Couette flow
+# at its exact steady state (the residual is only the truncation error).
+# Same form as the float64 bound, at float32 rounding: 2e-7 (about 3 units
+# of float32 rounding) of sum |coefficient| |flux|.
+@pytest.mark.parametrize("key", ["vortex21", "shockvortex", "riemann", "tgv", "couette"])
 def test_mixed_precision_residual(key):
     P = pair(key)
     P.import_oracle()
@@ -180,8 +189,12 @@ def test_mixed_precision_residual(key):
         P.S.force_switch_mask(torch.as_tensor(mask.numpy()[P.ow["pos"]], device=DEV))
         got = P.host(P.S.residual(P.dev(U)))
         err = block_rel_err(got, ref, P.owned)
-        print(f"[parity] {key} mixed-precision residual rel err {err:.2e}")
-        assert err <= MIXED_TOL[key]
+        q = residual_within(got, ref, cancellation_scale(P.sc, U, P.sw), P.owned,
+                            rel=1e-5, abs_rel=2e-7)
+        print(f"[parity] {key} mixed-precision residual rel err {err:.2e}, tolerance use {q:.2f}")
+        assert q <= 1.0
+        if key in ("vortex21", "shockvortex", "riemann"):
+            assert err <= 1e-5    # no cancellation: the relative bound alone
     finally:
         P.S.force_switch_mask(None)
         P.S.set_precision("fp64")
