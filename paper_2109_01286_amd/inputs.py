@@ -293,6 +293,18 @@ def couette(mesh: Mesh, L=10.0, y0=5.0, u0=0.5, T_top=1.5, T_bottom=1.0, p=1.0,
                          (zero, zero))
 
 
+def circular_sod(mesh: Mesh, center=(1.0, 1.0), radius=0.5, gamma=1.4,
+                 inner=(1.0, 0.0, 0.0, 1.0), outer=(0.125, 0.0, 0.0, 0.1)):
+    """Circular Sod problem (Section 3.3): (rho, u, v, p) = ``inner`` for
+    |x - c| < r, ``outer`` elsewhere, zero gradients."""
+    d = mesh.xy - np.asarray(center)[None, :]
+    inside = (d * d).sum(axis=1) < radius * radius
+    S = np.where(inside[:, None], np.asarray(inner)[None, :], np.asarray(outer)[None, :])
+    z = np.zeros(mesh.nv)
+    return prim_to_state(gamma, S[:, 0], S[:, 1], S[:, 2], S[:, 3], (z, z), (z, z), (z, z),
+                         (z, z))
+
+
 def normal_shock_states(mach, gamma=1.4, rho1=1.0, p1=1.0):
     """Upstream/downstream (rho, u, v, p) of a stationary normal shock
     (Rankine-Hugoniot relations)."""
@@ -401,6 +413,12 @@ def workload(name, scale=None):
         gamma, cp, K, mu = 1.4, 10.0, 0.01, 0.1
         prm = dict(gamma=gamma, mu=mu, prandtl=mu * cp / K, gas_R=cp * (gamma - 1.0) / gamma,
                    switch="smooth", cfl=0.3, steps=20)
+    elif name == "sod_circle":
+        # the 2 x 2 square of the paper's circular Sod problem, transmissive
+        n = scale or 101
+        m = jittered_grid(n, n, 2.0, 2.0, (False, False), 5, seed=7)
+        U = circular_sod(m)
+        prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=40, t_end=0.2)
     else:
         raise KeyError(name)
     return m, U, prm
