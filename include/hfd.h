@@ -86,7 +86,11 @@ typedef struct hfd_opts {
   int32_t precision;   /* hfd_precision                                   */
   int32_t order;       /* hfd_order: vertex renumbering                   */
   int32_t flux;        /* hfd_flux                                        */
-  int32_t reserved[4];
+  int32_t stage_off;   /* nonzero: the vertex pass gathers every slot's
+                          neighbour data from HBM instead of staging each
+                          block's distinct rows and fluxes in LDS (same
+                          results bit for bit)                            */
+  int32_t reserved[3];
 } hfd_opts;
 
 typedef struct hfd_info {
@@ -113,6 +117,13 @@ typedef struct hfd_info {
    * 0 when the rows are always read and counted there. */
   double bytes_edge_w3_side;
   double setup_ms[4];    /* host setup, upload, GPU precompute, total       */
+  /* Vertex pass: bytes of a slot's local id when each block of 16 owned
+   * vertices stages its distinct state rows and edge fluxes in LDS (1 or 2),
+   * 0 when every slot gathers from HBM; the longest such lists. */
+  int32_t stage_idx_bytes;
+  int32_t stage_max_rows;
+  int32_t stage_max_edges;
+  int32_t reserved_info;
 } hfd_info;
 
 /* Default options: gamma 1.4, R 1, mu 0, Pr 0.72, eps 1e-6, (0.01, 0.79),

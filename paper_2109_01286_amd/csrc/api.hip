@@ -13,6 +13,12 @@
 #include "kernels.h"
 #include "setup.h"
 
+// Stage a vertex-pass block's neighbour data in LDS (0: gather every slot
+// from HBM).
+#ifndef HFD_VERTEX_STAGE
+#define HFD_VERTEX_STAGE 1
+#endif
+
 using hfd::GasParams;
 
 struct hfd_ctx {
@@ -30,6 +36,17 @@ struct hfd_ctx {
   int8_t* trunc3 = nullptr;
   int32_t *vptr = nullptr, *eptr = nullptr, *vg = nullptr, *ve = nullptr;
   double *dv = nullptr, *de = nullptr, *dvis = nullptr;
+  // LDS staging lists of the vertex pass (host copies live until upload)
+  struct Stage {
+    std::vector<int32_t> rp, rows, ep, edges;
+    std::vector<uint16_t> vloc, eloc;
+    std::vector<uint32_t> base;
+    int max_rows = 0, max_edges = 0, idx_bytes = 0;
+    int64_t list_ints = 0;  // 4-byte entries of rp, rows, ep, edges and base
+  } stage;
+  int32_t *hrp = nullptr, *hrow = nullptr, *hep = nullptr, *hedge = nullptr;
+  uint32_t* lbase = nullptr;
+  void *vloc = nullptr, *eloc = nullptr;
   double* hmin = nullptr;
   int32_t *dir_rows = nullptr, *copy_rows = nullptr, *copy_src = nullptr;
   // float32 copies (mixed form)
@@ -132,6 +149,76 @@ GasParams gas_params(const hfd_ctx* c, bool mixed) {
 
 bool mixed(const hfd_ctx* c) { return c->o.precision == HFD_FP32_MIXED; }
 
+// One staging list family: for each block of kStageVertices owned vertices
+// (slots ptr[v0] .. ptr[v0 + 16]), the sorted distinct ids its slots name
+// (list[bp[b] .. bp[b+1])); per vertex the first list position among its
+// slots (base), per slot its position minus its vertex's base (loc).
+// longest: longest list; span: largest loc + 1.
+void stage_lists(const std::vector<int64_t>& ptr, const std::vector<int32_t>& ids,
+                 int64_t nid, int64_t nowned, std::vector<int32_t>& bp,
+                 std::vector<int32_t>& list, std::vector<uint16_t>& base,
+                 std::vector<uint16_t>& loc, int& longest, int& span) {
+  const int64_t vpb = hfd::kStageVertices, nb = (nowned + vpb - 1) / vpb;
+  std::vector<int32_t> seen(size_t(nid), -1), pos(size_t(nid), 0);
+  std::vector<int32_t> blk;
+  bp.assign(size_t(nb + 1), 0);
+  base.assign(size_t(nowned), 0);
+  loc.assign(ids.size(), 0);
+  list.clear();
+  longest = span = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t v0 = b * vpb, v1 = std::min(nowned, v0 + vpb);
+    blk.clear();
+    for (int64_t k = ptr[v0]; k < ptr[v1]; ++k) {
+      const int32_t u = ids[k];
+      if (seen[u] != int32_t(b)) {
+        seen[u] = int32_t(b);
+        blk.push_back(u);
+      }
+    }
+    std::sort(blk.begin(), blk.end());
+    for (size_t k = 0; k < blk.size(); ++k) pos[blk[k]] = int32_t(k);
+    for (int64_t v = v0; v < v1; ++v) {
+      int32_t lo = INT32_MAX;
+      for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) lo = std::min(lo, pos[ids[k]]);
+      if (ptr[v + 1] == ptr[v]) lo = 0;
+      base[v] = uint16_t(lo);
+      for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+        loc[k] = uint16_t(pos[ids[k]] - lo);
+        span = std::max(span, pos[ids[k]] - lo + 1);
+      }
+    }
+    list.insert(list.end(), blk.begin(), blk.end());
+    bp[b + 1] = int32_t(list.size());
+    longest = std::max(longest, int(blk.size()));
+  }
+}
+
+// Staging lists of the vertex pass, kept when a block's data fits in LDS
+// (float32 values, gradients with viscosity, and fluxes).  Local ids take
+// one byte when every vertex's slots span at most 256 list positions.
+void build_stage(hfd_ctx* c) {
+  auto& g = c->stage;
+  g = hfd_ctx::Stage{};
+  const hfd::HostSetup& h = c->hs;
+  if (!HFD_VERTEX_STAGE || c->o.stage_off || h.n_owned == 0) return;
+  std::vector<uint16_t> rb, eb;
+  int rspan = 0, espan = 0;
+  stage_lists(h.vptr, h.v_gather, h.nv, h.n_owned, g.rp, g.rows, rb, g.vloc, g.max_rows, rspan);
+  stage_lists(h.eptr, h.v_edges, std::max<int64_t>(h.ne, 1), h.n_owned, g.ep, g.edges, eb,
+              g.eloc, g.max_edges, espan);
+  const int64_t lds = ((c->o.mu > 0.0 ? 3 : 1) * int64_t(g.max_rows) + g.max_edges) * 16;
+  if (lds > 48 * 1024 || g.max_rows > 65536 || g.max_edges > 65536) {
+    g = hfd_ctx::Stage{};
+    return;
+  }
+  g.base.resize(size_t(h.n_owned));
+  for (int64_t v = 0; v < h.n_owned; ++v) g.base[v] = uint32_t(rb[v]) | (uint32_t(eb[v]) << 16);
+  g.idx_bytes = (rspan <= 256 && espan <= 256) ? 1 : 2;
+  g.list_ints = int64_t(g.rp.size() + g.ep.size() + g.rows.size() + g.edges.size() +
+                        g.base.size());
+}
+
 void byte_model(hfd_ctx* c) {
   hfd_info& I = c->info;
   const double s = mixed(c) ? 4.0 : 8.0;
@@ -149,9 +236,19 @@ void byte_model(hfd_ctx* c) {
   // averaged over the three stages: U^n read and U^new written every stage,
   // U^k read in stages 2 and 3, gather-layout copy written in stages 1 and 2
   double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + (2.0 / 3.0) * 12 * s);
-  I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (4 + 6 * s + visc * 5 * s) +
-                          double(I.n_eslots) * (4 + 3 * s) + nv * (4 + 8 * visc) * s +
-                          ne * 4 * s + rk;
+  // slot ids: 4-byte global ids, or 1/2-byte local ids plus the per-block
+  // lists of distinct rows and edges and the per-vertex bases when the
+  // block's data is staged in LDS (float32 form)
+  const auto& g = c->stage;
+  const bool staged = g.idx_bytes && mixed(c);
+  I.stage_idx_bytes = staged ? g.idx_bytes : 0;
+  I.stage_max_rows = staged ? g.max_rows : 0;
+  I.stage_max_edges = staged ? g.max_edges : 0;
+  const double ib = staged ? double(g.idx_bytes) : 4.0;
+  const double lists = staged ? double(g.list_ints) * 4 : 0.0;
+  I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (ib + 6 * s + visc * 5 * s) +
+                          double(I.n_eslots) * (ib + 3 * s) + nv * (4 + 8 * visc) * s +
+                          ne * 4 * s + rk + lists;
 }
 
 template <class T>
@@ -187,10 +284,18 @@ hfd_status ensure_mixed_buffers(hfd_ctx* c) {
 hfd::EdgeCoef<double> ecoef64(const hfd_ctx* c) { return {c->stg, c->n, c->w5, c->w3}; }
 hfd::EdgeCoef<float> ecoef32(const hfd_ctx* c) { return {c->stg, c->fn, c->fw5, c->fw3}; }
 hfd::VertexCoef<double> vcoef64(const hfd_ctx* c) {
-  return {c->vptr, c->eptr, c->vg, c->ve, c->dv, c->de, c->dvis};
+  const auto& g = c->stage;
+  return {c->vptr, c->eptr, c->vg,   c->ve,   c->dv,        c->de,       c->dvis,
+          c->hrp,  c->hrow, c->hep,  c->hedge, c->lbase,    c->vloc,     c->eloc,
+          g.idx_bytes,
+          g.max_rows, g.max_edges};
 }
 hfd::VertexCoef<float> vcoef32(const hfd_ctx* c) {
-  return {c->vptr, c->eptr, c->vg, c->ve, c->fdv, c->fde, c->fdvis};
+  const auto& g = c->stage;
+  return {c->vptr, c->eptr, c->vg,   c->ve,   c->fdv,       c->fde,      c->fdvis,
+          c->hrp,  c->hrow, c->hep,  c->hedge, c->lbase,    c->vloc,     c->eloc,
+          g.idx_bytes,
+          g.max_rows, g.max_edges};
 }
 
 hfd_status need_device(const hfd_ctx* c) {
@@ -544,6 +649,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
              std::to_string(h.max_vs) + " stencil vertices (limit 64)";
     return bail(HFD_E_MESH);
   }
+  build_stage(c);
   byte_model(c);
   if (device < 0) {
     *out = c;
@@ -575,6 +681,33 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
       (s = upload(c, &d_mnrm, h.m_nrm)) || (s = upload(c, &d_vh, h.v_h)) ||
       (s = upload(c, &d_vptr64, h.vptr)) || (s = upload(c, &d_eptr64, h.eptr)))
     return bail(s);
+  if (c->stage.idx_bytes) {
+    auto& g = c->stage;
+    if ((s = upload(c, &c->hrp, g.rp)) || (s = upload(c, &c->hrow, g.rows)) ||
+        (s = upload(c, &c->hep, g.ep)) || (s = upload(c, &c->hedge, g.edges)) ||
+        (s = upload(c, &c->lbase, g.base)))
+      return bail(s);
+    if (g.idx_bytes == 1) {
+      std::vector<uint8_t> v8(g.vloc.begin(), g.vloc.end()), e8(g.eloc.begin(), g.eloc.end());
+      uint8_t *pv = nullptr, *pe = nullptr;
+      if ((s = upload(c, &pv, v8)) || (s = upload(c, &pe, e8))) return bail(s);
+      c->vloc = pv;
+      c->eloc = pe;
+    } else {
+      uint16_t *pv = nullptr, *pe = nullptr;
+      if ((s = upload(c, &pv, g.vloc)) || (s = upload(c, &pe, g.eloc))) return bail(s);
+      c->vloc = pv;
+      c->eloc = pe;
+    }
+    // the host copies are not needed any more (the byte model keeps list_ints)
+    std::vector<int32_t>().swap(g.rp);
+    std::vector<int32_t>().swap(g.rows);
+    std::vector<int32_t>().swap(g.ep);
+    std::vector<int32_t>().swap(g.edges);
+    std::vector<uint32_t>().swap(g.base);
+    std::vector<uint16_t>().swap(g.vloc);
+    std::vector<uint16_t>().swap(g.eloc);
+  }
   if ((s = dalloc(c, &c->w5, 30 * ne)) || (s = dalloc(c, &c->w3, 18 * ne)) ||
       (s = dalloc(c, &c->rank, 2 * ne)) || (s = dalloc(c, &c->trunc3, 6 * ne)) ||
       (s = dalloc(c, &c->dv, 6 * nvs)) || (s = dalloc(c, &c->de, 3 * nes)) ||

@@ -84,7 +84,27 @@ struct VertexCoef {
   const T* dv;             // [n_vslots][6]
   const T* de;             // [n_eslots][3]
   const T* dvis;           // [n_vslots][5] or null
+  // Staging of a block's neighbour data in LDS (idx_bytes 1 or 2; 0 = every
+  // slot gathers from HBM through vg/ve; float32 only).  Per block of 16
+  // owned vertices: its distinct gather rows hrow[hrp[b] .. hrp[b+1]) and
+  // distinct edges hedge[hep[b] .. hep[b+1]), sorted.  A slot's row (edge)
+  // is at position base + vloc[slot] (eloc) of its block's list, where
+  // lbase[v] = row base | edge base << 16 is the first position among v's
+  // slots; vloc/eloc take idx_bytes bytes.
+  const int32_t* hrp;      // [n_blocks+1]
+  const int32_t* hrow;
+  const int32_t* hep;      // [n_blocks+1]
+  const int32_t* hedge;
+  const uint32_t* lbase;   // [n_owned]
+  const void* vloc;        // [n_vslots]
+  const void* eloc;        // [n_eslots]
+  int idx_bytes;
+  int max_rows, max_edges; // longest lists (LDS size)
 };
+
+// Owned vertices per block of the vertex pass when its neighbour data is
+// staged in LDS.
+constexpr int kStageVertices = 16;
 
 // Gather layout of a stage state: values Gv[nv] and gradients Gg[2 nv]
 // (x then y) as 4-vectors, so that one vertex's data is one or two

@@ -666,7 +666,18 @@ template <> struct VertexWaves<float> { static constexpr int value = HFD_VERTEX_
 template <class T> struct VertexSplit { static constexpr bool value = false; };
 template <> struct VertexSplit<float> { static constexpr bool value = true; };
 
-template <class T, bool VISC>
+// Slot id of a coefficient stream at byte base b, slot r: a global row or
+// edge (IB = 0, int32) or a position in the block's staged list (1 or 2 bytes).
+template <int IB>
+__device__ inline int slot_id(const char* b, uint32_t r) {
+  if constexpr (IB == 0) return *reinterpret_cast<const int32_t*>(b + 4u * r);
+  else if constexpr (IB == 1) return *reinterpret_cast<const uint8_t*>(b + r);
+  else return *reinterpret_cast<const uint16_t*>(b + 2u * r);
+}
+
+extern __shared__ __attribute__((aligned(32))) unsigned char hfd_stage_lds[];
+
+template <class T, bool VISC, int IB>
 __global__ void __launch_bounds__(256, VISC ? 2 : VertexWaves<T>::value)
 k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
          const V4<T>* __restrict__ Gv, const V4<T>* __restrict__ Gg,
@@ -675,6 +686,7 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
          int32_t* __restrict__ flag) {
   constexpr int VL = VertexLanes<T>::value, VPB = 256 / VL;
   static_assert(VL == 8 || VL == 16, "8 or 16 lanes per vertex");
+  static_assert(IB == 0 || VPB == kStageVertices, "staged lists are per 16 vertices");
   // slots per lane and iteration: every load of a batch is issued before any
   // of its data is used
   constexpr int NVS = VL == 16 ? 2 : 3;   // vertex slots
@@ -706,6 +718,47 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
   }
   if (mode == 1) dt = rk.dt_dev ? *rk.dt_dev : rk.dt;
 
+  // Staging: the block's distinct state rows (and gradient rows) and edge
+  // fluxes go to LDS once; the slots then read them by local id.
+  const V4<T>* sV = Gv;
+  const V4<T>* sG = Gg;
+  const V4<T>* sH = H;
+  if constexpr (IB > 0) {
+    V4<T>* lv = reinterpret_cast<V4<T>*>(hfd_stage_lds);
+    V4<T>* lg = lv + c.max_rows;
+    V4<T>* lh = lv + (VISC ? 3 : 1) * c.max_rows;
+    const int64_t b = v0 / VPB;
+    const int r0 = c.hrp[b], nr = c.hrp[b + 1] - r0;
+    const int q0 = c.hep[b], nq = c.hep[b + 1] - q0;
+    // every block has at least one row and one edge (a vertex's own row and
+    // an edge of it): lanes past a list's end load its last entry again and
+    // do not store it
+    const int nk = nr > nq ? nr : nq;
+    for (int k = t; k < nk; k += 256) {
+      const int64_t row = c.hrow[r0 + (k < nr ? k : nr - 1)];
+      const int64_t ed = c.hedge[q0 + (k < nq ? k : nq - 1)];
+      const V4<T> a = Gv[row];
+      V4<T> g0, g1;
+      if (VISC) {
+        g0 = Gg[2 * row];
+        g1 = Gg[2 * row + 1];
+      }
+      const V4<T> hh = H[ed];
+      if (k < nr) {
+        lv[k] = a;
+        if (VISC) {
+          lg[2 * k] = g0;
+          lg[2 * k + 1] = g1;
+        }
+      }
+      if (k < nq) lh[k] = hh;
+    }
+    __syncthreads();
+    sV = lv;
+    sG = lg;
+    sH = lh;
+  }
+
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = T(gp.gamma - 1.0);
   T acc[16];
@@ -721,10 +774,15 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
     // The coefficient streams are addressed from the block's first slots
     // (uniform) with 32-bit byte offsets: one register per address.
     const int sb = c.vptr[v0], eb = c.eptr[v0];
-    const char* vgb = reinterpret_cast<const char*>(c.vg + sb);
+    const char* vgb = IB ? reinterpret_cast<const char*>(c.vloc) + IB * sb
+                         : reinterpret_cast<const char*>(c.vg + sb);
+    // staged: positions in the block's lists are v's base plus the slot's id
+    const uint32_t lb = IB ? c.lbase[v] : 0u;
+    const int rbase = int(lb & 0xffffu), ebase = int(lb >> 16);
     const char* dvb = reinterpret_cast<const char*>(c.dv + int64_t(6) * sb);
     const char* dkb = VISC ? reinterpret_cast<const char*>(c.dvis + int64_t(5) * sb) : nullptr;
-    const char* veb = reinterpret_cast<const char*>(c.ve + eb);
+    const char* veb = IB ? reinterpret_cast<const char*>(c.eloc) + IB * eb
+                         : reinterpret_cast<const char*>(c.ve + eb);
     const char* deb = reinterpret_cast<const char*>(c.de + int64_t(3) * eb);
     if constexpr (VertexSplit<T>::value) {
       // vertex slots, then edge slots: fewer values in flight per wave,
@@ -742,7 +800,7 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
 #pragma unroll
         for (int k = 0; k < NVS; ++k) {
           const uint32_t r = uint32_t(js[k] - sb);
-          u[k] = *reinterpret_cast<const int32_t*>(vgb + 4u * r);
+          u[k] = rbase + slot_id<IB>(vgb, r);
           const Rec<T, 6> dr = *reinterpret_cast<const Rec<T, 6>*>(dvb + uint32_t(6 * sizeof(T)) * r);
 #pragma unroll
           for (int q = 0; q < 6; ++q) d[k][q] = dr.v[q];
@@ -755,10 +813,10 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
         V4<T> A[NVS], G[NVS][2];
 #pragma unroll
         for (int k = 0; k < NVS; ++k) {
-          A[k] = Gv[u[k]];
+          A[k] = sV[u[k]];
           if (VISC) {
-            G[k][0] = Gg[2 * int64_t(u[k])];
-            G[k][1] = Gg[2 * int64_t(u[k]) + 1];
+            G[k][0] = sG[2 * int64_t(u[k])];
+            G[k][1] = sG[2 * int64_t(u[k]) + 1];
           }
         }
 #pragma unroll
@@ -785,14 +843,14 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
 #pragma unroll
         for (int k = 0; k < NES; ++k) {
           const uint32_t r = uint32_t(je[k] - eb);
-          m[k] = *reinterpret_cast<const int32_t*>(veb + 4u * r);
+          m[k] = ebase + slot_id<IB>(veb, r);
           const Rec<T, 3> er = *reinterpret_cast<const Rec<T, 3>*>(deb + uint32_t(3 * sizeof(T)) * r);
 #pragma unroll
           for (int q = 0; q < 3; ++q) de[k][q] = er.v[q];
         }
         V4<T> Hh[NES];
 #pragma unroll
-        for (int k = 0; k < NES; ++k) Hh[k] = H[m[k]];
+        for (int k = 0; k < NES; ++k) Hh[k] = sH[m[k]];
 #pragma unroll
         for (int k = 0; k < NES; ++k) {
           const T w0 = oke[k] ? de[k][0] : T(0), w1 = oke[k] ? de[k][1] : T(0),
@@ -827,7 +885,7 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
 #pragma unroll
         for (int k = 0; k < NVS; ++k) {
           const uint32_t r = uint32_t(js[k] - sb);
-          u[k] = *reinterpret_cast<const int32_t*>(vgb + 4u * r);
+          u[k] = rbase + slot_id<IB>(vgb, r);
           const Rec<T, 6> dr = *reinterpret_cast<const Rec<T, 6>*>(dvb + uint32_t(6 * sizeof(T)) * r);
 #pragma unroll
           for (int q = 0; q < 6; ++q) d[k][q] = dr.v[q];
@@ -840,7 +898,7 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
 #pragma unroll
         for (int k = 0; k < NES; ++k) {
           const uint32_t r = uint32_t(je[k] - eb);
-          m[k] = *reinterpret_cast<const int32_t*>(veb + 4u * r);
+          m[k] = ebase + slot_id<IB>(veb, r);
           const Rec<T, 3> er = *reinterpret_cast<const Rec<T, 3>*>(deb + uint32_t(3 * sizeof(T)) * r);
 #pragma unroll
           for (int q = 0; q < 3; ++q) de[k][q] = er.v[q];
@@ -848,14 +906,14 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
         V4<T> A[NVS], G[NVS][2], Hh[NES];
 #pragma unroll
         for (int k = 0; k < NVS; ++k) {
-          A[k] = Gv[u[k]];
+          A[k] = sV[u[k]];
           if (VISC) {
-            G[k][0] = Gg[2 * int64_t(u[k])];
-            G[k][1] = Gg[2 * int64_t(u[k]) + 1];
+            G[k][0] = sG[2 * int64_t(u[k])];
+            G[k][1] = sG[2 * int64_t(u[k]) + 1];
           }
         }
 #pragma unroll
-        for (int k = 0; k < NES; ++k) Hh[k] = H[m[k]];
+        for (int k = 0; k < NES; ++k) Hh[k] = sH[m[k]];
 #pragma unroll
         for (int k = 0; k < NVS; ++k) {
 #pragma unroll
@@ -1091,12 +1149,28 @@ hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
   if (nowned == 0) return hipSuccess;
   constexpr int VPB = 256 / VertexLanes<T>::value;
   const unsigned nb = nblocks(nowned, VPB);
-  if (c.dvis)
-    hipLaunchKernelGGL((k_vertex<T, true>), dim3(nb), dim3(256), 0, st, nowned, nv, c,
-                       gp, Gv, Gg, H, mode, dU, rk, Gv_new, Gg_new, flag);
-  else
-    hipLaunchKernelGGL((k_vertex<T, false>), dim3(nb), dim3(256), 0, st, nowned, nv, c,
-                       gp, Gv, Gg, H, mode, dU, rk, Gv_new, Gg_new, flag);
+  const size_t lds = c.idx_bytes && sizeof(T) == 4 ? size_t((c.dvis ? 3 : 1) * c.max_rows + c.max_edges) *
+                                       sizeof(V4<T>)
+                                 : 0;
+#define HFD_LAUNCH_VERTEX(V, I)                                                              \
+  hipLaunchKernelGGL((k_vertex<T, V, I>), dim3(nb), dim3(256), lds, st, nowned, nv, c, gp, Gv, \
+                     Gg, H, mode, dU, rk, Gv_new, Gg_new, flag)
+  if constexpr (VPB == kStageVertices && sizeof(T) == 4) {
+    if (c.dvis) {
+      if (c.idx_bytes == 1) HFD_LAUNCH_VERTEX(true, 1);
+      else if (c.idx_bytes == 2) HFD_LAUNCH_VERTEX(true, 2);
+      else HFD_LAUNCH_VERTEX(true, 0);
+    } else {
+      if (c.idx_bytes == 1) HFD_LAUNCH_VERTEX(false, 1);
+      else if (c.idx_bytes == 2) HFD_LAUNCH_VERTEX(false, 2);
+      else HFD_LAUNCH_VERTEX(false, 0);
+    }
+  } else {
+    // (float64: the staged pass measured slower, its lists are not used)
+    if (c.dvis) HFD_LAUNCH_VERTEX(true, 0);
+    else HFD_LAUNCH_VERTEX(false, 0);
+  }
+#undef HFD_LAUNCH_VERTEX
   return hipGetLastError();
 }
 template hipError_t launch_vertex<double>(int64_t, int64_t, const VertexCoef<double>&,

@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("period", ctypes.c_double * 2), ("w_ref", ctypes.c_double * 4),
                 ("switch_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("flux", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("stage_off", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Info(ctypes.Structure):
@@ -51,7 +51,9 @@ class Info(ctypes.Structure):
                 ("bytes_edge_launch", ctypes.c_double),
                 ("bytes_vertex_launch", ctypes.c_double),
                 ("bytes_edge_w3_side", ctypes.c_double),
-                ("setup_ms", ctypes.c_double * 4)]
+                ("setup_ms", ctypes.c_double * 4),
+                ("stage_idx_bytes", ctypes.c_int32), ("stage_max_rows", ctypes.c_int32),
+                ("stage_max_edges", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}

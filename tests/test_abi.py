@@ -28,9 +28,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # hfd_opts: 14 doubles + 8 int32; hfd_info: 8 int64 + 2 int32 + 17 int64 + 6 double
+    # hfd_opts: 14 doubles + 8 int32; hfd_info: 8 int64 + 2 int32 + 17 int64 + 7 double
+    # + 4 int32
     assert ctypes.sizeof(hfd.Opts) == 14 * 8 + 8 * 4
-    assert ctypes.sizeof(hfd.Info) == 8 * 8 + 2 * 4 + 17 * 8 + 7 * 8
+    assert ctypes.sizeof(hfd.Info) == 8 * 8 + 2 * 4 + 17 * 8 + 7 * 8 + 4 * 4
 
 
 def test_default_opts():
@@ -85,3 +86,47 @@ def test_host_only_context_refuses_device_calls():
     assert L.hfd_residual(S._h, None, None, None) == 6
     assert L.hfd_rk_step(S._h, None, 0.1, None) == 6
     assert S.info["n_owned"] == 81 and S.info["nv"] == 19 * 19
+
+
+def _stage_lists(ptr, ids, nowned, vpb=16):
+    """Sorted distinct ids per block of vpb owned vertices, and the largest
+    spread of one vertex's slots over its block's list (brute force)."""
+    lists, span = [], 0
+    for b in range(0, nowned, vpb):
+        lst = np.unique(ids[ptr[b]:ptr[min(nowned, b + vpb)]])
+        lists.append(lst)
+        for v in range(b, min(nowned, b + vpb)):
+            p = np.searchsorted(lst, ids[ptr[v]:ptr[v + 1]])
+            span = max(span, int(p.max() - p.min()) + 1)
+    return lists, span
+
+
+def test_vertex_stage_lists_and_byte_model():
+    # periodic lattice: no ghosts, so a slot's gather row is its vertex's
+    # internal index and the staged lists can be recounted from the export;
+    # the staging serves the float32 form
+    m = inputs.jittered_grid(24, 20, 1.0, 1.0, periodic=(True, True), seed=3)
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1, precision="fp32")
+    S0 = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1, precision="fp32",
+                    stage_off=1)
+    S64 = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1)
+    i, i0 = S.info, S0.info
+    assert i0["stage_idx_bytes"] == 0 and i0["stage_max_rows"] == 0
+    assert S64.info["stage_idx_bytes"] == 0
+    vptr, vn, eptr, ve = S.export_vertex_stencils()
+    rows, rspan = _stage_lists(vptr, S.new_of_old[vn], S.n_owned)
+    edges, espan = _stage_lists(eptr, ve, S.n_owned)
+    assert i["stage_max_rows"] == max(len(r) for r in rows)
+    assert i["stage_max_edges"] == max(len(e) for e in edges)
+    assert i["stage_idx_bytes"] == (1 if max(rspan, espan) <= 256 else 2)
+    # byte model: each slot id shrinks from 4 bytes to stage_idx_bytes; the
+    # lists (offsets per block and their entries) and a 4-byte pair of bases
+    # per vertex are read once
+    nb = len(rows)
+    lists = 4 * (2 * (nb + 1) + sum(len(r) for r in rows) + sum(len(e) for e in edges)
+                 + S.n_owned)
+    saved = (4 - i["stage_idx_bytes"]) * (i["n_vslots"] + i["n_eslots"])
+    assert i0["bytes_vertex_launch"] - i["bytes_vertex_launch"] == pytest.approx(saved - lists, rel=1e-12)
+    # the staging changes nothing else
+    for k in ("n_vslots", "n_eslots", "bytes_edge_launch", "max_vslots", "max_eslots"):
+        assert i[k] == i0[k]
