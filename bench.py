@@ -89,7 +89,8 @@ def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
         bytes_edge += w3_sides * info["bytes_edge_w3_side"]
     return dict(U=U, wall=wall, edge_ms=e_ms / max(n_e, 1), vertex_ms=v_ms / max(n_v, 1),
                 n_edge=n_e, n_vertex=n_v, bytes_edge=bytes_edge, w3_sides=w3_sides,
-                bytes_vertex=info["bytes_vertex_launch"])
+                bytes_vertex=info["bytes_vertex_launch"],
+                bytes_vertex_staged=info["bytes_vertex_staged"])
 
 
 def measured_traffic(workload, kernel):
@@ -116,6 +117,12 @@ def roofline(r):
         gbs = r[f"bytes_{k}"] / (ms * 1e-3) / 1e9
         kern[k] = dict(avg_ms=ms, alg_bytes=r[f"bytes_{k}"], achieved_gbs=gbs,
                        frac=gbs / HBM_PEAK_GBS, launches=r[f"n_{k}"])
+    if r.get("bytes_vertex_staged"):
+        # the float32 vertex pass stages its blocks in LDS and reads 1-byte
+        # local ids plus lists instead of 4-byte slot ids: its own bytes
+        # beside the method's
+        kern["vertex"]["staged_bytes"] = r["bytes_vertex_staged"]
+        kern["vertex"]["staged_gbs"] = r["bytes_vertex_staged"] / (r["vertex_ms"] * 1e-3) / 1e9
     dom = max(kern, key=lambda k: kern[k]["avg_ms"])
     return dom, kern
 

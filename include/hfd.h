@@ -124,6 +124,11 @@ typedef struct hfd_info {
   int32_t stage_max_rows;
   int32_t stage_max_edges;
   int32_t reserved_info;
+  /* Bytes the staged vertex pass reads and writes per launch (0 when not
+   * staged): bytes_vertex_launch with the local ids, lists and bases in
+   * place of the 4-byte slot ids.  bytes_vertex_launch stays the method's
+   * figure, with 4-byte ids. */
+  double bytes_vertex_staged;
 } hfd_info;
 
 /* Default options: gamma 1.4, R 1, mu 0, Pr 0.72, eps 1e-6, (0.01, 0.79),

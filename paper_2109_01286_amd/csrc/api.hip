@@ -236,19 +236,22 @@ void byte_model(hfd_ctx* c) {
   // averaged over the three stages: U^n read and U^new written every stage,
   // U^k read in stages 2 and 3, gather-layout copy written in stages 1 and 2
   double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + (2.0 / 3.0) * 12 * s);
-  // slot ids: 4-byte global ids, or 1/2-byte local ids plus the per-block
-  // lists of distinct rows and edges and the per-vertex bases when the
-  // block's data is staged in LDS (float32 form)
+  I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (4 + 6 * s + visc * 5 * s) +
+                          double(I.n_eslots) * (4 + 3 * s) + nv * (4 + 8 * visc) * s +
+                          ne * 4 * s + rk;
+  // What the pass that stages its blocks in LDS (float32 form) reads instead:
+  // 1/2-byte local slot ids plus the per-block lists of distinct rows and
+  // edges and the per-vertex bases.
   const auto& g = c->stage;
   const bool staged = g.idx_bytes && mixed(c);
   I.stage_idx_bytes = staged ? g.idx_bytes : 0;
   I.stage_max_rows = staged ? g.max_rows : 0;
   I.stage_max_edges = staged ? g.max_edges : 0;
-  const double ib = staged ? double(g.idx_bytes) : 4.0;
-  const double lists = staged ? double(g.list_ints) * 4 : 0.0;
-  I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (ib + 6 * s + visc * 5 * s) +
-                          double(I.n_eslots) * (ib + 3 * s) + nv * (4 + 8 * visc) * s +
-                          ne * 4 * s + rk + lists;
+  I.bytes_vertex_staged =
+      staged ? I.bytes_vertex_launch -
+                   (4.0 - g.idx_bytes) * double(I.n_vslots + I.n_eslots) +
+                   double(g.list_ints) * 4
+             : 0.0;
 }
 
 template <class T>

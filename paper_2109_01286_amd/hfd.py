@@ -53,7 +53,8 @@ class Info(ctypes.Structure):
                 ("bytes_edge_w3_side", ctypes.c_double),
                 ("setup_ms", ctypes.c_double * 4),
                 ("stage_idx_bytes", ctypes.c_int32), ("stage_max_rows", ctypes.c_int32),
-                ("stage_max_edges", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
+                ("stage_max_edges", ctypes.c_int32), ("reserved_info", ctypes.c_int32),
+                ("bytes_vertex_staged", ctypes.c_double)]
 
     def as_dict(self):
         d = {}
