@@ -28,6 +28,10 @@ CASES = {
     "shockvortex": ("shockvortex2049", 25, {"w3_cap": 2.0}, "paper"),
     "tgv": ("tgv513", 25, {"mu": 0.01}, "smooth"),
     "couette": ("couette", 31, {"mu": 0.1, "prandtl": 100.0, "gas_R": 20.0 / 7.0}, "smooth"),
+    # smallest meshes: 36 owned vertices (a partial last vertex block), fewer
+    # edges than one edge block (108 periodic; 249 with ghost regions)
+    "tiny": ("vortex21", 7, {"w3_cap": 2.0}, "paper"),
+    "tiny_ghost": ("riemann201", 6, {"w3_cap": 2.0}, "weno"),
 }
 
 
@@ -176,7 +180,8 @@ def test_residual_with_gpu_weights_close_to_oracle():
 # at its exact steady state (the residual is only the truncation error).
 # Same form as the float64 bound, at float32 rounding: 2e-7 (about 3 units
 # of float32 rounding) of sum |coefficient| |flux|.
-@pytest.mark.parametrize("key", ["vortex21", "shockvortex", "riemann", "tgv", "couette"])
+@pytest.mark.parametrize("key", ["vortex21", "shockvortex", "riemann", "tgv", "couette", "tiny",
+                                 "tiny_ghost"])
 def test_mixed_precision_residual(key):
     P = pair(key)
     P.import_oracle()
@@ -193,7 +198,7 @@ def test_mixed_precision_residual(key):
                             rel=1e-5, abs_rel=2e-7)
         print(f"[parity] {key} mixed-precision residual rel err {err:.2e}, tolerance use {q:.2f}")
         assert q <= 1.0
-        if key in ("vortex21", "shockvortex", "riemann"):
+        if key in ("vortex21", "shockvortex", "riemann", "tiny", "tiny_ghost"):
             assert err <= 1e-5    # no cancellation: the relative bound alone
     finally:
         P.S.force_switch_mask(None)

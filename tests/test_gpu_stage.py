@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 CASES = [("vortex21", None), ("riemann201", 61), ("tgv513", 65), ("couette", 41),
-         ("sod_circle", 41), ("shockvortex2049", 65)]
+         ("sod_circle", 41), ("shockvortex2049", 65), ("vortex21", 7), ("riemann201", 6)]
 
 
 def options(name, prm):
