@@ -308,7 +308,7 @@ def main():
                          "known-size kernel for calibrating HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the mesh would be partitioned with a halo exchange per stage).",
               file=sys.stderr)
         sys.exit(2)
