@@ -195,7 +195,7 @@ void stage_lists(const std::vector<int64_t>& ptr, const std::vector<int32_t>& id
 }
 
 // Staging lists of the vertex pass, kept when a block's data fits in LDS
-// (float32 values, gradients with viscosity, and fluxes).  Local ids take
+// (float64 values, gradients with viscosity, and fluxes).  Local ids take
 // one byte when every vertex's slots span at most 256 list positions.
 void build_stage(hfd_ctx* c) {
   auto& g = c->stage;
@@ -207,7 +207,7 @@ void build_stage(hfd_ctx* c) {
   stage_lists(h.vptr, h.v_gather, h.nv, h.n_owned, g.rp, g.rows, rb, g.vloc, g.max_rows, rspan);
   stage_lists(h.eptr, h.v_edges, std::max<int64_t>(h.ne, 1), h.n_owned, g.ep, g.edges, eb,
               g.eloc, g.max_edges, espan);
-  const int64_t lds = ((c->o.mu > 0.0 ? 3 : 1) * int64_t(g.max_rows) + g.max_edges) * 16;
+  const int64_t lds = ((c->o.mu > 0.0 ? 3 : 1) * int64_t(g.max_rows) + g.max_edges) * 32;
   if (lds > 48 * 1024 || g.max_rows > 65536 || g.max_edges > 65536) {
     g = hfd_ctx::Stage{};
     return;
@@ -239,11 +239,11 @@ void byte_model(hfd_ctx* c) {
   I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (4 + 6 * s + visc * 5 * s) +
                           double(I.n_eslots) * (4 + 3 * s) + nv * (4 + 8 * visc) * s +
                           ne * 4 * s + rk;
-  // What the pass that stages its blocks in LDS (float32 form) reads instead:
-  // 1/2-byte local slot ids plus the per-block lists of distinct rows and
-  // edges and the per-vertex bases.
+  // What the pass that stages its blocks in LDS reads instead: 1/2-byte
+  // local slot ids plus the per-block lists of distinct rows and edges and
+  // the per-vertex bases.
   const auto& g = c->stage;
-  const bool staged = g.idx_bytes && mixed(c);
+  const bool staged = g.idx_bytes != 0;
   I.stage_idx_bytes = staged ? g.idx_bytes : 0;
   I.stage_max_rows = staged ? g.max_rows : 0;
   I.stage_max_edges = staged ? g.max_edges : 0;

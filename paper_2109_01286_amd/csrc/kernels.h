@@ -85,7 +85,7 @@ struct VertexCoef {
   const T* de;             // [n_eslots][3]
   const T* dvis;           // [n_vslots][5] or null
   // Staging of a block's neighbour data in LDS (idx_bytes 1 or 2; 0 = every
-  // slot gathers from HBM through vg/ve; float32 only).  Per block of 16
+  // slot gathers from HBM through vg/ve).  Per block of 16
   // owned vertices: its distinct gather rows hrow[hrp[b] .. hrp[b+1]) and
   // distinct edges hedge[hep[b] .. hep[b+1]), sorted.  A slot's row (edge)
   // is at position base + vloc[slot] (eloc) of its block's list, where

@@ -661,9 +661,9 @@ struct Rec {
 
 // Waves per SIMD the vertex kernel is compiled for (register budget 512/waves),
 // and whether vertex and edge slots are loaded in separate batches.
-template <class T> struct VertexWaves { static constexpr int value = 3; };
+template <class T> struct VertexWaves { static constexpr int value = 4; };
 template <> struct VertexWaves<float> { static constexpr int value = HFD_VERTEX_WAVES; };
-template <class T> struct VertexSplit { static constexpr bool value = false; };
+template <class T> struct VertexSplit { static constexpr bool value = true; };
 template <> struct VertexSplit<float> { static constexpr bool value = true; };
 
 // Slot id of a coefficient stream at byte base b, slot r: a global row or
@@ -1149,13 +1149,13 @@ hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
   if (nowned == 0) return hipSuccess;
   constexpr int VPB = 256 / VertexLanes<T>::value;
   const unsigned nb = nblocks(nowned, VPB);
-  const size_t lds = c.idx_bytes && sizeof(T) == 4 ? size_t((c.dvis ? 3 : 1) * c.max_rows + c.max_edges) *
+  const size_t lds = c.idx_bytes ? size_t((c.dvis ? 3 : 1) * c.max_rows + c.max_edges) *
                                        sizeof(V4<T>)
                                  : 0;
 #define HFD_LAUNCH_VERTEX(V, I)                                                              \
   hipLaunchKernelGGL((k_vertex<T, V, I>), dim3(nb), dim3(256), lds, st, nowned, nv, c, gp, Gv, \
                      Gg, H, mode, dU, rk, Gv_new, Gg_new, flag)
-  if constexpr (VPB == kStageVertices && sizeof(T) == 4) {
+  if constexpr (VPB == kStageVertices) {
     if (c.dvis) {
       if (c.idx_bytes == 1) HFD_LAUNCH_VERTEX(true, 1);
       else if (c.idx_bytes == 2) HFD_LAUNCH_VERTEX(true, 2);
@@ -1166,7 +1166,8 @@ hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,
       else HFD_LAUNCH_VERTEX(false, 0);
     }
   } else {
-    // (float64: the staged pass measured slower, its lists are not used)
+    // (8 lanes per vertex: 32-vertex blocks, no staging lists)
+    if (c.idx_bytes != 0) return hipErrorInvalidValue;
     if (c.dvis) HFD_LAUNCH_VERTEX(true, 0);
     else HFD_LAUNCH_VERTEX(false, 0);
   }

@@ -103,8 +103,7 @@ def _stage_lists(ptr, ids, nowned, vpb=16):
 
 def test_vertex_stage_lists_and_byte_model():
     # periodic lattice: no ghosts, so a slot's gather row is its vertex's
-    # internal index and the staged lists can be recounted from the export;
-    # the staging serves the float32 form
+    # internal index and the staged lists can be recounted from the export
     m = inputs.jittered_grid(24, 20, 1.0, 1.0, periodic=(True, True), seed=3)
     S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1, precision="fp32")
     S0 = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1, precision="fp32",
@@ -112,7 +111,7 @@ def test_vertex_stage_lists_and_byte_model():
     S64 = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1)
     i, i0 = S.info, S0.info
     assert i0["stage_idx_bytes"] == 0 and i0["stage_max_rows"] == 0
-    assert S64.info["stage_idx_bytes"] == 0
+    assert S64.info["stage_idx_bytes"] == i["stage_idx_bytes"]   # both precisions stage
     vptr, vn, eptr, ve = S.export_vertex_stencils()
     rows, rspan = _stage_lists(vptr, S.new_of_old[vn], S.n_owned)
     edges, espan = _stage_lists(eptr, ve, S.n_owned)
