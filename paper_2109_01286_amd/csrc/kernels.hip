@@ -8,13 +8,14 @@
 // omega-weighted 3-node values, back-projection, Rusanov flux along the edge.
 //
 // Vertex pass (eq. flux_polynomials and the rows d0, dx, dy; viscous
-// vertex-only rows; three-stage TVD Runge-Kutta): 16 lanes per owned vertex
-// stride over the vertex slots (analytic fluxes recomputed from the
-// gathered state, dotted with the coefficient record of the slot) and the
-// edge slots (gathered edge flux), all loads of a batch in flight together;
-// a transposed DPP reduction gives the twelve right-hand sides, staged in
-// LDS so that the float64 Runge-Kutta update is written row by row.  No
-// atomics: every output has exactly one writer.
+// vertex-only rows; three-stage TVD Runge-Kutta): a block of 16 owned
+// vertices first copies its distinct state rows and edge fluxes into LDS;
+// then 16 lanes per vertex stride over the vertex slots (analytic fluxes
+// recomputed from the staged state, dotted with the coefficient record of
+// the slot) and the edge slots (staged edge flux), all loads of a batch in
+// flight together; a transposed DPP reduction gives the twelve right-hand
+// sides, staged in LDS so that the float64 Runge-Kutta update is written
+// row by row.  No atomics: every output has exactly one writer.
 //
 // Two precisions share the code: float64 throughout, or float32 arithmetic
 // on a float32 perturbation state w' = w - w_ref (gradients unchanged) with
@@ -35,7 +36,7 @@
 #define HFD_NT_COEF 0         // 1: non-temporal loads for single-use coefficient streams
 #endif
 #ifndef HFD_VERTEX_WAVES
-#define HFD_VERTEX_WAVES 7    // waves per SIMD of the float32 vertex kernel
+#define HFD_VERTEX_WAVES 7    // waves per SIMD of the float32 vertex kernel (Euler)
 #endif
 #ifndef HFD_EDGE_WAVES
 #define HFD_EDGE_WAVES 2      // waves per SIMD of the float32 edge kernel
@@ -659,12 +660,9 @@ struct Rec {
 };
 
 
-// Waves per SIMD the vertex kernel is compiled for (register budget 512/waves),
-// and whether vertex and edge slots are loaded in separate batches.
+// Waves per SIMD the vertex kernel is compiled for (register budget 512/waves).
 template <class T> struct VertexWaves { static constexpr int value = 4; };
 template <> struct VertexWaves<float> { static constexpr int value = HFD_VERTEX_WAVES; };
-template <class T> struct VertexSplit { static constexpr bool value = true; };
-template <> struct VertexSplit<float> { static constexpr bool value = true; };
 
 // Slot id of a coefficient stream at byte base b, slot r: a global row or
 // edge (IB = 0, int32) or a position in the block's staged list (1 or 2 bytes).
@@ -784,157 +782,82 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
     const char* veb = IB ? reinterpret_cast<const char*>(c.eloc) + IB * eb
                          : reinterpret_cast<const char*>(c.ve + eb);
     const char* deb = reinterpret_cast<const char*>(c.de + int64_t(3) * eb);
-    if constexpr (VertexSplit<T>::value) {
-      // vertex slots, then edge slots: fewer values in flight per wave,
-      // more waves per SIMD
-      for (int bs = s0 + sub; bs < s1; bs += NVS * VL) {
-        int js[NVS];
-        bool oks[NVS];
+    // vertex slots, then edge slots (separate batches: fewer values in
+    // flight per wave, more waves per SIMD)
+    for (int bs = s0 + sub; bs < s1; bs += NVS * VL) {
+      int js[NVS];
+      bool oks[NVS];
 #pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-          oks[k] = bs + k * VL < s1;
-          js[k] = oks[k] ? bs + k * VL : s1 - 1;
-        }
-        int u[NVS];
-        T d[NVS][6], kv[NVS][5];
+      for (int k = 0; k < NVS; ++k) {
+        oks[k] = bs + k * VL < s1;
+        js[k] = oks[k] ? bs + k * VL : s1 - 1;
+      }
+      int u[NVS];
+      T d[NVS][6], kv[NVS][5];
 #pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-          const uint32_t r = uint32_t(js[k] - sb);
-          u[k] = rbase + slot_id<IB>(vgb, r);
-          const Rec<T, 6> dr = *reinterpret_cast<const Rec<T, 6>*>(dvb + uint32_t(6 * sizeof(T)) * r);
+      for (int k = 0; k < NVS; ++k) {
+        const uint32_t r = uint32_t(js[k] - sb);
+        u[k] = rbase + slot_id<IB>(vgb, r);
+        const Rec<T, 6> dr = *reinterpret_cast<const Rec<T, 6>*>(dvb + uint32_t(6 * sizeof(T)) * r);
 #pragma unroll
-          for (int q = 0; q < 6; ++q) d[k][q] = dr.v[q];
-          if (VISC) {
-            const Rec<T, 5> kr = *reinterpret_cast<const Rec<T, 5>*>(dkb + uint32_t(5 * sizeof(T)) * r);
+        for (int q = 0; q < 6; ++q) d[k][q] = dr.v[q];
+        if (VISC) {
+          const Rec<T, 5> kr = *reinterpret_cast<const Rec<T, 5>*>(dkb + uint32_t(5 * sizeof(T)) * r);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) kv[k][q] = kr.v[q];
-          }
-        }
-        V4<T> A[NVS], G[NVS][2];
-#pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-          A[k] = sV[u[k]];
-          if (VISC) {
-            G[k][0] = sG[2 * int64_t(u[k])];
-            G[k][1] = sG[2 * int64_t(u[k]) + 1];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-#pragma unroll
-          for (int q = 0; q < 6; ++q) d[k][q] = oks[k] ? d[k][q] : T(0);
-          if (VISC) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) kv[k][q] = oks[k] ? kv[k][q] : T(0);
-          }
-          vslot<T, VISC>(A[k], G[k], d[k], kv[k], ref, gm1, gp, acc);
+          for (int q = 0; q < 5; ++q) kv[k][q] = kr.v[q];
         }
       }
-      for (int be = e0 + sub; be < e1; be += NES * VL) {
-        int je[NES];
-        bool oke[NES];
+      V4<T> A[NVS], G[NVS][2];
 #pragma unroll
-        for (int k = 0; k < NES; ++k) {
-          oke[k] = be + k * VL < e1;
-          je[k] = oke[k] ? be + k * VL : e1 - 1;
-        }
-        int m[NES];
-        T de[NES][3];
-#pragma unroll
-        for (int k = 0; k < NES; ++k) {
-          const uint32_t r = uint32_t(je[k] - eb);
-          m[k] = ebase + slot_id<IB>(veb, r);
-          const Rec<T, 3> er = *reinterpret_cast<const Rec<T, 3>*>(deb + uint32_t(3 * sizeof(T)) * r);
-#pragma unroll
-          for (int q = 0; q < 3; ++q) de[k][q] = er.v[q];
-        }
-        V4<T> Hh[NES];
-#pragma unroll
-        for (int k = 0; k < NES; ++k) Hh[k] = sH[m[k]];
-#pragma unroll
-        for (int k = 0; k < NES; ++k) {
-          const T w0 = oke[k] ? de[k][0] : T(0), w1 = oke[k] ? de[k][1] : T(0),
-                  w2 = oke[k] ? de[k][2] : T(0);
-          const T hq[4] = {Hh[k].x, Hh[k].y, Hh[k].z, Hh[k].w};
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            acc[q] -= w0 * hq[q];
-            acc[4 + q] -= w1 * hq[q];
-            acc[8 + q] -= w2 * hq[q];
-          }
+      for (int k = 0; k < NVS; ++k) {
+        A[k] = sV[u[k]];
+        if (VISC) {
+          G[k][0] = sG[2 * int64_t(u[k])];
+          G[k][1] = sG[2 * int64_t(u[k]) + 1];
         }
       }
-    } else {
-      // vertex and edge slots in one batch
-      for (int bs = s0 + sub, be = e0 + sub; bs < s1 || be < e1;
-           bs += NVS * VL, be += NES * VL) {
-        int js[NVS], je[NES];
-        bool oks[NVS], oke[NES];
 #pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-          oks[k] = bs + k * VL < s1;
-          js[k] = oks[k] ? bs + k * VL : s1 - 1;
+      for (int k = 0; k < NVS; ++k) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) d[k][q] = oks[k] ? d[k][q] : T(0);
+        if (VISC) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) kv[k][q] = oks[k] ? kv[k][q] : T(0);
         }
+        vslot<T, VISC>(A[k], G[k], d[k], kv[k], ref, gm1, gp, acc);
+      }
+    }
+    for (int be = e0 + sub; be < e1; be += NES * VL) {
+      int je[NES];
+      bool oke[NES];
 #pragma unroll
-        for (int k = 0; k < NES; ++k) {
-          oke[k] = be + k * VL < e1;
-          je[k] = oke[k] ? be + k * VL : e1 - 1;
-        }
-        int u[NVS], m[NES];
-        T d[NVS][6], kv[NVS][5], de[NES][3];
+      for (int k = 0; k < NES; ++k) {
+        oke[k] = be + k * VL < e1;
+        je[k] = oke[k] ? be + k * VL : e1 - 1;
+      }
+      int m[NES];
+      T de[NES][3];
 #pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-          const uint32_t r = uint32_t(js[k] - sb);
-          u[k] = rbase + slot_id<IB>(vgb, r);
-          const Rec<T, 6> dr = *reinterpret_cast<const Rec<T, 6>*>(dvb + uint32_t(6 * sizeof(T)) * r);
+      for (int k = 0; k < NES; ++k) {
+        const uint32_t r = uint32_t(je[k] - eb);
+        m[k] = ebase + slot_id<IB>(veb, r);
+        const Rec<T, 3> er = *reinterpret_cast<const Rec<T, 3>*>(deb + uint32_t(3 * sizeof(T)) * r);
 #pragma unroll
-          for (int q = 0; q < 6; ++q) d[k][q] = dr.v[q];
-          if (VISC) {
-            const Rec<T, 5> kr = *reinterpret_cast<const Rec<T, 5>*>(dkb + uint32_t(5 * sizeof(T)) * r);
+        for (int q = 0; q < 3; ++q) de[k][q] = er.v[q];
+      }
+      V4<T> Hh[NES];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) kv[k][q] = kr.v[q];
-          }
-        }
+      for (int k = 0; k < NES; ++k) Hh[k] = sH[m[k]];
 #pragma unroll
-        for (int k = 0; k < NES; ++k) {
-          const uint32_t r = uint32_t(je[k] - eb);
-          m[k] = ebase + slot_id<IB>(veb, r);
-          const Rec<T, 3> er = *reinterpret_cast<const Rec<T, 3>*>(deb + uint32_t(3 * sizeof(T)) * r);
+      for (int k = 0; k < NES; ++k) {
+        const T w0 = oke[k] ? de[k][0] : T(0), w1 = oke[k] ? de[k][1] : T(0),
+                w2 = oke[k] ? de[k][2] : T(0);
+        const T hq[4] = {Hh[k].x, Hh[k].y, Hh[k].z, Hh[k].w};
 #pragma unroll
-          for (int q = 0; q < 3; ++q) de[k][q] = er.v[q];
-        }
-        V4<T> A[NVS], G[NVS][2], Hh[NES];
-#pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-          A[k] = sV[u[k]];
-          if (VISC) {
-            G[k][0] = sG[2 * int64_t(u[k])];
-            G[k][1] = sG[2 * int64_t(u[k]) + 1];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < NES; ++k) Hh[k] = sH[m[k]];
-#pragma unroll
-        for (int k = 0; k < NVS; ++k) {
-#pragma unroll
-          for (int q = 0; q < 6; ++q) d[k][q] = oks[k] ? d[k][q] : T(0);
-          if (VISC) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) kv[k][q] = oks[k] ? kv[k][q] : T(0);
-          }
-          vslot<T, VISC>(A[k], G[k], d[k], kv[k], ref, gm1, gp, acc);
-        }
-#pragma unroll
-        for (int k = 0; k < NES; ++k) {
-          const T w0 = oke[k] ? de[k][0] : T(0), w1 = oke[k] ? de[k][1] : T(0),
-                  w2 = oke[k] ? de[k][2] : T(0);
-          const T hq[4] = {Hh[k].x, Hh[k].y, Hh[k].z, Hh[k].w};
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            acc[q] -= w0 * hq[q];
-            acc[4 + q] -= w1 * hq[q];
-            acc[8 + q] -= w2 * hq[q];
-          }
+        for (int q = 0; q < 4; ++q) {
+          acc[q] -= w0 * hq[q];
+          acc[4 + q] -= w1 * hq[q];
+          acc[8 + q] -= w2 * hq[q];
         }
       }
     }
