@@ -288,6 +288,33 @@ def adjoint_ratio(steps=200, ckpt=20):
             "grad_finite": bool(torch.isfinite(g).all().item())}
 
 
+def viscous_line(steps=12, warmup=1):
+    """Throughput of the viscous path on the Taylor-Green recipe at 513 x 513
+    (262 k vertices, about the one-GPU share of the shock-vortex mesh split
+    eight ways; its working set exceeds the MALL), float32 and float64, with
+    the vertex pass against the HBM roofline.  Every timed step restarts
+    from the initial state: under the readings the lattice is unstable from
+    the second step on."""
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+    m, U0, prm = inputs.workload("tgv513")
+    kw = workload_options("tgv513", prm)
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, **kw)
+    U0d = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+    wref = U0[0:4, m.ghost_src == -1].mean(axis=1)
+    out = {"workload": "tgv513", "owned": int(m.n_owned()), "steps": steps,
+           "steps_per_restart": 1}
+    for prec in ("fp32", "fp64"):
+        r = time_precision(S, U0d, prec, wref, steps, warmup, 0.3, 1)
+        _, kern = roofline(r)
+        out[prec] = {"value": m.n_owned() * 3 * steps / r["wall"],
+                     "unit": "vertex-stage/s", "ms_per_step": r["wall"] / steps * 1e3,
+                     "kernels": kern}
+    del S
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +329,7 @@ def main():
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-viscous", action="store_true")
     ap.add_argument("--no-flux-variants", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (a "
@@ -418,6 +446,12 @@ def main():
         log("[bench] accuracy: " + ", ".join(
             f"{k} rho L2 fp64 {v['fp64']['rho']['l2']:.3e} fp32 {v['fp32']['rho']['l2']:.3e}"
             for k, v in out["accuracy"].items()))
+    if not a.no_viscous:
+        out["viscous"] = viscous_line()
+        v = out["viscous"]
+        log("[bench] viscous (tgv513): " + ", ".join(
+            f"{p} {v[p]['value'] / 1e9:.3f} G vertex-stage/s, vertex {v[p]['kernels']['vertex']['avg_ms']:.3f} ms "
+            f"({v[p]['kernels']['vertex']['frac'] * 100:.0f} % of HBM)" for p in ("fp32", "fp64")))
     if not a.no_adjoint:
         del S
         torch.cuda.empty_cache()
