@@ -279,8 +279,35 @@ def adjoint_ratio(steps=200, ckpt=20):
                "adjoint_over_forward": t_rev / t_fwd,
                "backward_forward_steps": RKStepsRevolve.last_stats["forward_steps"],
                "grad_equal_to_uniform": bool(torch.equal(gr, g))}
+    # the mixed form: float32 steps and adjoint steps (float64 states and
+    # lambdas), the same schedule; its gradient against the float64 one
+    S.set_precision("fp32", U[0:4, m.ghost_src == -1].mean(axis=1))
+    X = Ud.clone()
+    S.rk_step(X, dt)
+    U0 = Ud.clone().requires_grad_(True)
+    Jw = pressure_disk_objective(rk_steps(U0, S, 1, dt, 1), xy, (7.0, 7.0), 1.0, area)
+    torch.autograd.grad(Jw, U0)
+    torch.cuda.synchronize()
+    X = Ud.clone()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.rk_step(X, dt)
+    torch.cuda.synchronize()
+    t_fwd32 = time.perf_counter() - t0
+    U0 = Ud.clone().requires_grad_(True)
+    J32 = pressure_disk_objective(rk_steps(U0, S, steps, dt, ckpt), xy, (7.0, 7.0), 1.0, area)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    (g32,) = torch.autograd.grad(J32, U0)
+    torch.cuda.synchronize()
+    t_bwd32 = time.perf_counter() - t0
+    S.check()
+    fp32 = {"forward_ms": t_fwd32 * 1e3, "backward_ms": t_bwd32 * 1e3,
+            "adjoint_over_forward": t_bwd32 / t_fwd32,
+            "J_rel_diff_vs_fp64": abs(J32.item() - J.item()) / abs(J.item()),
+            "grad_rel_l2_diff_vs_fp64": float(torch.linalg.norm(g32 - g) / torch.linalg.norm(g))}
     return {"workload": "vortex257", "steps": steps, "ckpt_every": ckpt, "dtype": "f64",
-            "binomial": revolve,
+            "binomial": revolve, "fp32": fp32,
             "switch": "weno", "forward_ms": t_fwd * 1e3,
             "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
             "adjoint_setup_ms": t_setup * 1e3,
@@ -456,8 +483,10 @@ def main():
         del S
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_ratio()
-        log(f"[bench] adjoint/forward (vortex257, 200 steps, f64): "
-            f"{out['adjoint']['adjoint_over_forward']:.2f}")
+        a32 = out["adjoint"]["fp32"]
+        log(f"[bench] adjoint/forward (vortex257, 200 steps): f64 "
+            f"{out['adjoint']['adjoint_over_forward']:.2f}, f32 {a32['adjoint_over_forward']:.2f} "
+            f"(f32 gradient vs f64: {a32['grad_rel_l2_diff_vs_fp64']:.1e} rel L2)")
     if not a.no_cpu:
         log("[bench] timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(m, U0, prm, kw, a.cpu_budget)

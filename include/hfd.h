@@ -258,8 +258,11 @@ hfd_status hfd_fill_ghosts(hfd_ctx* ctx, double* U, void* stream);
  * vertex (the flag is then cleared). */
 hfd_status hfd_check(hfd_ctx* ctx, void* stream);
 
-/* Adjoint of the residual (float64, Euler fluxes only; mu > 0 gives
- * HFD_E_STATE): out = (dR/dU)^T lam, all device [12][nv] float64.  The
+/* Adjoint of the residual (Euler fluxes only; mu > 0 gives HFD_E_STATE):
+ * out = (dR/dU)^T lam, all device [12][nv] float64.  Computed in the
+ * context's precision: float64, or in HFD_FP32_MIXED float32 arithmetic on
+ * the float32 perturbation state of the forward pass, each vertex's sums
+ * written in float64.  The
  * branch of eq. 2d_hweno_intp and the WENO weights are differentiated
  * through the branch the forward pass takes, the Rusanov maximum through its
  * larger argument.  Rows of ghost vertices of out are zero (derivatives with
@@ -268,7 +271,9 @@ hfd_status hfd_check(hfd_ctx* ctx, void* stream);
 hfd_status hfd_adjoint_residual(hfd_ctx* ctx, const double* U, const double* lam,
                                 double* out, void* stream);
 
-/* Adjoint of one hfd_rk_step with step size dt (float64): given the step's
+/* Adjoint of one hfd_rk_step with step size dt (the context's precision for
+ * the stage states and adjoint residuals, float64 for the Runge-Kutta
+ * combinations of lambda): given the step's
  * input state U_n and lam_np1 = dJ/dU_{n+1}, lam_n = (dU_{n+1}/dU_n)^T
  * lam_np1 (device, [12][nv]).  The two intermediate stages are recomputed.
  * Dirichlet rows of lam_n carry lam_np1 through; rows of copying ghosts are
@@ -276,8 +281,8 @@ hfd_status hfd_adjoint_residual(hfd_ctx* ctx, const double* U, const double* lam
 hfd_status hfd_rk_step_adjoint(hfd_ctx* ctx, const double* U_n, double dt,
                                const double* lam_np1, double* lam_n, void* stream);
 
-/* One step of hfd_rk_step in float64 (whatever the context's precision)
- * that also returns its two intermediate stages (end of Section 2.3):
+/* One step of hfd_rk_step (the context's precision) that also returns its
+ * two intermediate stages (end of Section 2.3):
  * U1 = U + dt R(U), U2 = 3/4 U + 1/4 (U1 + dt R(U1)), device [12][nv]
  * (owned rows; ghost rows unspecified).  For hfd_rk_step_adjoint_stages,
  * which then need not recompute them. */

@@ -1,7 +1,8 @@
 """Gradients through many Runge-Kutta steps: a torch.autograd.Function
 whose backward runs the library's hand-written adjoint step in reverse, with
-checkpointing.  The steps are float64 whatever the solver's precision (the
-adjoint is the transpose of the float64 step).
+checkpointing.  The steps and their adjoints run in the solver's precision:
+float64, or the mixed form (float32 arithmetic, float64 states and
+lambdas).
 
 Two checkpointing schedules:
 

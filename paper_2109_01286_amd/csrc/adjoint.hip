@@ -1,4 +1,6 @@
-// Hand-written adjoint (vector-Jacobian product) of the residual, float64.
+// Hand-written adjoint (vector-Jacobian product) of the residual, float64 or
+// float32 (the mixed form: float32 arithmetic on its own stage states, the
+// per-vertex sums written to float64).
 //
 // The residual R(U) of eq. HWENO is a composition of
 //   (1) the edge pass: h_e = Rusanov(w_L(e), w_R(e); n_e), w_L / w_R the
@@ -32,49 +34,52 @@ namespace hfd {
 namespace {
 
 // derivative of F(w).n transposed, applied to g: out += A_n(w)^T g
-__device__ inline void flux_jac_t(const double w[4], double nx, double ny, double gm1,
-                                  const double g[4], double out[4]) {
-  const double rho = w[0], ir = 1.0 / rho, u = w[1] * ir, v = w[2] * ir;
-  const double un = u * nx + v * ny;
-  const double p = gm1 * (w[3] - 0.5 * rho * (u * u + v * v));
+template <class T>
+__device__ inline void flux_jac_t(const T w[4], T nx, T ny, T gm1,
+                                  const T g[4], T out[4]) {
+  const T rho = w[0], ir = T(1.0) / rho, u = w[1] * ir, v = w[2] * ir;
+  const T un = u * nx + v * ny;
+  const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
   // d un / dw, d p / dw
-  const double dun[4] = {-un * ir, nx * ir, ny * ir, 0.0};
-  const double dp[4] = {gm1 * 0.5 * (u * u + v * v), -gm1 * u, -gm1 * v, gm1};
-  const double m = w[1], n = w[2], E = w[3];
+  const T dun[4] = {-un * ir, nx * ir, ny * ir, T(0.0)};
+  const T dp[4] = {gm1 * T(0.5) * (u * u + v * v), -gm1 * u, -gm1 * v, gm1};
+  const T m = w[1], n = w[2], E = w[3];
   for (int k = 0; k < 4; ++k) {
-    double s = 0.0;
+    T s = T(0.0);
     // component 0: rho un = m nx + n ny
-    s += g[0] * (k == 1 ? nx : (k == 2 ? ny : 0.0));
+    s += g[0] * (k == 1 ? nx : (k == 2 ? ny : T(0.0)));
     // component 1: m un + p nx
-    s += g[1] * ((k == 1 ? un : 0.0) + m * dun[k] + nx * dp[k]);
+    s += g[1] * ((k == 1 ? un : T(0.0)) + m * dun[k] + nx * dp[k]);
     // component 2: n un + p ny
-    s += g[2] * ((k == 2 ? un : 0.0) + n * dun[k] + ny * dp[k]);
+    s += g[2] * ((k == 2 ? un : T(0.0)) + n * dun[k] + ny * dp[k]);
     // component 3: (E + p) un
-    s += g[3] * (un * ((k == 3 ? 1.0 : 0.0) + dp[k]) + (E + p) * dun[k]);
+    s += g[3] * (un * ((k == 3 ? T(1.0) : T(0.0)) + dp[k]) + (E + p) * dun[k]);
     out[k] += s;
   }
 }
 
 // d(|u.n| + c)/dw
-__device__ inline void speed_grad(const double w[4], double nx, double ny, double gam,
-                                  double out[4]) {
-  const double gm1 = gam - 1.0;
-  const double rho = w[0], ir = 1.0 / rho, u = w[1] * ir, v = w[2] * ir;
-  const double un = u * nx + v * ny;
-  const double p = gm1 * (w[3] - 0.5 * rho * (u * u + v * v));
-  const double c = sqrt(gam * p * ir);
-  const double sg = un > 0.0 ? 1.0 : (un < 0.0 ? -1.0 : 0.0);
-  const double dun[4] = {-un * ir, nx * ir, ny * ir, 0.0};
-  const double dp[4] = {gm1 * 0.5 * (u * u + v * v), -gm1 * u, -gm1 * v, gm1};
-  const double k = gam / (2.0 * c * rho);
-  for (int j = 0; j < 4; ++j) out[j] = sg * dun[j] + k * (dp[j] - (j == 0 ? p * ir : 0.0));
+template <class T>
+__device__ inline void speed_grad(const T w[4], T nx, T ny, T gam,
+                                  T out[4]) {
+  const T gm1 = gam - T(1.0);
+  const T rho = w[0], ir = T(1.0) / rho, u = w[1] * ir, v = w[2] * ir;
+  const T un = u * nx + v * ny;
+  const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
+  const T c = sqrt(gam * p * ir);
+  const T sg = un > T(0.0) ? T(1.0) : (un < T(0.0) ? -T(1.0) : T(0.0));
+  const T dun[4] = {-un * ir, nx * ir, ny * ir, T(0.0)};
+  const T dp[4] = {gm1 * T(0.5) * (u * u + v * v), -gm1 * u, -gm1 * v, gm1};
+  const T k = gam / (T(2.0) * c * rho);
+  for (int j = 0; j < 4; ++j) out[j] = sg * dun[j] + k * (dp[j] - (j == 0 ? p * ir : T(0.0)));
 }
 
-__device__ inline void cart_flux_n(const double w[4], double nx, double ny, double gm1,
-                                   double f[4], double* sp, double gam) {
-  const double rho = w[0], ir = 1.0 / rho, u = w[1] * ir, v = w[2] * ir;
-  const double un = u * nx + v * ny;
-  const double p = gm1 * (w[3] - 0.5 * rho * (u * u + v * v));
+template <class T>
+__device__ inline void cart_flux_n(const T w[4], T nx, T ny, T gm1,
+                                   T f[4], T* sp, T gam) {
+  const T rho = w[0], ir = T(1.0) / rho, u = w[1] * ir, v = w[2] * ir;
+  const T un = u * nx + v * ny;
+  const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
   f[0] = rho * un;
   f[1] = w[1] * un + p * nx;
   f[2] = w[2] * un + p * ny;
@@ -97,7 +102,8 @@ __device__ inline T launder(T x) {
 // ---------------------------------------------------------------------------
 // Sum over the 8 lanes of a group, every lane gets it: the half-row mirror
 // and the two quad swaps pair disjoint lane sets at each stage.
-__device__ inline double sum8(double x) {
+template <class T>
+__device__ inline T sum8(T x) {
   x += dpp_mov<0x141>(x);
   x += dpp_mov<0x4E>(x);
   x += dpp_mov<0xB1>(x);
@@ -108,13 +114,14 @@ __device__ inline double sum8(double x) {
 // batch with all loads in flight; the coefficients are in the transposed
 // order (de_t, contiguous per edge).  Every active edge has an entry, so
 // k1 - 1 is one: lanes past the end load it again with zero weight.
+template <class T>
 __global__ void __launch_bounds__(256)
 k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __restrict__ tv,
-                const double* __restrict__ de_t, const V4<double>* __restrict__ Lv,
-                const V4<double>* __restrict__ Lg, V4<double>* __restrict__ lh) {
+                const T* __restrict__ de_t, const V4<T>* __restrict__ Lv,
+                const V4<T>* __restrict__ Lg, V4<T>* __restrict__ lh) {
   const int64_t m = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 8;
   const int sub = threadIdx.x & 7;
-  double a[4] = {0, 0, 0, 0};
+  T a[4] = {0, 0, 0, 0};
   if (m < ne) {
     const int k0 = tptr[m], k1 = tptr[m + 1];
     for (int b = k0 + sub; b < k1; b += 16) {
@@ -125,20 +132,20 @@ k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __r
         kk[i] = ok[i] ? b + 8 * i : k1 - 1;
       }
       int v[2];
-      double d[2][3];
+      T d[2][3];
       for (int i = 0; i < 2; ++i) {
         v[i] = tv[kk[i]];
         for (int q = 0; q < 3; ++q) d[i][q] = de_t[3 * int64_t(kk[i]) + q];
       }
-      V4<double> l0[2], lx[2], ly[2];
+      V4<T> l0[2], lx[2], ly[2];
       for (int i = 0; i < 2; ++i) {
         l0[i] = Lv[v[i]];
         lx[i] = Lg[2 * int64_t(v[i])];
         ly[i] = Lg[2 * int64_t(v[i]) + 1];
       }
       for (int i = 0; i < 2; ++i) {
-        const double d0 = ok[i] ? d[i][0] : 0.0, dx = ok[i] ? d[i][1] : 0.0,
-                     dy = ok[i] ? d[i][2] : 0.0;
+        const T d0 = ok[i] ? d[i][0] : T(0.0), dx = ok[i] ? d[i][1] : T(0.0),
+                     dy = ok[i] ? d[i][2] : T(0.0);
         a[0] -= d0 * l0[i].x + dx * lx[i].x + dy * ly[i].x;
         a[1] -= d0 * l0[i].y + dx * lx[i].y + dy * ly[i].y;
         a[2] -= d0 * l0[i].z + dx * lx[i].z + dy * ly[i].z;
@@ -147,7 +154,7 @@ k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __r
     }
   }
   for (int q = 0; q < 4; ++q) a[q] = sum8(a[q]);
-  if (m < ne && sub == 0) lh[m] = V4<double>{a[0], a[1], a[2], a[3]};
+  if (m < ne && sub == 0) lh[m] = V4<T>{a[0], a[1], a[2], a[3]};
 }
 
 // ---------------------------------------------------------------------------
@@ -159,53 +166,64 @@ k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __r
 // the four scalar gradients of the Roe state (u, v, H, c) and the
 // contributions to the nodes both sides share, then lane 0 writes nodes
 // 0, 1, 2 and lane 1 nodes 5, 4, 3 (positions 0, 1, 2 of each lane).
+template <class T>
 __global__ void __launch_bounds__(256, ADJ_EDGE_WAVES)
-k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __restrict__ Gv,
-           const V4<double>* __restrict__ Gg, const uint8_t* __restrict__ force,
-           const V4<double>* __restrict__ lh, double* __restrict__ out) {
+k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
+           const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
+           const V4<T>* __restrict__ lh, T* __restrict__ out) {
   const int s = threadIdx.x & 1;
   const int64_t e = int64_t(blockIdx.x) * (blockDim.x / 2) + threadIdx.x / 2;
   if (e >= ne) return;  // both lanes of a pair leave together
-  const double gam = gp.gamma, gm1 = gam - 1.0;
-  const double nx = c.n[e], ny = c.n[ne + e];
+  const T gam = gp.gamma, gm1 = gam - T(1.0);
+  const T nx = c.n[e], ny = c.n[ne + e];
   const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
   int id[5];
   for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
-  const double eps = gp.eps;
-  const double dw[3] = {1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0};
+  const T eps = gp.eps;
+  const T dw[3] = {T(1.0) / T(16.0), T(10.0) / T(16.0), T(5.0) / T(16.0)};
   const uint8_t fm = force ? force[e] : uint8_t(0);
+  // The float32 form stores the perturbation w - w_ref of the values (the
+  // gradients unchanged); the reverse works on the full state.
+  auto full = [&](T x, int q) -> T {
+    if constexpr (sizeof(T) == 4) return x + T(gp.wref[q]);
+    else return x;
+  };
   // Roe average of nodes 2 and 3 and the eigenvector matrices L (rows), R
-  auto roe = [&](double A[4], double B[4], double& sa, double& sb, double& D, double& pa,
-                 double& pb, double& u, double& v, double& H, double& cc) {
-    const V4<double> a = Gv[launder(ia)], b = Gv[launder(ib)];
+  auto roe = [&](T A[4], T B[4], T& sa, T& sb, T& D, T& pa,
+                 T& pb, T& u, T& v, T& H, T& cc) {
+    const V4<T> a = Gv[launder(ia)], b = Gv[launder(ib)];
     A[0] = a.x; A[1] = a.y; A[2] = a.z; A[3] = a.w;
     B[0] = b.x; B[1] = b.y; B[2] = b.z; B[3] = b.w;
-    const double ra = A[0], rb = B[0];
+    for (int q = 0; q < 4; ++q) {
+      A[q] = full(A[q], q);
+      B[q] = full(B[q], q);
+    }
+    const T ra = A[0], rb = B[0];
     sa = sqrt(ra);
     sb = sqrt(rb);
     D = sa + sb;
-    pa = gm1 * (A[3] - 0.5 * (A[1] * A[1] + A[2] * A[2]) / ra);
-    pb = gm1 * (B[3] - 0.5 * (B[1] * B[1] + B[2] * B[2]) / rb);
-    const double Pa = A[1] / sa, Pb = B[1] / sb, Qa = A[2] / sa, Qb = B[2] / sb;
-    const double Ka = (A[3] + pa) / sa, Kb = (B[3] + pb) / sb;
+    pa = gm1 * (A[3] - T(0.5) * (A[1] * A[1] + A[2] * A[2]) / ra);
+    pb = gm1 * (B[3] - T(0.5) * (B[1] * B[1] + B[2] * B[2]) / rb);
+    const T Pa = A[1] / sa, Pb = B[1] / sb, Qa = A[2] / sa, Qb = B[2] / sb;
+    const T Ka = (A[3] + pa) / sa, Kb = (B[3] + pb) / sb;
     u = (Pa + Pb) / D;
     v = (Qa + Qb) / D;
     H = (Ka + Kb) / D;
-    cc = sqrt(gm1 * (H - 0.5 * (u * u + v * v)));
+    cc = sqrt(gm1 * (H - T(0.5) * (u * u + v * v)));
   };
-  auto eig = [&](double u, double v, double H, double cc, double L[4][4], double R[4][4]) {
-    const double q2 = u * u + v * v;
-    const double un = u * nx + v * ny, ut = -u * ny + v * nx;
-    const double b1 = gm1 / (cc * cc), b2 = 0.5 * b1 * q2, ic = 1.0 / cc;
-    const double Lv[4][4] = {
-        {0.5 * (b2 + un * ic), -0.5 * (b1 * u + nx * ic), -0.5 * (b1 * v + ny * ic), 0.5 * b1},
-        {1.0 - b2, b1 * u, b1 * v, -b1},
-        {0.5 * (b2 - un * ic), -0.5 * (b1 * u - nx * ic), -0.5 * (b1 * v - ny * ic), 0.5 * b1},
-        {-ut, -ny, nx, 0.0}};
-    const double Rv[4][4] = {{1.0, 1.0, 1.0, 0.0},
+  auto eig = [&](T u, T v, T H, T cc, T L[4][4], T R[4][4]) {
+    const T q2 = u * u + v * v;
+    const T un = u * nx + v * ny, ut = -u * ny + v * nx;
+    const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1.0) / cc;
+    const T Lv[4][4] = {
+        {T(0.5) * (b2 + un * ic), -T(0.5) * (b1 * u + nx * ic), -T(0.5) * (b1 * v + ny * ic), T(0.5) * b1},
+        {T(1.0) - b2, b1 * u, b1 * v, -b1},
+        {T(0.5) * (b2 - un * ic), -T(0.5) * (b1 * u - nx * ic), -T(0.5) * (b1 * v - ny * ic), T(0.5) * b1},
+        {-ut, -ny, nx, T(0.0)}};
+    const T Rv[4][4] = {{T(1.0), T(1.0), T(1.0), T(0.0)},
                              {u - cc * nx, u, u + cc * nx, -ny},
                              {v - cc * ny, v, v + cc * ny, nx},
-                             {H - un * cc, 0.5 * q2, H + un * cc, ut}};
+                             {H - un * cc, T(0.5) * q2, H + un * cc, ut}};
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
         L[i][j] = Lv[i][j];
@@ -215,45 +233,46 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
   // this side's node values and coefficient rows.  The indices and the base
   // pointers pass through launder() at every use, so that the compiler
   // recomputes the addresses there instead of keeping them in registers.
-  const double* w5p = c.w5 + int64_t(s * 15) * ne + e;
-  const double* w3p = c.w3 + int64_t(s * 9) * ne + e;
-  auto load_W = [&](double W[5][4]) {
+  const T* w5p = c.w5 + int64_t(s * 15) * ne + e;
+  const T* w3p = c.w3 + int64_t(s * 9) * ne + e;
+  auto load_W = [&](T W[5][4]) {
     for (int t = 0; t < 5; ++t) {
-      const V4<double> a = Gv[launder(id[t])];
-      W[t][0] = a.x; W[t][1] = a.y; W[t][2] = a.z; W[t][3] = a.w;
+      const V4<T> a = Gv[launder(id[t])];
+      W[t][0] = full(a.x, 0); W[t][1] = full(a.y, 1); W[t][2] = full(a.z, 2);
+      W[t][3] = full(a.w, 3);
     }
   };
-  auto load_w5 = [&](double w5[5][3]) {
-    const double* b = launder(w5p);
+  auto load_w5 = [&](T w5[5][3]) {
+    const T* b = launder(w5p);
     for (int t = 0; t < 5; ++t)
       for (int k = 0; k < 3; ++k) w5[t][k] = b[int64_t(3 * t + k) * ne];
   };
-  auto load_w3 = [&](double w3[9]) {
-    const double* b = launder(w3p);
+  auto load_w3 = [&](T w3[9]) {
+    const T* b = launder(w3p);
     for (int j = 0; j < 9; ++j) w3[j] = b[int64_t(j) * ne];
   };
   // projected node values of component q
-  auto proj = [&](const double L[4][4], const double W[5][4], int q, double cq[5]) {
+  auto proj = [&](const T L[4][4], const T W[5][4], int q, T cq[5]) {
     for (int t = 0; t < 5; ++t)
       cq[t] = L[q][0] * W[t][0] + L[q][1] * W[t][1] + L[q][2] * W[t][2] + L[q][3] * W[t][3];
   };
   // smoothness indicators, WENO weights and 3-node values of component q
-  auto weno_parts = [&](const double w3[9], const double cq[5], double be[3], double al[3],
-                        double& sal, double om[3], double Sk[3]) {
-    const double t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
-    const double t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
-    const double t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
-    be[0] = 13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2;
-    be[1] = 13.0 / 12.0 * t3 * t3 + 0.25 * t4 * t4;
-    be[2] = 13.0 / 12.0 * t5 * t5 + 0.25 * t6 * t6;
-    sal = 0.0;
+  auto weno_parts = [&](const T w3[9], const T cq[5], T be[3], T al[3],
+                        T& sal, T om[3], T Sk[3]) {
+    const T t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
+    const T t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
+    const T t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
+    be[0] = T(13.0) / T(12.0) * t1 * t1 + T(0.25) * t2 * t2;
+    be[1] = T(13.0) / T(12.0) * t3 * t3 + T(0.25) * t4 * t4;
+    be[2] = T(13.0) / T(12.0) * t5 * t5 + T(0.25) * t6 * t6;
+    sal = T(0.0);
     for (int k = 0; k < 3; ++k) {
       al[k] = dw[k] / ((eps + be[k]) * (eps + be[k]));
       sal += al[k];
     }
     for (int k = 0; k < 3; ++k) om[k] = al[k] / sal;
     for (int k = 0; k < 3; ++k) {
-      double sk = 0.0;
+      T sk = T(0.0);
       for (int t = 0; t < 3; ++t) sk += w3[3 * k + t] * cq[k + t];
       Sk[k] = sk;
     }
@@ -261,27 +280,27 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
 
   // ---- forward ---------------------------------------------------------------------
   bool weno[4];
-  double hs[4] = {0, 0, 0, 0}, C[4], wm[4], wl[4], wr[4], sl, sr, lam;
+  T hs[4] = {0, 0, 0, 0}, C[4], wm[4], wl[4], wr[4], sl, sr, lam;
   {
-    double A[4], B[4], sa, sb, D, pa, pb, u, v, H, cc, L[4][4], R[4][4];
+    T A[4], B[4], sa, sb, D, pa, pb, u, v, H, cc, L[4][4], R[4][4];
     roe(A, B, sa, sb, D, pa, pb, u, v, H, cc);
     eig(u, v, H, cc, L, R);
-    double W[5][4], w5[5][3], w3[9];
+    T W[5][4], w5[5][3], w3[9];
     load_W(W);
     load_w5(w5);
     load_w3(w3);
     for (int t = 0; t < 5; ++t) {
-      const V4<double> bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
-      const double X[4] = {bx.x, bx.y, bx.z, bx.w}, Y[4] = {by.x, by.y, by.z, by.w};
+      const V4<T> bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
+      const T X[4] = {bx.x, bx.y, bx.z, bx.w}, Y[4] = {by.x, by.y, by.z, by.w};
       for (int q = 0; q < 4; ++q) hs[q] += w5[t][0] * W[t][q] + w5[t][1] * X[q] + w5[t][2] * Y[q];
     }
     for (int q = 0; q < 4; ++q) {
-      double cq[5], be[3], al[3], sal, om[3], Sk[3];
+      T cq[5], be[3], al[3], sal, om[3], Sk[3];
       proj(L, W, q, cq);
       weno_parts(w3, cq, be, al, sal, om, Sk);
       bool wq;
       if (force) wq = (fm >> (4 * s + q)) & 1;
-      else if (gp.sw == HFD_SWITCH_PAPER) wq = !(om[0] > gp.sw_lo && om[0] < gp.sw_hi);
+      else if (gp.sw == HFD_SWITCH_PAPER) wq = !(om[0] > T(gp.sw_lo) && om[0] < T(gp.sw_hi));
       else wq = (gp.sw == HFD_SWITCH_WENO_ONLY);
       weno[q] = wq;
       C[q] = wq ? om[0] * Sk[0] + om[1] * Sk[1] + om[2] * Sk[2]
@@ -289,11 +308,11 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
     }
     for (int r = 0; r < 4; ++r) wm[r] = R[r][0] * C[0] + R[r][1] * C[1] + R[r][2] * C[2] + R[r][3] * C[3];
     for (int r = 0; r < 4; ++r) {
-      const double o = dpp_mov<0xB1>(wm[r]);  // the partner lane's state
+      const T o = dpp_mov<0xB1>(wm[r]);  // the partner lane's state
       wl[r] = s == 0 ? wm[r] : o;
       wr[r] = s == 0 ? o : wm[r];
     }
-    double fl[4], fr[4];
+    T fl[4], fr[4];
     cart_flux_n(wl, nx, ny, gm1, fl, &sl, gam);
     cart_flux_n(wr, nx, ny, gm1, fr, &sr, gam);
     lam = sl >= sr ? sl : sr;
@@ -303,59 +322,59 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
   // them in registers through the forward pass: the compiler barriers keep
   // it from reusing the forward's copies.
   asm volatile("" ::: "memory");
-  double u, v, H, cc, L[4][4], R[4][4];
+  T u, v, H, cc, L[4][4], R[4][4];
   {
-    double A[4], B[4], sa, sb, D, pa, pb;
+    T A[4], B[4], sa, sb, D, pa, pb;
     roe(A, B, sa, sb, D, pa, pb, u, v, H, cc);
   }
   eig(u, v, H, cc, L, R);
-  const double q2 = u * u + v * v;
-  const double un = u * nx + v * ny;
-  const double b1 = gm1 / (cc * cc), b2 = 0.5 * b1 * q2, ic = 1.0 / cc;
+  const T q2 = u * u + v * v;
+  const T un = u * nx + v * ny;
+  const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1.0) / cc;
 
   // ---- reverse: Rusanov flux -> this side's state ------------------------------------
-  const V4<double> g4 = lh[e];
-  const double gh[4] = {g4.x, g4.y, g4.z, g4.w};
-  double glam = 0.0, gw[4];
+  const V4<T> g4 = lh[e];
+  const T gh[4] = {g4.x, g4.y, g4.z, g4.w};
+  T glam = T(0.0), gw[4];
   for (int q = 0; q < 4; ++q) {
-    glam -= 0.5 * gh[q] * (wr[q] - wl[q]);
-    gw[q] = (s == 0 ? 0.5 : -0.5) * lam * gh[q];
+    glam -= T(0.5) * gh[q] * (wr[q] - wl[q]);
+    gw[q] = (s == 0 ? T(0.5) : -T(0.5)) * lam * gh[q];
   }
-  const double half[4] = {0.5 * gh[0], 0.5 * gh[1], 0.5 * gh[2], 0.5 * gh[3]};
+  const T half[4] = {T(0.5) * gh[0], T(0.5) * gh[1], T(0.5) * gh[2], T(0.5) * gh[3]};
   flux_jac_t(wm, nx, ny, gm1, half, gw);
   if ((sl >= sr ? 0 : 1) == s) {
-    double ds[4];
+    T ds[4];
     speed_grad(wm, nx, ny, gam, ds);
     for (int k = 0; k < 4; ++k) gw[k] += glam * ds[k];
   }
   // ---- reverse: this side's reconstruction ----------------------------------------------
   // Gradients of R and L are folded into those of the Roe state (u, v, H, c)
   // as they arise (this side's part; the pair's parts are summed below).
-  const double ic2 = ic * ic;
-  double gu = 0, gv = 0, gH = 0, gc = 0;
-  auto foldL = [&](int q, const double z[4]) {  // z = gradient of row q of L
+  const T ic2 = ic * ic;
+  T gu = 0, gv = 0, gH = 0, gc = 0;
+  auto foldL = [&](int q, const T z[4]) {  // z = gradient of row q of L
     if (q == 0) {
-      gu += z[0] * 0.5 * (b1 * u + nx * ic) + z[1] * (-0.5 * b1);
-      gv += z[0] * 0.5 * (b1 * v + ny * ic) + z[2] * (-0.5 * b1);
-      gc += z[0] * 0.5 * (-2.0 * b2 * ic - un * ic2) + z[1] * 0.5 * (2.0 * b1 * u * ic + nx * ic2) +
-            z[2] * 0.5 * (2.0 * b1 * v * ic + ny * ic2) + z[3] * (-b1 * ic);
+      gu += z[0] * T(0.5) * (b1 * u + nx * ic) + z[1] * (-T(0.5) * b1);
+      gv += z[0] * T(0.5) * (b1 * v + ny * ic) + z[2] * (-T(0.5) * b1);
+      gc += z[0] * T(0.5) * (-T(2.0) * b2 * ic - un * ic2) + z[1] * T(0.5) * (T(2.0) * b1 * u * ic + nx * ic2) +
+            z[2] * T(0.5) * (T(2.0) * b1 * v * ic + ny * ic2) + z[3] * (-b1 * ic);
     } else if (q == 1) {
       gu += z[0] * (-b1 * u) + z[1] * b1;
       gv += z[0] * (-b1 * v) + z[2] * b1;
-      gc += z[0] * (2.0 * b2 * ic) + z[1] * (-2.0 * b1 * u * ic) + z[2] * (-2.0 * b1 * v * ic) +
-            z[3] * (2.0 * b1 * ic);
+      gc += z[0] * (T(2.0) * b2 * ic) + z[1] * (-T(2.0) * b1 * u * ic) + z[2] * (-T(2.0) * b1 * v * ic) +
+            z[3] * (T(2.0) * b1 * ic);
     } else if (q == 2) {
-      gu += z[0] * 0.5 * (b1 * u - nx * ic) + z[1] * (-0.5 * b1);
-      gv += z[0] * 0.5 * (b1 * v - ny * ic) + z[2] * (-0.5 * b1);
-      gc += z[0] * 0.5 * (-2.0 * b2 * ic + un * ic2) + z[1] * 0.5 * (2.0 * b1 * u * ic - nx * ic2) +
-            z[2] * 0.5 * (2.0 * b1 * v * ic - ny * ic2) + z[3] * (-b1 * ic);
+      gu += z[0] * T(0.5) * (b1 * u - nx * ic) + z[1] * (-T(0.5) * b1);
+      gv += z[0] * T(0.5) * (b1 * v - ny * ic) + z[2] * (-T(0.5) * b1);
+      gc += z[0] * T(0.5) * (-T(2.0) * b2 * ic + un * ic2) + z[1] * T(0.5) * (T(2.0) * b1 * u * ic - nx * ic2) +
+            z[2] * T(0.5) * (T(2.0) * b1 * v * ic - ny * ic2) + z[3] * (-b1 * ic);
     } else {
       gu += z[0] * ny;
       gv += z[0] * (-nx);
     }
   };
   {
-    double gR[4][4];
+    T gR[4][4];
     for (int r = 0; r < 4; ++r)
       for (int q = 0; q < 4; ++q) gR[r][q] = gw[r] * C[q];
     gu += gR[1][0] + gR[1][1] + gR[1][2] + gR[3][0] * (-nx * cc) + gR[3][1] * u +
@@ -366,16 +385,16 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
     gc += gR[1][0] * (-nx) + gR[1][2] * nx + gR[2][0] * (-ny) + gR[2][2] * ny +
           gR[3][0] * (-un) + gR[3][2] * un;
   }
-  double gC[4];
+  T gC[4];
   for (int q = 0; q < 4; ++q)
     gC[q] = R[0][q] * gw[0] + R[1][q] * gw[1] + R[2][q] * gw[2] + R[3][q] * gw[3];
-  double W[5][4], w3[9];
+  T W[5][4], w3[9];
   load_W(W);
   load_w3(w3);
-  double gW[5][4] = {}, ghs[4] = {0, 0, 0, 0};
+  T gW[5][4] = {}, ghs[4] = {0, 0, 0, 0};
   for (int q = 0; q < 4; ++q) {
-    const double gCq = gC[q];
-    double z[4];
+    const T gCq = gC[q];
+    T z[4];
     if (!weno[q]) {
       // C_q = L_q . hs
       for (int k = 0; k < 4; ++k) {
@@ -385,10 +404,10 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
       foldL(q, z);
       continue;
     }
-    double cq[5], be[3], al[3], sal, om[3], Sk[3];
+    T cq[5], be[3], al[3], sal, om[3], Sk[3];
     proj(L, W, q, cq);
     weno_parts(w3, cq, be, al, sal, om, Sk);
-    double gcv[5] = {0, 0, 0, 0, 0}, gS[3], gom[3];
+    T gcv[5] = {0, 0, 0, 0, 0}, gS[3], gom[3];
     for (int k = 0; k < 3; ++k) {
       gS[k] = gCq * om[k];
       gom[k] = gCq * Sk[k];
@@ -396,26 +415,26 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
     for (int k = 0; k < 3; ++k)
       for (int t = 0; t < 3; ++t) gcv[k + t] += gS[k] * w3[3 * k + t];
     // omega = alpha / sum(alpha), alpha = d / (eps + beta)^2
-    double dot = 0.0;
+    T dot = T(0.0);
     for (int k = 0; k < 3; ++k) dot += gom[k] * om[k];
-    double gbe[3];
+    T gbe[3];
     for (int k = 0; k < 3; ++k) {
-      const double gal = (gom[k] - dot) / sal;
-      gbe[k] = -2.0 * gal * al[k] / (eps + be[k]);
+      const T gal = (gom[k] - dot) / sal;
+      gbe[k] = -T(2.0) * gal * al[k] / (eps + be[k]);
     }
-    const double t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
-    const double t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
-    const double t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
-    const double gt1 = gbe[0] * (13.0 / 6.0) * t1, gt2 = gbe[0] * 0.5 * t2;
-    const double gt3 = gbe[1] * (13.0 / 6.0) * t3, gt4 = gbe[1] * 0.5 * t4;
-    const double gt5 = gbe[2] * (13.0 / 6.0) * t5, gt6 = gbe[2] * 0.5 * t6;
+    const T t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
+    const T t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
+    const T t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
+    const T gt1 = gbe[0] * (T(13.0) / T(6.0)) * t1, gt2 = gbe[0] * T(0.5) * t2;
+    const T gt3 = gbe[1] * (T(13.0) / T(6.0)) * t3, gt4 = gbe[1] * T(0.5) * t4;
+    const T gt5 = gbe[2] * (T(13.0) / T(6.0)) * t5, gt6 = gbe[2] * T(0.5) * t6;
     gcv[0] += gt1 + gt2;
-    gcv[1] += -2.0 * gt1 - 4.0 * gt2 + gt3 + gt4;
-    gcv[2] += gt1 + 3.0 * gt2 - 2.0 * gt3 + gt5 + 3.0 * gt6;
-    gcv[3] += gt3 - gt4 - 2.0 * gt5 - 4.0 * gt6;
+    gcv[1] += -T(2.0) * gt1 - T(4.0) * gt2 + gt3 + gt4;
+    gcv[2] += gt1 + T(3.0) * gt2 - T(2.0) * gt3 + gt5 + T(3.0) * gt6;
+    gcv[3] += gt3 - gt4 - T(2.0) * gt5 - T(4.0) * gt6;
     gcv[4] += gt5 + gt6;
     // cv[q][t] = L[q] . W_t
-    for (int k = 0; k < 4; ++k) z[k] = 0.0;
+    for (int k = 0; k < 4; ++k) z[k] = T(0.0);
     for (int t = 0; t < 5; ++t)
       for (int k = 0; k < 4; ++k) {
         z[k] += gcv[t] * W[t][k];
@@ -425,13 +444,13 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
   }
   // hs = sum_t w5 . data: the value part here, the gradient parts at output
   asm volatile("" ::: "memory");
-  double w5[5][3];
+  T w5[5][3];
   load_w5(w5);
   for (int t = 0; t < 5; ++t)
     for (int k = 0; k < 4; ++k) gW[t][k] += w5[t][0] * ghs[k];
   // sum over the pair in a fixed order (left part + right part)
   {
-    const double ou = dpp_mov<0xB1>(gu), ov = dpp_mov<0xB1>(gv), oH = dpp_mov<0xB1>(gH),
+    const T ou = dpp_mov<0xB1>(gu), ov = dpp_mov<0xB1>(gv), oH = dpp_mov<0xB1>(gH),
                  oc = dpp_mov<0xB1>(gc);
     gu = s == 0 ? gu + ou : ou + gu;
     gv = s == 0 ? gv + ov : ov + gv;
@@ -439,48 +458,48 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
     gc = s == 0 ? gc + oc : oc + gc;
   }
   // c = sqrt(gm1 (H - q2/2))
-  gH += gc * gm1 / (2.0 * cc);
-  gu += gc * (-gm1 * u / (2.0 * cc));
-  gv += gc * (-gm1 * v / (2.0 * cc));
+  gH += gc * gm1 / (T(2.0) * cc);
+  gu += gc * (-gm1 * u / (T(2.0) * cc));
+  gv += gc * (-gm1 * v / (T(2.0) * cc));
   // ---- Roe average -> this lane's end state (node 2 or 3, position 2) ---------------
   {
-    double A[4], B[4], sa, sb, D, pa, pb, u_, v_, H_, cc_;
+    T A[4], B[4], sa, sb, D, pa, pb, u_, v_, H_, cc_;
     roe(A, B, sa, sb, D, pa, pb, u_, v_, H_, cc_);
-    const double gP = gu / D, gQ = gv / D, gK = gH / D;
-    const double gD = -(gu * u + gv * v + gH * H) / D;
-    const double* S = s == 0 ? A : B;
-    double* g = gW[2];
-    const double r = S[0], s_ = s == 0 ? sa : sb, p = s == 0 ? pa : pb;
-    double gs = gD;
+    const T gP = gu / D, gQ = gv / D, gK = gH / D;
+    const T gD = -(gu * u + gv * v + gH * H) / D;
+    const T* S = s == 0 ? A : B;
+    T* g = gW[2];
+    const T r = S[0], s_ = s == 0 ? sa : sb, p = s == 0 ? pa : pb;
+    T gs = gD;
     // P = m/s, Q = n/s, K = (E + p)/s
     g[1] += gP / s_;
     g[2] += gQ / s_;
     gs += -(gP * S[1] + gQ * S[2] + gK * (S[3] + p)) / (s_ * s_);
-    const double gE = gK / s_, gp_ = gK / s_;
+    const T gE = gK / s_, gp_ = gK / s_;
     g[3] += gE;
     // p = gm1 (E - (m^2 + n^2) / (2 r))
     g[3] += gm1 * gp_;
     g[1] += -gm1 * gp_ * S[1] / r;
     g[2] += -gm1 * gp_ * S[2] / r;
-    g[0] += gm1 * gp_ * 0.5 * (S[1] * S[1] + S[2] * S[2]) / (r * r);
+    g[0] += gm1 * gp_ * T(0.5) * (S[1] * S[1] + S[2] * S[2]) / (r * r);
     // s = sqrt(r)
-    g[0] += gs / (2.0 * s_);
+    g[0] += gs / (T(2.0) * s_);
   }
   // ---- shared nodes: position p (1, 2) of one lane is position 5 - p of the
-  // other; each lane adds the partner's contribution to its positions 1, 2.
+  // other; each lane adds the partner's contribution to its positions 1, T(2.)
   // The gradient parts are w5[t][1] ghs and w5[t][2] ghs.
-  double pghs[4], pw5[3][2];
+  T pghs[4], pw5[3][2];
   for (int k = 0; k < 4; ++k) pghs[k] = dpp_mov<0xB1>(ghs[k]);
   for (int p = 1; p <= 2; ++p) {
     pw5[p][0] = dpp_mov<0xB1>(w5[5 - p][1]);
     pw5[p][1] = dpp_mov<0xB1>(w5[5 - p][2]);
     for (int k = 0; k < 4; ++k) gW[p][k] += dpp_mov<0xB1>(gW[5 - p][k]);
   }
-  double* o = out + int64_t(e) * 72;
+  T* o = out + int64_t(e) * 72;
   for (int p = 0; p < 3; ++p) {
     const int j = s == 0 ? p : 5 - p;
     for (int k = 0; k < 4; ++k) {
-      double gx = w5[p][1] * ghs[k], gy = w5[p][2] * ghs[k];
+      T gx = w5[p][1] * ghs[k], gy = w5[p][2] * ghs[k];
       if (p > 0) {
         gx += pw5[p][0] * pghs[k];
         gy += pw5[p][1] * pghs[k];
@@ -502,19 +521,20 @@ k_adj_edge(int64_t ne, EdgeCoef<double> c, GasParams gp, const V4<double>* __res
 // batch.  A transposed DPP reduction leaves the 20 sums in LDS; one lane per
 // vertex applies the flux Jacobians, and the 12 output rows are written in
 // 16-wide runs.
+template <class T>
 __global__ void __launch_bounds__(256)
 k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict__ U,
              const int32_t* __restrict__ vtp, const int32_t* __restrict__ vtv,
-             const double* __restrict__ dv_t, const int32_t* __restrict__ ntp,
+             const T* __restrict__ dv_t, const int32_t* __restrict__ ntp,
              const int32_t* __restrict__ nte, const int8_t* __restrict__ ntj,
-             const double* __restrict__ bnode, const V4<double>* __restrict__ Lv,
-             const V4<double>* __restrict__ Lg, double* __restrict__ out) {
+             const T* __restrict__ bnode, const V4<T>* __restrict__ Lv,
+             const V4<T>* __restrict__ Lg, double* __restrict__ out, AdjCombine<T> rc) {
   constexpr int VPB = 16;
-  __shared__ double sres[VPB][21];
+  __shared__ T sres[VPB][21];
   const int t = threadIdx.x, vl = t / 16, sub = t & 15;
   const int64_t u0 = int64_t(blockIdx.x) * VPB, u = u0 + vl;
-  double acc[32];
-  for (int k = 0; k < 32; ++k) acc[k] = 0.0;
+  T acc[32];
+  for (int k = 0; k < 32; ++k) acc[k] = T(0.0);
   if (u < nowned) {
     // (1) edge-pass contributions; every owned vertex is a stencil node of
     // some edge and lies in its own S(u), so k1 - 1 is an entry in both loops
@@ -527,13 +547,13 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
           ok[i] = b + 16 * i < k1;
           kk[i] = ok[i] ? b + 16 * i : k1 - 1;
         }
-        const double* src[2];
+        const T* src[2];
         for (int i = 0; i < 2; ++i) src[i] = bnode + int64_t(nte[kk[i]]) * 72 + 12 * ntj[kk[i]];
-        double x[2][12];
+        T x[2][12];
         for (int i = 0; i < 2; ++i)
           for (int q = 0; q < 12; ++q) x[i][q] = src[i][q];
         for (int i = 0; i < 2; ++i)
-          for (int q = 0; q < 12; ++q) acc[q] += ok[i] ? x[i][q] : 0.0;
+          for (int q = 0; q < 12; ++q) acc[q] += ok[i] ? x[i][q] : T(0.0);
       }
     }
     // (2) lambda_f (12..15), lambda_g (16..19)
@@ -547,23 +567,23 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
           kk[i] = ok[i] ? b + 16 * i : k1 - 1;
         }
         int v[2];
-        double d[2][6];
+        T d[2][6];
         for (int i = 0; i < 2; ++i) {
           v[i] = vtv[kk[i]];
           for (int q = 0; q < 6; ++q) d[i][q] = dv_t[6 * int64_t(kk[i]) + q];
         }
-        V4<double> l0[2], lx[2], ly[2];
+        V4<T> l0[2], lx[2], ly[2];
         for (int i = 0; i < 2; ++i) {
           l0[i] = Lv[v[i]];
           lx[i] = Lg[2 * int64_t(v[i])];
           ly[i] = Lg[2 * int64_t(v[i]) + 1];
         }
         for (int i = 0; i < 2; ++i) {
-          double dd[6];
-          for (int q = 0; q < 6; ++q) dd[q] = ok[i] ? d[i][q] : 0.0;
-          const double a0[4] = {l0[i].x, l0[i].y, l0[i].z, l0[i].w};
-          const double ax[4] = {lx[i].x, lx[i].y, lx[i].z, lx[i].w};
-          const double ay[4] = {ly[i].x, ly[i].y, ly[i].z, ly[i].w};
+          T dd[6];
+          for (int q = 0; q < 6; ++q) dd[q] = ok[i] ? d[i][q] : T(0.0);
+          const T a0[4] = {l0[i].x, l0[i].y, l0[i].z, l0[i].w};
+          const T ax[4] = {lx[i].x, lx[i].y, lx[i].z, lx[i].w};
+          const T ay[4] = {ly[i].x, ly[i].y, ly[i].z, ly[i].w};
           for (int q = 0; q < 4; ++q) {
             acc[12 + q] -= dd[0] * a0[q] + dd[2] * ax[q] + dd[4] * ay[q];
             acc[16 + q] -= dd[1] * a0[q] + dd[3] * ax[q] + dd[5] * ay[q];
@@ -583,21 +603,38 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
   if (t < VPB && u0 + t < nowned) {
     // A_f^T lambda_f + A_g^T lambda_g at w_u (n = (1, 0) and (0, 1))
     const int64_t uu = u0 + t;
-    const double gm1 = gp.gamma - 1.0;
-    double w[4], lf[4], lg[4], o[4] = {0, 0, 0, 0};
+    const T gm1 = gp.gamma - T(1.0);
+    T w[4], lf[4], lg[4], o[4] = {0, 0, 0, 0};
     for (int q = 0; q < 4; ++q) {
-      w[q] = U[q * nv + uu];
+      w[q] = T(U[q * nv + uu]);
       lf[q] = sres[t][12 + q];
       lg[q] = sres[t][16 + q];
     }
-    flux_jac_t(w, 1.0, 0.0, gm1, lf, o);
-    flux_jac_t(w, 0.0, 1.0, gm1, lg, o);
+    flux_jac_t(w, T(1.0), T(0.0), gm1, lf, o);
+    flux_jac_t(w, T(0.0), T(1.0), gm1, lg, o);
     for (int q = 0; q < 4; ++q) sres[t][q] += o[q];
   }
   __syncthreads();
   if (t < 12 * VPB) {
     const int q = t / VPB, vl2 = t % VPB;
-    if (u0 + vl2 < nowned) out[q * nv + u0 + vl2] = sres[vl2][q];
+    const int64_t uu = u0 + vl2;
+    if (uu < nowned) {
+      const int64_t o = q * nv + uu;
+      const double x = double(sres[vl2][q]);
+      if (out) out[o] = x;
+      if (rc.lam_k) {
+        const double lk = rc.lam_k[o];
+        if (rc.nxt) {
+          const double n = rc.ca * lk + rc.cb * x;
+          rc.nxt[o] = n;
+          if (q < 4) reinterpret_cast<T*>(rc.nGv)[4 * uu + q] = T(n);
+          else reinterpret_cast<T*>(rc.nGg)[8 * uu + (q - 4)] = T(n);
+        }
+        double a = rc.cd * lk + rc.ce * x;
+        if (rc.cc != 0.0) a += rc.cc * rc.acc[o];
+        rc.acc[o] = a;
+      }
+    }
   }
 }
 
@@ -610,19 +647,22 @@ __global__ void k_take_rows(int64_t n, int w, const int32_t* __restrict__ idx,
   dst[i] = src[int64_t(idx[r]) * w + q];
 }
 
-hipError_t launch_adjoint_residual(const AdjointArgs& a, hipStream_t st) {
+template <class T>
+hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
   if (a.ne > 0) {
-    hipLaunchKernelGGL(k_adj_edge_flux, dim3(unsigned((8 * a.ne + 255) / 256)), dim3(256), 0, st,
-                       a.ne, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lh);
-    hipLaunchKernelGGL(k_adj_edge, dim3(unsigned((2 * a.ne + 255) / 256)), dim3(256), 0, st, a.ne,
-                       a.ec, a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
+    hipLaunchKernelGGL(k_adj_edge_flux<T>, dim3(unsigned((8 * a.ne + 255) / 256)), dim3(256), 0,
+                       st, a.ne, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lh);
+    hipLaunchKernelGGL(k_adj_edge<T>, dim3(unsigned((2 * a.ne + 255) / 256)), dim3(256), 0, st,
+                       a.ne, a.ec, a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
   }
   if (a.nowned > 0)
-    hipLaunchKernelGGL(k_adj_vertex, dim3(unsigned((a.nowned + 15) / 16)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_adj_vertex<T>, dim3(unsigned((a.nowned + 15) / 16)), dim3(256), 0, st,
                        a.nowned, a.nv, a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.ntp, a.nte, a.ntj,
-                       a.bnode, a.Lv, a.Lg, a.out);
+                       a.bnode, a.Lv, a.Lg, a.out, a.rc);
   return hipGetLastError();
 }
+template hipError_t launch_adjoint_residual<double>(const AdjointArgs<double>&, hipStream_t);
+template hipError_t launch_adjoint_residual<float>(const AdjointArgs<float>&, hipStream_t);
 
 hipError_t launch_take_rows(int64_t n, int w, const int32_t* idx, const double* src,
                             double* dst, hipStream_t st) {

@@ -76,11 +76,17 @@ struct hfd_ctx {
   int8_t* ntj = nullptr;
   int32_t *gsp = nullptr, *gsr = nullptr, *gsg = nullptr;  // copy source -> ghosts
   int64_t n_gsrc = 0;
-  double *bnode = nullptr, *AL1 = nullptr, *AL2 = nullptr, *AL3 = nullptr, *AB = nullptr;
+  double *bnode = nullptr, *AL1 = nullptr, *AL2 = nullptr, *AL3 = nullptr;
   double *de_t = nullptr, *dv_t = nullptr;  // coefficient rows in transposed order
+  // float32 adjoint (mixed form, allocated at its first use)
+  bool adj_coef32_ready = false;             // fde_t, fdv_t match de_t, dv_t
+  float *fde_t = nullptr, *fdv_t = nullptr, *bnode32 = nullptr;
+  hfd::V4<float>* lh32 = nullptr;
+  hfd::V4<float>* LGv32[2] = {nullptr, nullptr};  // lambda in gather layout,
+  hfd::V4<float>* LGg32[2] = {nullptr, nullptr};  // two for successive stages
   hfd::V4<double>* lh = nullptr;
-  hfd::V4<double>* LGv = nullptr;
-  hfd::V4<double>* LGg = nullptr;
+  hfd::V4<double>* LGv[2] = {nullptr, nullptr};
+  hfd::V4<double>* LGg[2] = {nullptr, nullptr};
   // measurement: event pairs around the edge (0) and vertex (1) passes
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -440,6 +446,7 @@ hfd_status ensure_adjoint_coefs(hfd_ctx* c) {
   HIPCHK(c, hfd::launch_take_rows(nvs, 6, c->vts, c->dv, c->dv_t, nullptr));
   HIPCHK(c, hipStreamSynchronize(nullptr));
   c->adj_coef_ready = true;
+  c->adj_coef32_ready = false;
   return HFD_OK;
 }
 
@@ -514,40 +521,96 @@ hfd_status ensure_adjoint(hfd_ctx* c) {
   }
   if ((s = dalloc(c, &c->bnode, 72 * ne)) || (s = dalloc(c, &c->AL1, 12 * nv)) ||
       (s = dalloc(c, &c->AL2, 12 * nv)) || (s = dalloc(c, &c->AL3, 12 * nv)) ||
-      (s = dalloc(c, &c->AB, 12 * nv)) || (s = dalloc(c, &c->lh, ne)) ||
-      (s = dalloc(c, &c->LGv, nv)) || (s = dalloc(c, &c->LGg, 2 * nv)))
+      (s = dalloc(c, &c->lh, ne)) ||
+      (s = dalloc(c, &c->LGv[0], nv)) || (s = dalloc(c, &c->LGg[0], 2 * nv)) ||
+      (s = dalloc(c, &c->LGv[1], nv)) || (s = dalloc(c, &c->LGg[1], 2 * nv)))
     return s;
   c->adj_ready = true;
   return ensure_adjoint_coefs(c);
 }
 
-// out = J(U)^T lam, U given in both layouts (SoA U, gather Gv/Gg)
-hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<double>* Gv,
-                         const hfd::V4<double>* Gg, const double* lam, double* out,
-                         hipStream_t st) {
+// Buffers and coefficients of one precision.
+template <class T> hfd_ctx::Bufs<T>& bufs(hfd_ctx* c);
+template <> hfd_ctx::Bufs<double>& bufs<double>(hfd_ctx* c) { return c->b64; }
+template <> hfd_ctx::Bufs<float>& bufs<float>(hfd_ctx* c) { return c->b32; }
+template <class T> hfd::EdgeCoef<T> ecoef(const hfd_ctx* c);
+template <> hfd::EdgeCoef<double> ecoef<double>(const hfd_ctx* c) { return ecoef64(c); }
+template <> hfd::EdgeCoef<float> ecoef<float>(const hfd_ctx* c) { return ecoef32(c); }
+template <class T> hfd::VertexCoef<T> vcoef(const hfd_ctx* c);
+template <> hfd::VertexCoef<double> vcoef<double>(const hfd_ctx* c) { return vcoef64(c); }
+template <> hfd::VertexCoef<float> vcoef<float>(const hfd_ctx* c) { return vcoef32(c); }
+
+// The float32 adjoint's buffers and coefficient copies (first use in the
+// mixed form; the copies follow the float64 ones).
+hfd_status ensure_adjoint32(hfd_ctx* c) {
+  hfd_status s;
+  if ((s = ensure_adjoint(c))) return s;
+  const int64_t ne = c->hs.ne, nv = c->hs.nv;
+  const int64_t nes = c->info.n_eslots, nvs = c->info.n_vslots;
+  if (!c->fde_t) {
+    if ((s = dalloc(c, &c->fde_t, 3 * nes)) || (s = dalloc(c, &c->fdv_t, 6 * nvs)) ||
+        (s = dalloc(c, &c->bnode32, 72 * ne)) || (s = dalloc(c, &c->lh32, ne)) ||
+        (s = dalloc(c, &c->LGv32[0], nv)) || (s = dalloc(c, &c->LGg32[0], 2 * nv)) ||
+        (s = dalloc(c, &c->LGv32[1], nv)) || (s = dalloc(c, &c->LGg32[1], 2 * nv)))
+      return s;
+    c->adj_coef32_ready = false;
+  }
+  if (!c->adj_coef32_ready) {
+    HIPCHK(c, hfd::launch_cast(3 * nes, c->de_t, c->fde_t, nullptr));
+    HIPCHK(c, hfd::launch_cast(6 * nvs, c->dv_t, c->fdv_t, nullptr));
+    HIPCHK(c, hipStreamSynchronize(nullptr));
+    c->adj_coef32_ready = true;
+  }
+  return HFD_OK;
+}
+
+hfd_status ensure_adjoint_t(hfd_ctx* c) { return mixed(c) ? ensure_adjoint32(c) : ensure_adjoint(c); }
+
+// Lambda gather buffer k (0, 1) of the precision.
+template <class T> hfd::V4<T>* lam_gv(hfd_ctx* c, int k);
+template <> hfd::V4<double>* lam_gv<double>(hfd_ctx* c, int k) { return c->LGv[k]; }
+template <> hfd::V4<float>* lam_gv<float>(hfd_ctx* c, int k) { return c->LGv32[k]; }
+template <class T> hfd::V4<T>* lam_gg(hfd_ctx* c, int k);
+template <> hfd::V4<double>* lam_gg<double>(hfd_ctx* c, int k) { return c->LGg[k]; }
+template <> hfd::V4<float>* lam_gg<float>(hfd_ctx* c, int k) { return c->LGg32[k]; }
+
+// out = J(U)^T lam (owned rows; out may be null when rc consumes it), U given
+// in both layouts (SoA U, gather Gv/Gg of the precision: in float32 the
+// perturbation from w_ref).  lam is read in gather buffer k, converted
+// there first when `convert`; rc: the fused Runge-Kutta combination.
+template <class T>
+hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<T>* Gv,
+                         const hfd::V4<T>* Gg, const double* lam, int k, bool convert,
+                         double* out, const hfd::AdjCombine<T>& rc, hipStream_t st) {
+  constexpr bool f32 = sizeof(T) == 4;
   const hfd::HostSetup& h = c->hs;
-  GasParams zero = gas_params(c, false);
-  HIPCHK(c, hfd::launch_to_gather<double>(h.nv, lam, zero, c->LGv, c->LGg, st));
-  hfd::AdjointArgs a{};
+  hfd::V4<T>* LGv = lam_gv<T>(c, k);
+  hfd::V4<T>* LGg = lam_gg<T>(c, k);
+  // lambda in gather layout, no reference state
+  if (convert)
+    HIPCHK(c, hfd::launch_to_gather<T>(h.nv, lam, gas_params(c, false), LGv, LGg, st));
+  hfd::AdjointArgs<T> a{};
   a.ne = h.ne;
   a.nowned = h.n_owned;
   a.nv = h.nv;
   a.etp = c->etp; a.etv = c->etv;
-  a.de_t = c->de_t;
-  a.Lv = c->LGv; a.Lg = c->LGg;
-  a.lh = c->lh;
-  a.ec = ecoef64(c);
-  a.gp = zero;
+  a.Lv = LGv; a.Lg = LGg;
+  a.ec = ecoef<T>(c);
+  a.gp = gas_params(c, f32);
   a.Gv = Gv; a.Gg = Gg;
   a.force = c->force;
-  a.bnode = c->bnode;
   a.U = U;
   a.vtp = c->vtp; a.vtv = c->vtv;
-  a.dv_t = c->dv_t;
   a.ntp = c->ntp; a.nte = c->nte; a.ntj = c->ntj;
   a.out = out;
-  HIPCHK(c, hfd::launch_adjoint_residual(a, st));
-  HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, out, st));
+  a.rc = rc;
+  if constexpr (f32) {
+    a.de_t = c->fde_t; a.dv_t = c->fdv_t; a.lh = c->lh32; a.bnode = c->bnode32;
+  } else {
+    a.de_t = c->de_t; a.dv_t = c->dv_t; a.lh = c->lh; a.bnode = c->bnode;
+  }
+  HIPCHK(c, hfd::launch_adjoint_residual<T>(a, st));
+  if (out) HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, out, st));
   return HFD_OK;
 }
 
@@ -979,17 +1042,97 @@ hfd_status hfd_adjoint_residual(hfd_ctx* c, const double* U, const double* lam, 
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
   if (c->o.flux != HFD_FLUX_RUSANOV)
     return fail(c, HFD_E_STATE, "the adjoint covers the Rusanov flux only");
-  if ((s = ensure_adjoint(c))) return s;
+  if ((s = ensure_adjoint_t(c))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nv = c->hs.nv;
+  if (mixed(c)) {
+    auto& B = c->b32;
+    HIPCHK(c, hfd::launch_to_gather<float>(nv, U, gas_params(c, true), B.Gv[0], B.Gg[0], st));
+    return adjoint_apply<float>(c, U, B.Gv[0], B.Gg[0], lam, 0, true, out, {}, st);
+  }
   auto& B = c->b64;
-  HIPCHK(c, hfd::launch_to_gather<double>(c->hs.nv, U, gas_params(c, false), B.Gv[0], B.Gg[0], st));
-  return adjoint_apply(c, U, B.Gv[0], B.Gg[0], lam, out, st);
+  HIPCHK(c, hfd::launch_to_gather<double>(nv, U, gas_params(c, false), B.Gv[0], B.Gg[0], st));
+  return adjoint_apply<double>(c, U, B.Gv[0], B.Gg[0], lam, 0, true, out, {}, st);
 }
 
+extern "C++" {
 namespace {
 
 // Adjoint of one RK3 step from U with stages U1, U2 (recomputed into the
-// work buffers when null).
+// work buffers when null), in the context's precision: the stage states in
+// its gather layout, the adjoint residuals in its arithmetic, the
+// Runge-Kutta combinations of lambda in float64.
+template <class T>
+hfd_status rk_step_adjoint_t(hfd_ctx* c, const double* U, const double* U1in,
+                             const double* U2in, double dt, const double* lam_np1,
+                             double* lam_n, hipStream_t st) {
+  constexpr bool f32 = sizeof(T) == 4;
+  const hfd::HostSetup& h = c->hs;
+  const int64_t nv = h.nv, ne = h.ne, no = h.n_owned, n12 = 12 * nv;
+  const int64_t nd = int64_t(h.dir_rows.size());
+  auto& B = bufs<T>(c);
+  const GasParams gp = gas_params(c, f32);
+  const double* Us[3] = {U, U1in, U2in};
+  HIPCHK(c, hfd::launch_to_gather<T>(nv, U, gp, B.Gv[0], B.Gg[0], st));
+  if (U1in) {
+    // the given stages in gather layout, Dirichlet rows from U
+    for (int k = 1; k < 3; ++k) {
+      HIPCHK(c, hfd::launch_to_gather<T>(nv, Us[k], gp, B.Gv[k], B.Gg[k], st));
+      HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
+                                                B.Gg[k], st));
+    }
+  } else {
+    // forward stages 1 and 2: U1, U2 and their gather copies
+    for (int k = 1; k < 3; ++k)
+      HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
+                                                B.Gg[k], st));
+    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
+    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
+    const double a[2] = {0.0, 0.75}, b[2] = {1.0, 0.25};
+    const double* in[2] = {U, c->U1};
+    double* outp[2] = {c->U1, c->U2};
+    for (int k = 0; k < 2; ++k) {
+      HIPCHK(c, hfd::launch_edge<T>(ne, ecoef<T>(c), gp, B.Gv[k], B.Gg[k], c->force, B.H,
+                                    nullptr, nullptr, nullptr, st));
+      hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, nullptr};
+      HIPCHK(c, hfd::launch_vertex<T>(no, nv, vcoef<T>(c), gp, B.Gv[k], B.Gg[k], B.H, 1,
+                                      nullptr, rk, B.Gv[k + 1], B.Gg[k + 1], c->flag, st));
+    }
+    Us[1] = c->U1;
+    Us[2] = c->U2;
+  }
+  // reverse.  A3 = lam_{n+1} with the final ghost fill transposed (lam_{n+1}
+  // itself when there are no copying ghosts).  The combinations of each
+  // stage run in the epilogue of its vertex pass (owned rows), which also
+  // writes the next stage's lambda in gather layout (the two buffers
+  // alternate: a stage reads one while its epilogue writes the other).
+  hfd_status s;
+  double *L2 = c->AL2, *L1 = c->AL1;
+  const double* A3 = lam_np1;
+  if (c->n_gsrc > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->AL3, lam_np1, n12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hfd::launch_adj_copy_ghosts(c->n_gsrc, c->gsp, c->gsr, c->gsg, nv, c->AL3, st));
+    A3 = c->AL3;
+  }
+  // stage 3: U3 = U/3 + 2/3 (U2 + dt R(U2)):
+  //   L2 = 2/3 A3 + 2/3 dt J^T A3, lam_n = 1/3 A3
+  const hfd::AdjCombine<T> r3{A3, L2, lam_gv<T>(c, 1), lam_gg<T>(c, 1), lam_n,
+                              2.0 / 3.0, 2.0 / 3.0 * dt, 0.0, 1.0 / 3.0, 0.0};
+  if ((s = adjoint_apply<T>(c, Us[2], B.Gv[2], B.Gg[2], A3, 0, true, nullptr, r3, st))) return s;
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1)):
+  //   L1 = 1/4 L2 + 1/4 dt J^T L2, lam_n += 3/4 L2
+  const hfd::AdjCombine<T> r2{L2, L1, lam_gv<T>(c, 0), lam_gg<T>(c, 0), lam_n,
+                              0.25, 0.25 * dt, 1.0, 0.75, 0.0};
+  if ((s = adjoint_apply<T>(c, Us[1], B.Gv[1], B.Gg[1], L2, 1, false, nullptr, r2, st))) return s;
+  // stage 1: U1 = U + dt R(U):  lam_n += L1 + dt J^T L1
+  const hfd::AdjCombine<T> r1{L1, nullptr, nullptr, nullptr, lam_n, 0.0, 0.0, 1.0, 1.0, dt};
+  if ((s = adjoint_apply<T>(c, U, B.Gv[0], B.Gg[0], L1, 0, false, nullptr, r1, st))) return s;
+  // ghost rows: Dirichlet rows pass lam_{n+1} through, copies carry nothing
+  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, A3, lam_n, st));
+  HIPCHK(c, hfd::launch_zero_ghost_rows(no + nd, nv, lam_n, st));
+  return HFD_OK;
+}
+
 hfd_status rk_step_adjoint_impl(hfd_ctx* c, const double* U, const double* U1in,
                                 const double* U2in, double dt, const double* lam_np1,
                                 double* lam_n, hipStream_t st) {
@@ -999,63 +1142,13 @@ hfd_status rk_step_adjoint_impl(hfd_ctx* c, const double* U, const double* U1in,
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
   if (c->o.flux != HFD_FLUX_RUSANOV)
     return fail(c, HFD_E_STATE, "the adjoint covers the Rusanov flux only");
-  if ((s = ensure_adjoint(c))) return s;
-  const hfd::HostSetup& h = c->hs;
-  const int64_t nv = h.nv, ne = h.ne, no = h.n_owned, n12 = 12 * nv;
-  const int64_t nd = int64_t(h.dir_rows.size());
-  auto& B = c->b64;
-  const GasParams gp = gas_params(c, false);
-  const double* Us[3] = {U, U1in, U2in};
-  HIPCHK(c, hfd::launch_to_gather<double>(nv, U, gp, B.Gv[0], B.Gg[0], st));
-  if (U1in) {
-    // the given stages in gather layout, Dirichlet rows from U
-    for (int k = 1; k < 3; ++k) {
-      HIPCHK(c, hfd::launch_to_gather<double>(nv, Us[k], gp, B.Gv[k], B.Gg[k], st));
-      HIPCHK(c, hfd::launch_copy_gather_rows<double>(nd, c->dir_rows, B.Gv[0], B.Gg[0],
-                                                     B.Gv[k], B.Gg[k], st));
-    }
-  } else {
-    // forward stages 1 and 2 (float64): U1, U2 and their gather copies
-    for (int k = 1; k < 3; ++k)
-      HIPCHK(c, hfd::launch_copy_gather_rows<double>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
-                                                     B.Gg[k], st));
-    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U1, st));
-    HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, U, c->U2, st));
-    const double a[2] = {0.0, 0.75}, b[2] = {1.0, 0.25};
-    const double* in[2] = {U, c->U1};
-    double* outp[2] = {c->U1, c->U2};
-    for (int k = 0; k < 2; ++k) {
-      HIPCHK(c, hfd::launch_edge<double>(ne, ecoef64(c), gp, B.Gv[k], B.Gg[k], c->force, B.H,
-                                         nullptr, nullptr, nullptr, st));
-      hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, nullptr};
-      HIPCHK(c, hfd::launch_vertex<double>(no, nv, vcoef64(c), gp, B.Gv[k], B.Gg[k], B.H, 1,
-                                           nullptr, rk, B.Gv[k + 1], B.Gg[k + 1], c->flag, st));
-    }
-    Us[1] = c->U1;
-    Us[2] = c->U2;
-  }
-  // reverse.  A3 = lam_{n+1} with the final ghost fill transposed
-  double *A3 = c->AL3, *L2 = c->AL2, *L1 = c->AL1, *Bt = c->AB;
-  HIPCHK(c, hipMemcpyAsync(A3, lam_np1, n12 * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HIPCHK(c, hfd::launch_adj_copy_ghosts(c->n_gsrc, c->gsp, c->gsr, c->gsg, nv, A3, st));
-  // stage 3: U3 = U/3 + 2/3 (U2 + dt R(U2))
-  if ((s = adjoint_apply(c, Us[2], B.Gv[2], B.Gg[2], A3, Bt, st))) return s;
-  HIPCHK(c, hfd::launch_axpbypcz(n12, 2.0 / 3.0, A3, 2.0 / 3.0 * dt, Bt, 0.0, nullptr, L2, st));
-  HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0 / 3.0, A3, 0.0, A3, 0.0, nullptr, lam_n, st));
-  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt R(U1))
-  if ((s = adjoint_apply(c, Us[1], B.Gv[1], B.Gg[1], L2, Bt, st))) return s;
-  HIPCHK(c, hfd::launch_axpbypcz(n12, 0.25, L2, 0.25 * dt, Bt, 0.0, nullptr, L1, st));
-  HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0, lam_n, 0.75, L2, 0.0, nullptr, lam_n, st));
-  // stage 1: U1 = U + dt R(U)
-  if ((s = adjoint_apply(c, U, B.Gv[0], B.Gg[0], L1, Bt, st))) return s;
-  HIPCHK(c, hfd::launch_axpbypcz(n12, 1.0, lam_n, 1.0, L1, dt, Bt, lam_n, st));
-  // ghost rows: Dirichlet rows pass lam_{n+1} through, copies carry nothing
-  HIPCHK(c, hfd::launch_copy_rows<double>(nd, c->dir_rows, nullptr, nv, A3, lam_n, st));
-  HIPCHK(c, hfd::launch_zero_ghost_rows(no + nd, nv, lam_n, st));
-  return HFD_OK;
+  if ((s = ensure_adjoint_t(c))) return s;
+  if (mixed(c)) return rk_step_adjoint_t<float>(c, U, U1in, U2in, dt, lam_np1, lam_n, st);
+  return rk_step_adjoint_t<double>(c, U, U1in, U2in, dt, lam_np1, lam_n, st);
 }
 
 }  // namespace
+}  // extern "C++"
 
 hfd_status hfd_rk_step_adjoint(hfd_ctx* c, const double* U, double dt, const double* lam_np1,
                                double* lam_n, void* stream) {
@@ -1076,6 +1169,9 @@ hfd_status hfd_rk_step_stages(hfd_ctx* c, double* U, double dt, double* U1, doub
   hfd_status s = need_device(c);
   if (s) return s;
   if (!U || !U1 || !U2) return fail(c, HFD_E_INVAL, "null state");
+  if (mixed(c))
+    return rk_step_t<float>(c, c->b32, ecoef32(c), vcoef32(c), true, U, dt, nullptr,
+                            static_cast<hipStream_t>(stream), U1, U2);
   return rk_step_t<double>(c, c->b64, ecoef64(c), vcoef64(c), false, U, dt, nullptr,
                            static_cast<hipStream_t>(stream), U1, U2);
 }

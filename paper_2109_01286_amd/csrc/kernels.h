@@ -158,27 +158,44 @@ hipError_t launch_cast(int64_t n, const double* a, float* b, hipStream_t st);
 hipError_t launch_widen(int64_t n, const float* a, double* b, hipStream_t st);
 
 // ---- adjoint (float64, Euler) ---------------------------------------------------
+// Runge-Kutta combination fused into the adjoint's vertex pass, owned rows
+// o (x = (J^T lam)[o]): nxt = ca lam_k + cb x, also written in gather layout
+// (nGv, nGg, the lambda of the next stage); acc = cc acc + cd lam_k + ce x
+// (acc not read when cc == 0).  lam_k == null: nothing.
+template <class T>
+struct AdjCombine {
+  const double* lam_k;
+  double* nxt;
+  V4<T>* nGv;
+  V4<T>* nGg;
+  double* acc;
+  double ca, cb, cc, cd, ce;
+};
+
+template <class T>
 struct AdjointArgs {
   int64_t ne, nowned, nv;
   const int32_t *etp, *etv;         // edge m <- (owner vertex, edge slot)
-  const double* de_t;               // de rows in the order of etv
-  const V4<double>* Lv;             // lambda in gather layout
-  const V4<double>* Lg;
-  V4<double>* lh;                   // [ne] flux adjoint
-  EdgeCoef<double> ec;
-  GasParams gp;
-  const V4<double>* Gv;             // state in gather layout
-  const V4<double>* Gg;
+  const T* de_t;                    // de rows in the order of etv
+  const V4<T>* Lv;                  // lambda in gather layout
+  const V4<T>* Lg;
+  V4<T>* lh;                        // [ne] flux adjoint
+  EdgeCoef<T> ec;
+  GasParams gp;                     // float32: with the reference state of Gv
+  const V4<T>* Gv;                  // state in gather layout
+  const V4<T>* Gg;
   const uint8_t* force;
-  double* bnode;                    // [ne][6][12] edge-pass contributions
+  T* bnode;                         // [ne][6][12] edge-pass contributions
   const double* U;                  // state [12][nv]
   const int32_t *vtp, *vtv;         // gather row <- (owner vertex, vertex slot)
-  const double* dv_t;               // dv rows in the order of vtv
+  const T* dv_t;                    // dv rows in the order of vtv
   const int32_t *ntp, *nte;         // gather row <- (edge, stencil position)
   const int8_t* ntj;
-  double* out;                      // [12][nv], owned rows written
+  double* out;                      // [12][nv], owned rows written, or null
+  AdjCombine<T> rc;
 };
-hipError_t launch_adjoint_residual(const AdjointArgs& a, hipStream_t st);
+template <class T>
+hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st);
 // dst[i][0..w) = src[idx[i]][0..w), i < n (transposed coefficient copies)
 hipError_t launch_take_rows(int64_t n, int w, const int32_t* idx, const double* src,
                             double* dst, hipStream_t st);

@@ -328,7 +328,8 @@ class Solver:
         self._chk(lib().hfd_force_switch_mask(self._h, _dptr(mask)))
 
     def adjoint_residual(self, U, lam, out=None):
-        """(dR/dU)^T lam (float64 device tensors [12, V], internal order)."""
+        """(dR/dU)^T lam (float64 device tensors [12, V], internal order),
+        computed in the context's precision."""
         import torch
         if out is None:
             out = torch.empty_like(U)
@@ -346,8 +347,8 @@ class Solver:
         return out
 
     def rk_step_stages(self, U, dt, U1, U2):
-        """One float64 RK3 step in place that also writes its intermediate
-        stages into U1, U2 (device tensors shaped like U)."""
+        """One RK3 step in place (the context's precision) that also writes
+        its intermediate stages into U1, U2 (device tensors shaped like U)."""
         self._chk(lib().hfd_rk_step_stages(self._h, _dptr(U), float(dt), _dptr(U1), _dptr(U2),
                                            _stream()))
         return U
