@@ -102,7 +102,7 @@ def measured_traffic(workload, kernel):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("workload") != workload or d.get("kernels_hip_sha256") != profile_summary.source_digest():
+    if d.get("workload") != workload or d.get("kernel_sources_sha256") != profile_summary.source_digest():
         return None
     for name, v in d["per_launch"].items():
         if name.startswith(kernel):

@@ -212,9 +212,8 @@ hfd_status hfd_import_weights(hfd_ctx* ctx, const double* w5, const double* w3,
 hfd_status hfd_set_precision(hfd_ctx* ctx, int32_t precision,
                              const double* w_ref);
 
-/* Riemann flux (hfd_flux) of later residual and step calls; the weights do
- * not depend on it.  Errors: HFD_E_INVAL for another value.  The adjoint
- * entry points require HFD_FLUX_RUSANOV (HFD_E_STATE otherwise). */
+/* Riemann flux (hfd_flux) of later residual, step and adjoint calls; the
+ * weights do not depend on it.  Errors: HFD_E_INVAL for another value. */
 hfd_status hfd_set_flux(hfd_ctx* ctx, int32_t flux);
 
 /* dU = right-hand side of eq. HWENO at state U (device, [12][nv] float64
@@ -265,7 +264,9 @@ hfd_status hfd_check(hfd_ctx* ctx, void* stream);
  * written in float64.  The
  * branch of eq. 2d_hweno_intp and the WENO weights are differentiated
  * through the branch the forward pass takes, the Rusanov maximum through its
- * larger argument.  Rows of ghost vertices of out are zero (derivatives with
+ * larger argument; the Roe and HLLC fluxes by forward-mode dual numbers
+ * through the branches they take (entropy fix, wave speeds, HLLC region).
+ * Rows of ghost vertices of out are zero (derivatives with
  * respect to copying ghosts land on their sources; Dirichlet data are
  * constants).  Allocates transposed maps and work buffers on first use. */
 hfd_status hfd_adjoint_residual(hfd_ctx* ctx, const double* U, const double* lam,

@@ -24,6 +24,7 @@
 // argument.  Euler only (viscous fluxes are not differentiated).
 #include <hip/hip_runtime.h>
 
+#include "gas.h"
 #include "kernels.h"
 
 #ifndef ADJ_EDGE_WAVES
@@ -32,6 +33,64 @@
 
 namespace hfd {
 namespace {
+
+// Forward-mode dual number: a value and its derivative along one direction.
+// The adjoint of the Roe and HLLC fluxes runs their code (gas.h) on it, one
+// direction per component of the lane's interface state, so that every
+// branch the flux takes (entropy fix, wave-speed minimum and maximum, HLLC
+// region) is differentiated as taken.
+// (the overloads below would hide the plain ones inside namespace hfd)
+using ::fabs;
+using ::fmax;
+using ::fmin;
+using ::isnan;
+using ::sqrt;
+
+template <class B>
+struct Dual {
+  B v, d;
+  Dual() = default;
+  __device__ Dual(B x) : v(x), d(B(0)) {}
+  __device__ Dual(B x, B y) : v(x), d(y) {}
+};
+template <class B>
+__device__ inline Dual<B> operator+(Dual<B> a, Dual<B> b) { return {a.v + b.v, a.d + b.d}; }
+template <class B>
+__device__ inline Dual<B> operator-(Dual<B> a, Dual<B> b) { return {a.v - b.v, a.d - b.d}; }
+template <class B>
+__device__ inline Dual<B> operator-(Dual<B> a) { return {-a.v, -a.d}; }
+template <class B>
+__device__ inline Dual<B> operator*(Dual<B> a, Dual<B> b) {
+  return {a.v * b.v, a.d * b.v + a.v * b.d};
+}
+template <class B>
+__device__ inline Dual<B> operator/(Dual<B> a, Dual<B> b) {
+  const B q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+template <class B>
+__device__ inline Dual<B>& operator+=(Dual<B>& a, Dual<B> b) { return a = a + b; }
+template <class B>
+__device__ inline bool operator<(Dual<B> a, Dual<B> b) { return a.v < b.v; }
+template <class B>
+__device__ inline bool operator>(Dual<B> a, Dual<B> b) { return a.v > b.v; }
+template <class B>
+__device__ inline bool operator<=(Dual<B> a, Dual<B> b) { return a.v <= b.v; }
+template <class B>
+__device__ inline bool operator>=(Dual<B> a, Dual<B> b) { return a.v >= b.v; }
+template <class B>
+__device__ inline Dual<B> sqrt(Dual<B> a) {
+  const B r = sqrt(a.v);
+  return {r, a.d / (B(2) * r)};
+}
+template <class B>
+__device__ inline Dual<B> fabs(Dual<B> a) { return a.v < B(0) ? -a : a; }
+template <class B>
+__device__ inline Dual<B> fmin(Dual<B> a, Dual<B> b) { return b.v < a.v ? b : a; }
+template <class B>
+__device__ inline Dual<B> fmax(Dual<B> a, Dual<B> b) { return b.v > a.v ? b : a; }
+template <class B>
+__device__ inline bool isnan(Dual<B> a) { return isnan(a.v); }
 
 // derivative of F(w).n transposed, applied to g: out += A_n(w)^T g
 template <class T>
@@ -166,8 +225,10 @@ k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __r
 // the four scalar gradients of the Roe state (u, v, H, c) and the
 // contributions to the nodes both sides share, then lane 0 writes nodes
 // 0, 1, 2 and lane 1 nodes 5, 4, 3 (positions 0, 1, 2 of each lane).
-template <class T>
-__global__ void __launch_bounds__(256, ADJ_EDGE_WAVES)
+// (the Roe and HLLC variants carry the dual-number flux: one wave per SIMD,
+// the whole register file)
+template <class T, int FLUX>
+__global__ void __launch_bounds__(256, FLUX == HFD_FLUX_RUSANOV ? ADJ_EDGE_WAVES : 1)
 k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
            const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
            const V4<T>* __restrict__ lh, T* __restrict__ out) {
@@ -312,10 +373,14 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       wl[r] = s == 0 ? wm[r] : o;
       wr[r] = s == 0 ? o : wm[r];
     }
-    T fl[4], fr[4];
-    cart_flux_n(wl, nx, ny, gm1, fl, &sl, gam);
-    cart_flux_n(wr, nx, ny, gm1, fr, &sr, gam);
-    lam = sl >= sr ? sl : sr;
+    if constexpr (FLUX == HFD_FLUX_RUSANOV) {
+      T fl[4], fr[4];
+      cart_flux_n(wl, nx, ny, gm1, fl, &sl, gam);
+      cart_flux_n(wr, nx, ny, gm1, fr, &sr, gam);
+      lam = sl >= sr ? sl : sr;
+    } else {
+      sl = sr = lam = T(0);
+    }
   }
   // The reverse reads the node values and coefficient rows again (cache hits)
   // and recomputes the Roe state where it needs them, instead of holding
@@ -332,20 +397,41 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   const T un = u * nx + v * ny;
   const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1.0) / cc;
 
-  // ---- reverse: Rusanov flux -> this side's state ------------------------------------
+  // ---- reverse: Riemann flux -> this side's state ------------------------------------
   const V4<T> g4 = lh[e];
   const T gh[4] = {g4.x, g4.y, g4.z, g4.w};
-  T glam = T(0.0), gw[4];
-  for (int q = 0; q < 4; ++q) {
-    glam -= T(0.5) * gh[q] * (wr[q] - wl[q]);
-    gw[q] = (s == 0 ? T(0.5) : -T(0.5)) * lam * gh[q];
-  }
-  const T half[4] = {T(0.5) * gh[0], T(0.5) * gh[1], T(0.5) * gh[2], T(0.5) * gh[3]};
-  flux_jac_t(wm, nx, ny, gm1, half, gw);
-  if ((sl >= sr ? 0 : 1) == s) {
-    T ds[4];
-    speed_grad(wm, nx, ny, gam, ds);
-    for (int k = 0; k < 4; ++k) gw[k] += glam * ds[k];
+  T gw[4];
+  if constexpr (FLUX == HFD_FLUX_RUSANOV) {
+    T glam = T(0.0);
+    for (int q = 0; q < 4; ++q) {
+      glam -= T(0.5) * gh[q] * (wr[q] - wl[q]);
+      gw[q] = (s == 0 ? T(0.5) : -T(0.5)) * lam * gh[q];
+    }
+    const T half[4] = {T(0.5) * gh[0], T(0.5) * gh[1], T(0.5) * gh[2], T(0.5) * gh[3]};
+    flux_jac_t(wm, nx, ny, gm1, half, gw);
+    if ((sl >= sr ? 0 : 1) == s) {
+      T ds[4];
+      speed_grad(wm, nx, ny, gam, ds);
+      for (int k = 0; k < 4; ++k) gw[k] += glam * ds[k];
+    }
+  } else {
+    // gw[k] = gh . dh/d(w_side)[k]: the flux on dual numbers seeded with
+    // direction k of this lane's state (full states, zero reference)
+    GasParams gz = gp;
+    for (int q = 0; q < 4; ++q) gz.wref[q] = 0.0;
+    const Ref<Dual<T>> rz = make_ref<Dual<T>>(gz);
+    for (int k = 0; k < 4; ++k) {
+      Dual<T> Ld[4], Rd[4], hd[4];
+      for (int q = 0; q < 4; ++q) {
+        Ld[q] = Dual<T>(wl[q], s == 0 && q == k ? T(1) : T(0));
+        Rd[q] = Dual<T>(wr[q], s == 1 && q == k ? T(1) : T(0));
+      }
+      if constexpr (FLUX == HFD_FLUX_ROE)
+        roe_flux<Dual<T>>(Ld, Rd, Dual<T>(nx), Dual<T>(ny), rz, Dual<T>(gm1), hd);
+      else
+        hllc_flux<Dual<T>>(Ld, Rd, Dual<T>(nx), Dual<T>(ny), rz, Dual<T>(gam), Dual<T>(gm1), hd);
+      gw[k] = gh[0] * hd[0].d + gh[1] * hd[1].d + gh[2] * hd[2].d + gh[3] * hd[3].d;
+    }
   }
   // ---- reverse: this side's reconstruction ----------------------------------------------
   // Gradients of R and L are folded into those of the Roe state (u, v, H, c)
@@ -652,8 +738,16 @@ hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
   if (a.ne > 0) {
     hipLaunchKernelGGL(k_adj_edge_flux<T>, dim3(unsigned((8 * a.ne + 255) / 256)), dim3(256), 0,
                        st, a.ne, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lh);
-    hipLaunchKernelGGL(k_adj_edge<T>, dim3(unsigned((2 * a.ne + 255) / 256)), dim3(256), 0, st,
-                       a.ne, a.ec, a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
+    const dim3 grid(unsigned((2 * a.ne + 255) / 256));
+    if (a.gp.flux == HFD_FLUX_ROE)
+      hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_ROE>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
+                         a.Gv, a.Gg, a.force, a.lh, a.bnode);
+    else if (a.gp.flux == HFD_FLUX_HLLC)
+      hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_HLLC>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
+                         a.Gv, a.Gg, a.force, a.lh, a.bnode);
+    else
+      hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_RUSANOV>), grid, dim3(256), 0, st, a.ne, a.ec,
+                         a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
   }
   if (a.nowned > 0)
     hipLaunchKernelGGL(k_adj_vertex<T>, dim3(unsigned((a.nowned + 15) / 16)), dim3(256), 0, st,

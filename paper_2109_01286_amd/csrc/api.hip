@@ -1040,8 +1040,6 @@ hfd_status hfd_adjoint_residual(hfd_ctx* c, const double* U, const double* lam, 
   if (s) return s;
   if (!U || !lam || !out) return fail(c, HFD_E_INVAL, "null pointer");
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
-  if (c->o.flux != HFD_FLUX_RUSANOV)
-    return fail(c, HFD_E_STATE, "the adjoint covers the Rusanov flux only");
   if ((s = ensure_adjoint_t(c))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t nv = c->hs.nv;
@@ -1140,8 +1138,6 @@ hfd_status rk_step_adjoint_impl(hfd_ctx* c, const double* U, const double* U1in,
   if (s) return s;
   if (!U || !lam_np1 || !lam_n) return fail(c, HFD_E_INVAL, "null pointer");
   if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
-  if (c->o.flux != HFD_FLUX_RUSANOV)
-    return fail(c, HFD_E_STATE, "the adjoint covers the Rusanov flux only");
   if ((s = ensure_adjoint_t(c))) return s;
   if (mixed(c)) return rk_step_adjoint_t<float>(c, U, U1in, U2in, dt, lam_np1, lam_n, st);
   return rk_step_adjoint_t<double>(c, U, U1in, U2in, dt, lam_np1, lam_n, st);

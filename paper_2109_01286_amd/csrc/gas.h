@@ -1,0 +1,241 @@
+// Gas model of the hot path, shared by the edge and vertex passes and the
+// adjoint: Euler fluxes in perturbation form about a reference state (zero in
+// the float64 form), the Roe state with its eigenvector matrices, and the
+// Riemann fluxes (Rusanov, Roe with an entropy fix, HLLC; Section 2.3).
+// Templates over the arithmetic type: float, double, and the forward-mode
+// dual numbers through which the adjoint differentiates the Roe and HLLC
+// fluxes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace hfd {
+
+// Division and square root.  float64 keeps the correctly rounded operations;
+// the float32 form uses the hardware reciprocal and square root (about 1 ulp,
+// far below the rounding of its float32 perturbation data) instead of the
+// much longer correctly rounded instruction sequences.
+template <class T>
+__device__ inline T fdiv(T a, T b) {
+  return a / b;
+}
+template <>
+__device__ inline float fdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+template <class T>
+__device__ inline T fsqrt(T x) {
+  return sqrt(x);
+}
+template <>
+__device__ inline float fsqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+
+// Fluxes minus the reference fluxes, from the perturbation w' and the full
+// density/momenta.  With a zero reference these are the plain fluxes.
+template <class T>
+struct Ref {
+  T w[4];   // reference state
+  T u, v;   // reference velocity
+  T etr;    // E + p of the reference
+};
+
+template <class T>
+__device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
+                                 T g[4], T* p_full = nullptr, T* rho_full = nullptr,
+                                 T* u_full = nullptr, T* v_full = nullptr,
+                                 T* p_pert = nullptr) {
+  const T rho = R.w[0] + wp[0];
+  const T m = R.w[1] + wp[1];
+  const T n = R.w[2] + wp[2];
+  const T ir = fdiv(T(1), rho);
+  // m^2/rho - m_r u_r, m n/rho - m_r v_r, n^2/rho - n_r v_r
+  const T amm = (wp[1] * (m + R.w[1]) - R.w[1] * R.u * wp[0]) * ir;
+  const T amn = (wp[1] * n + R.w[1] * wp[2] - R.w[1] * R.v * wp[0]) * ir;
+  const T ann = (wp[2] * (n + R.w[2]) - R.w[2] * R.v * wp[0]) * ir;
+  const T pp = gm1 * (wp[3] - T(0.5) * (amm + ann));  // p - p_r
+  const T du = (wp[1] - R.u * wp[0]) * ir;              // u - u_r
+  const T dv = (wp[2] - R.v * wp[0]) * ir;              // v - v_r
+  const T u = R.u + du, v = R.v + dv;
+  const T etp = wp[3] + pp;                              // (E + p) - (E + p)_r
+  f[0] = wp[1];
+  f[1] = amm + pp;
+  f[2] = amn;
+  f[3] = etp * u + R.etr * du;
+  g[0] = wp[2];
+  g[1] = amn;
+  g[2] = ann + pp;
+  g[3] = etp * v + R.etr * dv;
+  if (p_full) {
+    *p_full = (R.etr - R.w[3]) + pp;
+    *rho_full = rho;
+    *u_full = u;
+    *v_full = v;
+  }
+  if (p_pert) *p_pert = pp;
+}
+
+template <class T>
+__device__ inline Ref<T> make_ref(const GasParams& gp) {
+  Ref<T> r;
+  for (int q = 0; q < 4; ++q) r.w[q] = T(gp.wref[q]);
+  double rho = gp.wref[0];
+  double u = rho > 0 ? gp.wref[1] / rho : 0.0, v = rho > 0 ? gp.wref[2] / rho : 0.0;
+  double p = (gp.gamma - 1.0) * (gp.wref[3] - 0.5 * rho * (u * u + v * v));
+  r.u = T(u);
+  r.v = T(v);
+  r.etr = T(gp.wref[3] + p);
+  return r;
+}
+
+// Roe average of the edge's end states (nodes i, i+1) and the eigenvector
+// matrices of the flux Jacobian along n: R (columns: right eigenvectors for
+// u.n - c, u.n, u.n + c, shear) and its inverse L (rows).
+template <class T>
+struct Frame {
+  T L[4][4], R[4][4];
+  T un, c;  // normal velocity and sound speed of the Roe state
+};
+
+template <class T>
+__device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
+                                     const Ref<T>& ref, T gm1) {
+  const T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
+  const T ua = fdiv(ref.w[1] + A.y, ra), ub = fdiv(ref.w[1] + B.y, rb);
+  const T va = fdiv(ref.w[2] + A.z, ra), vb = fdiv(ref.w[2] + B.z, rb);
+  const T Ea = ref.w[3] + A.w, Eb = ref.w[3] + B.w;
+  const T pa = gm1 * (Ea - T(0.5) * ra * (ua * ua + va * va));
+  const T pb = gm1 * (Eb - T(0.5) * rb * (ub * ub + vb * vb));
+  const T sa = fsqrt(ra), sb = fsqrt(rb);
+  const T iw = fdiv(T(1), sa + sb);
+  const T u = (sa * ua + sb * ub) * iw;
+  const T v = (sa * va + sb * vb) * iw;
+  const T hh = (fdiv(sa * (Ea + pa), ra) + fdiv(sb * (Eb + pb), rb)) * iw;
+  const T cc = fsqrt(gm1 * (hh - T(0.5) * (u * u + v * v)));
+  const T q2 = u * u + v * v;
+  const T un = u * nx + v * ny, ut = -u * ny + v * nx;
+  const T b1 = fdiv(gm1, cc * cc), b2 = T(0.5) * b1 * q2, ic = fdiv(T(1), cc);
+  return Frame<T>{
+      {{T(0.5) * (b2 + un * ic), T(-0.5) * (b1 * u + nx * ic), T(-0.5) * (b1 * v + ny * ic), T(0.5) * b1},
+       {T(1) - b2, b1 * u, b1 * v, -b1},
+       {T(0.5) * (b2 - un * ic), T(-0.5) * (b1 * u - nx * ic), T(-0.5) * (b1 * v - ny * ic), T(0.5) * b1},
+       {-ut, -ny, nx, T(0)}},
+      {{T(1), T(1), T(1), T(0)},
+       {u - cc * nx, u, u + cc * nx, -ny},
+       {v - cc * ny, v, v + cc * ny, nx},
+       {hh - un * cc, T(0.5) * q2, hh + un * cc, ut}},
+      un, cc};
+}
+
+// Rusanov flux along n of the two interface states (perturbation form).
+template <class T>
+__device__ inline void rusanov(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                               T gam, T gm1, T h[4]) {
+  T fl[4], gl[4], fr[4], gr[4], pl, rl, ul, vl, pr, rr, ur, vr;
+  pert_flux<T>(wl, ref, gm1, fl, gl, &pl, &rl, &ul, &vl);
+  pert_flux<T>(wr, ref, gm1, fr, gr, &pr, &rr, &ur, &vr);
+  const T sl = fabs(ul * nx + vl * ny) + fsqrt(fdiv(gam * pl, rl));
+  const T sr = fabs(ur * nx + vr * ny) + fsqrt(fdiv(gam * pr, rr));
+  // NaN-propagating maximum: a non-physical state must not be hidden
+  const T lam = (isnan(sl) || isnan(sr)) ? sl + sr : (sl > sr ? sl : sr);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
+           T(0.5) * lam * (wr[q] - wl[q]);
+}
+
+// Roe's flux at the Roe average of the two interface states, with Harten's
+// entropy fix on the acoustic waves (|lambda| < d -> (lambda^2 + d^2)/(2 d),
+// d = 0.1 (|u.n| + c)); the dissipation acts on w_R - w_L, which the
+// perturbation form gives exactly.
+template <class T>
+__device__ inline void roe_flux(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                                T gm1, T h[4]) {
+  T fl[4], gl[4], fr[4], gr[4];
+  pert_flux<T>(wl, ref, gm1, fl, gl);
+  pert_flux<T>(wr, ref, gm1, fr, gr);
+  const Frame<T> F = roe_frame<T>(V4<T>{wl[0], wl[1], wl[2], wl[3]},
+                                  V4<T>{wr[0], wr[1], wr[2], wr[3]}, nx, ny, ref, gm1);
+  const T d = T(0.1) * (fabs(F.un) + F.c);
+  const T lam[4] = {F.un - F.c, F.un, F.un + F.c, F.un};
+  T al[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    al[k] = fabs(lam[k]);
+    if ((k == 0 || k == 2) && al[k] < d) al[k] = fdiv(lam[k] * lam[k] + d * d, T(2) * d);
+  }
+  const T dw[4] = {wr[0] - wl[0], wr[1] - wl[1], wr[2] - wl[2], wr[3] - wl[3]};
+  T a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    a[k] = al[k] * (F.L[k][0] * dw[0] + F.L[k][1] * dw[1] + F.L[k][2] * dw[2] + F.L[k][3] * dw[3]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
+           T(0.5) * (F.R[q][0] * a[0] + F.R[q][1] * a[1] + F.R[q][2] * a[2] + F.R[q][3] * a[3]);
+}
+
+// Toro's HLLC flux with the Davis-Einfeldt wave speeds (Roe state).  In the
+// perturbation form the star-state jumps U*_K - U_K are written so that no
+// large terms cancel: with g = (S_M - u_nK)/(S_K - S_M) and f = 1 + g,
+//   rho* - rho = g rho,  m* - m = g m + f rho (S_M - u_nK) n,
+//   E* - E = g E + f rho (S_M - u_nK)(S_M + p/(rho (S_K - u_nK))),
+// and pressure differences are taken from the perturbations.
+template <class T>
+__device__ inline void hllc_flux(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                                 T gam, T gm1, T h[4]) {
+  T fl[4], gl[4], fr[4], gr[4], pl, rl, ul, vl, pr, rr, ur, vr, ppl, ppr;
+  pert_flux<T>(wl, ref, gm1, fl, gl, &pl, &rl, &ul, &vl, &ppl);
+  pert_flux<T>(wr, ref, gm1, fr, gr, &pr, &rr, &ur, &vr, &ppr);
+  const Frame<T> F = roe_frame<T>(V4<T>{wl[0], wl[1], wl[2], wl[3]},
+                                  V4<T>{wr[0], wr[1], wr[2], wr[3]}, nx, ny, ref, gm1);
+  const T unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
+  const T cl = fsqrt(fdiv(gam * pl, rl)), cr = fsqrt(fdiv(gam * pr, rr));
+  const T sl = fmin(unl - cl, F.un - F.c), sr = fmax(unr + cr, F.un + F.c);
+  const T sm = fdiv((ppr - ppl) + rl * unl * (sl - unl) - rr * unr * (sr - unr),
+                    rl * (sl - unl) - rr * (sr - unr));
+  T Fn[4];
+  const T* w;
+  T rho, u, v, p, un, sk;
+  // regions in the order: left of S_L, S_L..S_M, S_M..S_R, right of S_R
+  if (sl >= T(0)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = fl[q] * nx + gl[q] * ny;
+    return;
+  }
+  if (sm < T(0) && sr < T(0)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = fr[q] * nx + gr[q] * ny;
+    return;
+  }
+  if (sm >= T(0)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Fn[q] = fl[q] * nx + gl[q] * ny;
+    w = wl, rho = rl, u = ul, v = vl, p = pl, un = unl, sk = sl;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Fn[q] = fr[q] * nx + gr[q] * ny;
+    w = wr, rho = rr, u = ur, v = vr, p = pr, un = unr, sk = sr;
+  }
+  const T dm = sm - un;
+  const T g = fdiv(dm, sk - sm), f = T(1) + g;
+  const T E = ref.w[3] + w[3];
+  const T dU[4] = {g * rho, g * rho * u + f * rho * dm * nx, g * rho * v + f * rho * dm * ny,
+                   g * E + f * rho * dm * (sm + fdiv(p, rho * (sk - un)))};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) h[q] = Fn[q] + sk * dU[q];
+}
+
+// The configured Riemann flux (hfd_flux; uniform across the launch).
+template <class T>
+__device__ inline void riemann(int kind, const T wl[4], const T wr[4], T nx, T ny,
+                               const Ref<T>& ref, T gam, T gm1, T h[4]) {
+  if (kind == HFD_FLUX_ROE) roe_flux<T>(wl, wr, nx, ny, ref, gm1, h);
+  else if (kind == HFD_FLUX_HLLC) hllc_flux<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+  else rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
+}
+
+}  // namespace hfd

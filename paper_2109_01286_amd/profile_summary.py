@@ -12,12 +12,16 @@ import json
 import os
 import sys
 
-KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+KERNEL_SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
+                  for f in ("kernels.hip", "gas.h")]
 
 
 def source_digest():
-    """sha256 of the hot-path kernel source the counters belong to."""
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    """sha256 of the hot-path kernel sources the counters belong to."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def _short(name):
@@ -61,7 +65,7 @@ def main(stats_dir, fetch_dir, write_dir, out, command):
             traffic[k[0]] = {"fetch_bytes": f, "write_bytes": w, "bytes": f + w}
     open(out, "w").write("\n".join(lines) + "\n")
     js = os.path.splitext(out)[0] + "_traffic.json"
-    json.dump({"workload": "shockvortex2049", "kernels_hip_sha256": source_digest(),
+    json.dump({"workload": "shockvortex2049", "kernel_sources_sha256": source_digest(),
                "fetch_factor": ff, "write_factor": fw, "per_launch": traffic},
               open(js, "w"), indent=1)
 

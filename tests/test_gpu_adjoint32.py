@@ -26,19 +26,28 @@ def rel(a, b):
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
-def solver(key):
+def solver(key, flux="rusanov"):
     name, scale, kw, sw = CASES[key]
     m, U, _ = inputs.workload(name, scale)
-    S = lib_solver(m, 0, switch=sw, **kw)
+    S = lib_solver(m, 0, switch=sw, flux=flux, **kw)
     wref = U[0:4, m.ghost_src == -1].mean(axis=1)
     return m, U, S, wref
 
 
-@pytest.mark.parametrize("key", list(CASES))
-def test_fp32_adjoint_residual_close_to_fp64(key):
+# HLLC is checked on the diagonal vortex flow only.  Its flux is not
+# differentiable where the contact speed S_M is 0 (continuous there, its
+# derivative jumps between the two star regions).  In the shock-vortex state
+# S_M is exactly 0 on every edge normal to the uniform flow outside the
+# vortex; float32 rounding of the interface states puts those edges on either
+# side, so the two precisions differentiate different one-sided branches
+# there.
+@pytest.mark.parametrize("key,flux", [(k, "rusanov") for k in CASES] +
+                         [("shockvortex", "roe"), ("vortex21-paper", "roe"),
+                          ("vortex21-paper", "hllc")])
+def test_fp32_adjoint_residual_close_to_fp64(key, flux):
     """J^T lam at the same state in both precisions, the switch pinned to
     the float64 decisions so that both differentiate the same branches."""
-    m, U, S, wref = solver(key)
+    m, U, S, wref = solver(key, flux)
     Ud = torch.as_tensor(S.to_internal(U), device=DEV)
     rng = np.random.default_rng(11)
     lam = torch.as_tensor(S.to_internal(rng.standard_normal(U.shape)), device=DEV)
@@ -51,7 +60,7 @@ def test_fp32_adjoint_residual_close_to_fp64(key):
     owned = torch.as_tensor(S.to_internal((m.ghost_src == -1).astype(np.float64)[None])[0],
                             device=DEV) > 0
     err = max(rel(got[4 * k:4 * k + 4][:, owned], ref[4 * k:4 * k + 4][:, owned]) for k in range(3))
-    print(f"[adjoint32] {key}: adjoint residual rel err per block (max) {err:.2e}")
+    print(f"[adjoint32] {key}/{flux}: adjoint residual rel err per block (max) {err:.2e}")
     assert torch.all(got[:, ~owned] == 0.0)
     assert err < 1e-4
 
