@@ -144,19 +144,30 @@ def cpu_baseline(m, U0, prm, kw, budget_s):
     sc = osch.Scheme(m.xy, m.tri, m.ghost_src, m.period, opts, verts=sample)
     setup = time.perf_counter() - t0
     Ut = torch.as_tensor(U0)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        sc.residual(Ut, kw["switch"])
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s:
-            break
-    rate = sample.size * n / el
-    return dict(value=rate, unit="vertex-stage/s", cores=torch.get_num_threads(),
+
+    def timed(budget):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            sc.residual(Ut, kw["switch"])
+            n += 1
+            el = time.perf_counter() - t0
+            if el > budget:
+                return n, el
+
+    n, el = timed(budget_s)
+    cores = torch.get_num_threads()
+    # the same on one thread, on a third of the budget
+    torch.set_num_threads(1)
+    try:
+        n1, el1 = timed(budget_s / 3)
+    finally:
+        torch.set_num_threads(cores)
+    return dict(value=sample.size * n / el, unit="vertex-stage/s", cores=cores,
                 kind="oracle",
                 sample=f"{sample.size} owned vertices (a compact patch), {n} residual "
-                       f"evaluations in {el:.1f} s; oracle setup {setup:.1f} s not timed")
+                       f"evaluations in {el:.1f} s; oracle setup {setup:.1f} s not timed",
+                value_1_thread=sample.size * n1 / el1)
 
 
 def accuracy_runs():
