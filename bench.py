@@ -53,10 +53,8 @@ def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
     import torch
     S.set_precision(prec, wref)
     U = U0d.clone()
-    dt = torch.empty(1, dtype=torch.float64, device=U.device)
-    for _ in range(warmup):
-        S.stable_dt(U, cfl, out=dt)
-        S.rk_step(U, dt)
+    dts = torch.empty(max(chunk, warmup, 1), dtype=torch.float64, device=U.device)
+    S.rk_steps(U, warmup, cfl, dts)
     torch.cuda.synchronize()
     S.check()
     S.kernel_times()
@@ -68,9 +66,8 @@ def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
         torch.cuda.synchronize()
         S.set_timing(True)
         t0 = time.perf_counter()
-        for _ in range(n):
-            S.stable_dt(U, cfl, out=dt)
-            S.rk_step(U, dt)
+        # n x (device-side time step, Runge-Kutta step) in one library call
+        S.rk_steps(U, n, cfl, dts)
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
         S.set_timing(False)

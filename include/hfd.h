@@ -230,6 +230,14 @@ hfd_status hfd_rk_step(hfd_ctx* ctx, double* U, double dt, void* stream);
 hfd_status hfd_rk_step_dev(hfd_ctx* ctx, double* U, const double* dt_dev,
                            void* stream);
 
+/* nsteps times: hfd_stable_dt(U, cfl) into dt_dev[i], then hfd_rk_step with
+ * that step size; dt_dev: device array [nsteps].  The same results bit for
+ * bit; between steps the state stays in the passes' gather layout instead of
+ * being converted from U again.  U may not be modified by the caller while
+ * the call's work runs. */
+hfd_status hfd_rk_steps(hfd_ctx* ctx, double* U, int64_t nsteps, double cfl, double* dt_dev,
+                        void* stream);
+
 /* *dt_dev = cfl * min over owned v of h_min(v) / (|u_v| + c_v), with h_min
  * the shortest edge at v (device output, no sync). */
 hfd_status hfd_stable_dt(hfd_ctx* ctx, const double* U, double cfl,

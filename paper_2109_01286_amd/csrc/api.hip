@@ -345,11 +345,16 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// One Runge-Kutta step.  `gathered`: B.Gv[0], B.Gg[0] already hold U in
+// gather layout (the previous step of hfd_rk_steps wrote it); `carry`: the
+// last stage also writes the new state's gather copy there.  The gather rows
+// of copying ghosts are never read (every gather is resolved to its source),
+// so the carried copy needs no ghost refresh.
 template <class T>
 hfd_status rk_step_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
                      const hfd::VertexCoef<T>& vc, bool mx, double* U, double dt,
                      const double* dt_dev, hipStream_t st, double* S1 = nullptr,
-                     double* S2 = nullptr) {
+                     double* S2 = nullptr, bool gathered = false, bool carry = false) {
   // S1, S2: where the two intermediate stages go (work buffers by default)
   if (!S1) S1 = c->U1;
   if (!S2) S2 = c->U2;
@@ -358,10 +363,12 @@ hfd_status rk_step_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec
   const GasParams gp = gas_params(c, mx);
   const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
   const int64_t nd = int64_t(h.dir_rows.size());
-  HIPCHK(c, hfd::launch_to_gather<T>(nv, U, gp, B.Gv[0], B.Gg[0], st));
-  for (int k = 1; k < 3; ++k)
-    HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
-                                              B.Gg[k], st));
+  if (!gathered) {
+    HIPCHK(c, hfd::launch_to_gather<T>(nv, U, gp, B.Gv[0], B.Gg[0], st));
+    for (int k = 1; k < 3; ++k)
+      HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
+                                                B.Gg[k], st));
+  }
   const double* in[3] = {U, S1, S2};
   double* outp[3] = {S1, S2, U};
   for (int k = 0; k < 3; ++k) {
@@ -373,8 +380,9 @@ hfd_status rk_step_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec
     hfd::RkArgs rk{U, in[k], outp[k], a[k], b[k], dt, dt_dev};
     PassTimer t(c, 1, st);
     HIPCHK(c, hfd::launch_vertex<T>(no, nv, vc, gp, B.Gv[k], B.Gg[k], B.H, 1, nullptr, rk,
-                                    k < 2 ? B.Gv[k + 1] : nullptr,
-                                    k < 2 ? B.Gg[k + 1] : nullptr, c->flag, st));
+                                    k < 2 ? B.Gv[k + 1] : (carry ? B.Gv[0] : nullptr),
+                                    k < 2 ? B.Gg[k + 1] : (carry ? B.Gg[0] : nullptr),
+                                    c->flag, st));
   }
   const int64_t ncp = int64_t(h.copy_rows.size());
   HIPCHK(c, hfd::launch_copy_rows<double>(ncp, c->copy_rows, c->copy_src, nv, U, U, st));
@@ -385,6 +393,24 @@ hfd_status rk_step_impl(hfd_ctx* c, double* U, double dt, const double* dt_dev,
                         hipStream_t st) {
   if (mixed(c)) return rk_step_t<float>(c, c->b32, ecoef32(c), vcoef32(c), true, U, dt, dt_dev, st);
   return rk_step_t<double>(c, c->b64, ecoef64(c), vcoef64(c), false, U, dt, dt_dev, st);
+}
+
+// nsteps x (time step on the device, then a Runge-Kutta step); dt of step i
+// into dt_dev[i].
+template <class T>
+hfd_status rk_steps_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
+                      const hfd::VertexCoef<T>& vc, bool mx, double* U, int64_t nsteps,
+                      double cfl, double* dt_dev, hipStream_t st) {
+  const hfd::HostSetup& h = c->hs;
+  hfd_status s;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    HIPCHK(c, hfd::launch_stable_dt(h.n_owned, h.nv, U, c->hmin, c->o.gamma, cfl, c->dtpart,
+                                    c->ndtpart, dt_dev + i, st));
+    if ((s = rk_step_t<T>(c, B, ec, vc, mx, U, 0.0, dt_dev + i, st, nullptr, nullptr, i > 0,
+                          i + 1 < nsteps)))
+      return s;
+  }
+  return HFD_OK;
 }
 
 template <class T>
@@ -979,6 +1005,17 @@ hfd_status hfd_rk_step_dev(hfd_ctx* c, double* U, const double* dt_dev, void* st
   if (s) return s;
   if (!U || !dt_dev) return fail(c, HFD_E_INVAL, "null state or dt");
   return rk_step_impl(c, U, 0.0, dt_dev, static_cast<hipStream_t>(stream));
+}
+
+hfd_status hfd_rk_steps(hfd_ctx* c, double* U, int64_t nsteps, double cfl, double* dt_dev,
+                        void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !dt_dev || nsteps < 0 || !(cfl > 0.0))
+    return fail(c, HFD_E_INVAL, "null pointer, nsteps < 0 or cfl <= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (mixed(c)) return rk_steps_t<float>(c, c->b32, ecoef32(c), vcoef32(c), true, U, nsteps, cfl, dt_dev, st);
+  return rk_steps_t<double>(c, c->b64, ecoef64(c), vcoef64(c), false, U, nsteps, cfl, dt_dev, st);
 }
 
 hfd_status hfd_stable_dt(hfd_ctx* c, const double* U, double cfl, double* dt_dev,

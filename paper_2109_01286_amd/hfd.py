@@ -87,6 +87,7 @@ SIGNATURES = {
     "hfd_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "hfd_rk_step": (ctypes.c_int, [_P, _P, _D, _P]),
     "hfd_rk_step_dev": (ctypes.c_int, [_P, _P, _P, _P]),
+    "hfd_rk_steps": (ctypes.c_int, [_P, _P, _I64, _D, _P, _P]),
     "hfd_stable_dt": (ctypes.c_int, [_P, _P, _D, _P, _P]),
     "hfd_edge_states": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "hfd_force_switch_mask": (ctypes.c_int, [_P, _P]),
@@ -302,6 +303,16 @@ class Solver:
         else:
             self._chk(lib().hfd_rk_step(self._h, _dptr(U), float(dt), _stream()))
         return U
+
+    def rk_steps(self, U, nsteps, cfl, dts=None):
+        """nsteps x (stable_dt then rk_step) in place; returns the device
+        tensor [nsteps] of step sizes (no host sync)."""
+        import torch
+        if dts is None:
+            dts = torch.empty(max(int(nsteps), 1), dtype=torch.float64, device=U.device)
+        self._chk(lib().hfd_rk_steps(self._h, _dptr(U), int(nsteps), float(cfl), _dptr(dts),
+                                     _stream()))
+        return dts
 
     def stable_dt(self, U, cfl, out=None):
         """Device tensor [1] with cfl * min h/(|u|+c) (no host sync)."""
