@@ -240,8 +240,10 @@ void byte_model(hfd_ctx* c) {
   // vertex pass: CSR offsets and ids, coefficient records, state (values,
   // plus gradients with viscosity), edge fluxes, float64 RK update
   // averaged over the three stages: U^n read and U^new written every stage,
-  // U^k read in stages 2 and 3, gather-layout copy written in stages 1 and 2
-  double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + (2.0 / 3.0) * 12 * s);
+  // U^k read in stages 2 and 3, the gather-layout copy of the new state
+  // written every stage (by the last one when hfd_rk_steps continues with
+  // another step)
+  double rk = no * (2 * 96.0 + (2.0 / 3.0) * 96.0 + 12 * s);
   I.bytes_vertex_launch = (no + 1) * 8 + double(I.n_vslots) * (4 + 6 * s + visc * 5 * s) +
                           double(I.n_eslots) * (4 + 3 * s) + nv * (4 + 8 * visc) * s +
                           ne * 4 * s + rk;
