@@ -85,6 +85,8 @@ def test_host_only_context_refuses_device_calls():
     L = hfd.lib()
     assert L.hfd_residual(S._h, None, None, None) == 6
     assert L.hfd_rk_step(S._h, None, 0.1, None) == 6
+    assert L.hfd_rk_steps(S._h, None, 3, 0.3, None, None) == 6
+    assert L.hfd_adjoint_residual(S._h, None, None, None, None) == 6
     assert S.info["n_owned"] == 81 and S.info["nv"] == 19 * 19
 
 
