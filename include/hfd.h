@@ -62,7 +62,7 @@ typedef enum {
   HFD_SWITCH_WENO_ONLY = 2
 } hfd_switch;
 
-typedef enum { HFD_ORDER_NONE = 0, HFD_ORDER_HILBERT = 1 } hfd_order;
+typedef enum { HFD_ORDER_NONE = 0, HFD_ORDER_HILBERT = 1, HFD_ORDER_RCM = 2 } hfd_order;
 
 /* Riemann flux along the edge (the paper leaves the solver open):
  * RUSANOV = local Lax-Friedrichs; ROE = Roe's flux at the Roe average of the

@@ -711,7 +711,8 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   const hfd_opts& op = c->o;
   if (!(op.gamma > 1.0) || op.mu < 0.0 || !(op.weno_eps > 0.0) || op.w3_cap < 0.0 ||
       op.switch_mode < 0 || op.switch_mode > 2 || op.precision < 0 || op.precision > 1 ||
-      op.flux < HFD_FLUX_RUSANOV || op.flux > HFD_FLUX_HLLC ||
+      op.flux < HFD_FLUX_RUSANOV || op.flux > HFD_FLUX_HLLC || op.order < HFD_ORDER_NONE ||
+      op.order > HFD_ORDER_RCM ||
       op.period[0] < 0.0 || op.period[1] < 0.0 ||
       (op.mu > 0.0 && (!(op.prandtl > 0.0) || !(op.gas_R > 0.0)))) {
     c->err = "invalid options";

@@ -190,6 +190,84 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
       if (ca != cb) return ca < cb;
       return hk[a] < hk[b];
     });
+  } else if (o.order == HFD_ORDER_RCM) {
+    // Reverse Cuthill-McKee over the owned vertices (edges between owned
+    // vertices): from a pseudo-peripheral start (repeated breadth-first
+    // sweeps to a minimum-degree vertex of the last level), visit the
+    // unvisited neighbours by increasing degree (then id), one component
+    // after another, and reverse.  Ghost classes keep the input order.
+    std::vector<int32_t> deg(nv, 0);
+    for (int64_t v = 0; v < nv; ++v)
+      if (gs[v] == -1)
+        for (int64_t k = aptr[v]; k < aptr[v + 1]; ++k) deg[v] += gs[anbr[k]] == -1;
+    std::vector<int32_t> lev(nv, -1), cm;
+    cm.reserve(nv);
+    auto bfs_levels = [&](int32_t s, std::vector<int32_t>& seen) {  // last level
+      std::vector<int32_t> cur{s}, nxt;
+      seen.push_back(s);
+      lev[s] = 0;
+      for (int l = 1;; ++l) {
+        nxt.clear();
+        for (int32_t u : cur)
+          for (int64_t k = aptr[u]; k < aptr[u + 1]; ++k) {
+            const int32_t w = anbr[k];
+            if (gs[w] == -1 && lev[w] < 0) {
+              lev[w] = l;
+              seen.push_back(w);
+              nxt.push_back(w);
+            }
+          }
+        if (nxt.empty()) return std::make_pair(l - 1, cur);
+        std::swap(cur, nxt);
+      }
+    };
+    std::vector<char> done(nv, 0);
+    std::vector<int32_t> seen;
+    for (int64_t s0 = 0; s0 < nv; ++s0) {
+      if (gs[s0] != -1 || done[s0]) continue;
+      // pseudo-peripheral vertex of this component
+      int32_t start = int32_t(s0);
+      int depth = -1;
+      for (int it = 0; it < 8; ++it) {
+        seen.clear();
+        auto [d, last] = bfs_levels(start, seen);
+        for (int32_t w : seen) lev[w] = -1;
+        int32_t best = last[0];
+        for (int32_t w : last)
+          if (deg[w] < deg[best] || (deg[w] == deg[best] && w < best)) best = w;
+        if (d <= depth) break;
+        depth = d;
+        start = best;
+      }
+      // Cuthill-McKee from start
+      const size_t c0 = cm.size();
+      cm.push_back(start);
+      done[start] = 1;
+      std::vector<int32_t> nb;
+      for (size_t h = c0; h < cm.size(); ++h) {
+        const int32_t u = cm[h];
+        nb.clear();
+        for (int64_t k = aptr[u]; k < aptr[u + 1]; ++k) {
+          const int32_t w = anbr[k];
+          if (gs[w] == -1 && !done[w]) {
+            done[w] = 1;
+            nb.push_back(w);
+          }
+        }
+        std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+          return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
+        });
+        cm.insert(cm.end(), nb.begin(), nb.end());
+      }
+    }
+    std::reverse(cm.begin(), cm.end());
+    std::vector<int64_t> rank(nv, 0);
+    for (size_t k = 0; k < cm.size(); ++k) rank[cm[k]] = int64_t(k);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      int ca = cls(a), cb = cls(b);
+      if (ca != cb) return ca < cb;
+      return ca == 0 ? rank[a] < rank[b] : false;
+    });
   } else {
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return cls(a) < cls(b); });

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhfd.so")
 HFD_FP64, HFD_FP32_MIXED = 0, 1
 SWITCH = {"paper": 0, "smooth": 1, "weno": 2}
 FLUX = {"rusanov": 0, "roe": 1, "hllc": 2}
-ORDER = {"none": 0, "hilbert": 1}
+ORDER = {"none": 0, "hilbert": 1, "rcm": 2}
 STATUS = {0: "HFD_OK", 1: "HFD_E_INVAL", 2: "HFD_E_MESH", 3: "HFD_E_NOMEM",
           4: "HFD_E_DEVICE", 5: "HFD_E_NUMERIC", 6: "HFD_E_STATE"}
 

@@ -241,3 +241,18 @@ def test_numeric_flag_reports_nan_and_negative_density():
         P.S.check()
     assert e.value.status == 5
     P.S.check()      # the flag was cleared
+
+
+@pytest.mark.parametrize("order", ["none", "rcm"])
+def test_renumbering_changes_only_the_summation_order(order):
+    """The residual in another vertex numbering (input order, reverse
+    Cuthill-McKee) equals the Hilbert-ordered one up to float64 rounding of
+    the reordered sums, in the caller's vertex order."""
+    P = pair("shockvortex")
+    name, scale, kw, sw = CASES["shockvortex"]
+    S2 = lib_solver(P.m, 0, switch=sw, order=order, **kw)
+    a = P.S.to_input(P.S.residual(P.dev(P.U)).cpu().numpy())
+    b = S2.to_input(S2.residual(torch.as_tensor(S2.to_internal(P.U), device=DEV)).cpu().numpy())
+    err = block_rel_err(b, a, P.owned)
+    print(f"[parity] shockvortex, {order} vs hilbert numbering: rel err {err:.2e}")
+    assert err <= 1e-12

@@ -10,7 +10,8 @@ from paper_2109_01286_amd import inputs
 from ._helpers import edge_map, lib_solver
 
 CASES = [("vortex21", None, {}), ("riemann201", 31, {}), ("shockvortex2049", 25, {}),
-         ("tgv513", 33, {}), ("vortex257", 33, {"order": "none"})]
+         ("tgv513", 33, {}), ("vortex257", 33, {"order": "none"}),
+         ("riemann201", 31, {"order": "rcm"}), ("vortex21", None, {"order": "rcm"})]
 
 
 @pytest.mark.parametrize("name,scale,opts", CASES)
@@ -50,6 +51,33 @@ def test_renumbering_of_a_shuffled_mesh_gives_the_same_stencils():
     # owned vertices first, then Dirichlet, then copying ghosts
     g = ms.ghost_src[S.old_of_new]
     assert (g[:S.n_owned] == -1).all() and (g[S.n_owned:] != -1).all()
+
+
+def test_reverse_cuthill_mckee_bounds_the_bandwidth():
+    """Reverse Cuthill-McKee numbering of a shuffled 41 x 41 lattice: every
+    edge between owned vertices joins indices at most about two lattice
+    rows apart (the breadth-first levels are anti-diagonals), against the
+    whole index range for the shuffled input order; owned vertices first."""
+    m, _, _ = inputs.workload("riemann201", 41)
+    ms = inputs.shuffled(m, seed=9)
+    band = {}
+    for o in ("none", "rcm"):
+        S = lib_solver(ms, -1, order=o)
+        ends, _ = S.export_edges()
+        a, b = S.new_of_old[ends[:, 0]], S.new_of_old[ends[:, 1]]
+        own = (a < S.n_owned) & (b < S.n_owned)
+        band[o] = int(np.abs(a - b)[own].max())
+        g = ms.ghost_src[S.old_of_new]
+        assert (g[:S.n_owned] == -1).all() and (g[S.n_owned:] != -1).all()
+        assert sorted(S.old_of_new.tolist()) == list(range(S.nv))
+    assert band["rcm"] <= 2 * 41
+    assert band["none"] > 10 * band["rcm"]
+
+
+def test_unknown_order_is_rejected():
+    m, _, _ = inputs.workload("vortex21", 9)
+    with pytest.raises(Exception):
+        lib_solver(m, -1, order=5)
 
 
 def test_sizes_match_the_lattice_recipe():
