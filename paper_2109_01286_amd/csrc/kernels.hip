@@ -33,9 +33,6 @@
 #ifndef HFD_VERTEX_LANES64
 #define HFD_VERTEX_LANES64 16 // lanes per vertex in the float64 vertex pass
 #endif
-#ifndef HFD_NT_COEF
-#define HFD_NT_COEF 0         // 1: non-temporal loads for single-use coefficient streams
-#endif
 #ifndef HFD_VERTEX_WAVES
 #define HFD_VERTEX_WAVES 7    // waves per SIMD of the float32 vertex kernel (Euler)
 #endif
@@ -48,17 +45,6 @@
 
 namespace hfd {
 namespace {
-
-// Load of a value that is used once per launch (coefficients, indices):
-// optionally marked non-temporal so it does not displace gathered data.
-template <class T>
-__device__ inline T ldc(const T* p) {
-#if HFD_NT_COEF
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
-}
 
 // base[uoff] plus a per-lane byte offset, with the wave-uniform element
 // offset pinned in scalar registers: the load then takes a scalar base and
@@ -486,7 +472,8 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
     un[i] = uk[i] = 0.0;
     if (mode == 1 && p < 12 * VPB && vv < nowned) {
       const int64_t o = int64_t(p / VPB) * nv + vv;
-      un[i] = rk.Un[o];
+      // (U^n has no weight in the first stage)
+      if (rk.a != 0.0) un[i] = rk.Un[o];
       uk[i] = rk.Uk[o];
     }
   }
