@@ -23,6 +23,8 @@ FULL = {
     "tgv513": dict(switch="smooth", mu=0.01),
     "vortex257": dict(switch="paper"),
     "shockvortex2049": dict(switch="paper", w3_cap=2.0),
+    "couette": dict(switch="smooth", mu=0.1, prandtl=100.0, gas_R=20.0 / 7.0),
+    "sod_circle": dict(switch="paper", w3_cap=2.0),
 }
 
 
@@ -40,7 +42,8 @@ def test_full_size_residual_at_sampled_vertices(name):
     print(f"[full] {name}: {m.nv} vertices", flush=True)
     S = lib_solver(m, 0, **kw)
     sample = sample_owned(m, 64, seed=11)
-    opts = osch.Options(mu=kw.get("mu", 0.0), w3_cap=kw.get("w3_cap", 0.0))
+    opts = osch.Options(mu=kw.get("mu", 0.0), w3_cap=kw.get("w3_cap", 0.0),
+                        prandtl=kw.get("prandtl", 0.72), gas_R=kw.get("gas_R", 1.0))
     sc = osch.Scheme(m.xy, m.tri, m.ghost_src, m.period, opts, verts=sample)
     print(f"[full] {name}: setups {time.time() - t0:.1f} s", flush=True)
     # force the library's switch to the oracle's decisions on the sample's edges
