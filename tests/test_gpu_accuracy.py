@@ -2,8 +2,7 @@
 against float64: the vortex of Section 3.1 advected exactly, and the decaying
 Taylor-Green vortex (small lattice: under the readings the viscous path of
 the recipe's 513 x 513 lattice grows a mode from its second step on).  The
-float32 error may be
-at most twice the float64 one."""
+float32 error may be at most twice the float64 one."""
 import numpy as np
 import pytest
 import torch
