@@ -62,6 +62,11 @@ typedef enum {
   HFD_SWITCH_WENO_ONLY = 2
 } hfd_switch;
 
+/* Internal numbering of the owned vertices: NONE = input order, HILBERT =
+ * along a Hilbert curve of the coordinates (the default), RCM = reverse
+ * Cuthill-McKee of the adjacency among owned vertices.  Dirichlet ghosts,
+ * then copying ghosts follow in input order.  Results differ only by the
+ * order of floating-point sums. */
 typedef enum { HFD_ORDER_NONE = 0, HFD_ORDER_HILBERT = 1, HFD_ORDER_RCM = 2 } hfd_order;
 
 /* Riemann flux along the edge (the paper leaves the solver open):
