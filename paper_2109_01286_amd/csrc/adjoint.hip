@@ -733,6 +733,44 @@ __global__ void k_take_rows(int64_t n, int w, const int32_t* __restrict__ idx,
   dst[i] = src[int64_t(idx[r]) * w + q];
 }
 
+// The three stage states of a Runge-Kutta step (U, U1, U2, float64 [12][nv])
+// in gather layout, in one pass: the same conversion as the forward passes
+// (minus the reference state in the mixed form).  The Dirichlet rows
+// [d0, d1) of the two stages take U's values, as in the forward step.
+template <class T>
+__global__ void k_stage_gathers(int64_t nv, int64_t d0, int64_t d1, const double* __restrict__ U,
+                                const double* __restrict__ U1, const double* __restrict__ U2,
+                                GasParams gp, StageGathers<T> g) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const bool dir = i >= d0 && i < d1;
+  const double* src[3] = {U, dir ? U : U1, dir ? U : U2};
+  for (int k = 0; k < 3; ++k) {
+    T w[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) w[q] = T(src[k][q * nv + i] - (q < 4 ? gp.wref[q] : 0.0));
+    g.v[k][i] = V4<T>{w[0], w[1], w[2], w[3]};
+    g.g[k][2 * i] = V4<T>{w[4], w[5], w[6], w[7]};
+    g.g[k][2 * i + 1] = V4<T>{w[8], w[9], w[10], w[11]};
+  }
+}
+
+template <class T>
+hipError_t launch_stage_gathers(int64_t nv, int64_t d0, int64_t d1, const double* U,
+                                const double* U1, const double* U2, const GasParams& gp,
+                                const StageGathers<T>& g, hipStream_t st) {
+  if (nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stage_gathers<T>, dim3(unsigned((nv + 255) / 256)), dim3(256), 0, st, nv,
+                     d0, d1, U, U1, U2, gp, g);
+  return hipGetLastError();
+}
+template hipError_t launch_stage_gathers<double>(int64_t, int64_t, int64_t, const double*,
+                                                 const double*, const double*, const GasParams&,
+                                                 const StageGathers<double>&, hipStream_t);
+template hipError_t launch_stage_gathers<float>(int64_t, int64_t, int64_t, const double*,
+                                                const double*, const double*, const GasParams&,
+                                                const StageGathers<float>&, hipStream_t);
+
 template <class T>
 hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
   if (a.ne > 0) {

@@ -734,6 +734,12 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   I.max_vslots = h.max_vs;
   I.max_eslots = h.max_es;
   I.setup_ms[0] = ms_since(t0);
+  // the passes take the Dirichlet ghosts as the rows right after the owned ones
+  for (size_t k = 0; k < h.dir_rows.size(); ++k)
+    if (h.dir_rows[k] != h.n_owned + int64_t(k)) {
+      c->err = "internal: Dirichlet ghost rows are not contiguous after the owned rows";
+      return bail(HFD_E_MESH);
+    }
   if (I.n_vslots >= (int64_t(1) << 31) || I.n_eslots >= (int64_t(1) << 31)) {
     c->err = "mesh too large for 32-bit slot offsets";
     return bail(HFD_E_MESH);
@@ -1111,15 +1117,13 @@ hfd_status rk_step_adjoint_t(hfd_ctx* c, const double* U, const double* U1in,
   auto& B = bufs<T>(c);
   const GasParams gp = gas_params(c, f32);
   const double* Us[3] = {U, U1in, U2in};
-  HIPCHK(c, hfd::launch_to_gather<T>(nv, U, gp, B.Gv[0], B.Gg[0], st));
   if (U1in) {
-    // the given stages in gather layout, Dirichlet rows from U
-    for (int k = 1; k < 3; ++k) {
-      HIPCHK(c, hfd::launch_to_gather<T>(nv, Us[k], gp, B.Gv[k], B.Gg[k], st));
-      HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],
-                                                B.Gg[k], st));
-    }
+    // the step's input and the given stages in gather layout, Dirichlet rows
+    // from U (internal rows no .. no + nd)
+    const hfd::StageGathers<T> g{{B.Gv[0], B.Gv[1], B.Gv[2]}, {B.Gg[0], B.Gg[1], B.Gg[2]}};
+    HIPCHK(c, hfd::launch_stage_gathers<T>(nv, no, no + nd, U, U1in, U2in, gp, g, st));
   } else {
+    HIPCHK(c, hfd::launch_to_gather<T>(nv, U, gp, B.Gv[0], B.Gg[0], st));
     // forward stages 1 and 2: U1, U2 and their gather copies
     for (int k = 1; k < 3; ++k)
       HIPCHK(c, hfd::launch_copy_gather_rows<T>(nd, c->dir_rows, B.Gv[0], B.Gg[0], B.Gv[k],

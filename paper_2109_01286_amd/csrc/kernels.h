@@ -196,6 +196,17 @@ struct AdjointArgs {
 };
 template <class T>
 hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st);
+// Gather layouts of a step's input and two stages in one launch; the
+// Dirichlet rows [d0, d1) of the stages come from U.
+template <class T>
+struct StageGathers {
+  V4<T>* v[3];
+  V4<T>* g[3];
+};
+template <class T>
+hipError_t launch_stage_gathers(int64_t nv, int64_t d0, int64_t d1, const double* U,
+                                const double* U1, const double* U2, const GasParams& gp,
+                                const StageGathers<T>& g, hipStream_t st);
 // dst[i][0..w) = src[idx[i]][0..w), i < n (transposed coefficient copies)
 hipError_t launch_take_rows(int64_t n, int w, const int32_t* idx, const double* src,
                             double* dst, hipStream_t st);
