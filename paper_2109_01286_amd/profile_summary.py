@@ -4,6 +4,9 @@ calibrated on k_cast, a streaming kernel of known size: it reads 8 bytes and
 writes 4 bytes per element).
 
     python -m paper_2109_01286_amd.profile_summary STATS_DIR FETCH_DIR WRITE_DIR OUT.md "COMMAND"
+    python -m paper_2109_01286_amd.profile_summary --stats STATS_DIR OUT.md "COMMAND" "TITLE"
+
+The second form writes the kernel statistics alone.
 """
 import collections
 import csv
@@ -70,5 +73,23 @@ def main(stats_dir, fetch_dir, write_dir, out, command):
               open(js, "w"), indent=1)
 
 
+def stats_only(stats_dir, out, command, title):
+    lines = [f"# rocprofv3 summary: {title}", "",
+             "Commands (on the MI355X box, from the repository root, `export TMPDIR=/tmp`):", "",
+             *["    " + c.strip() for c in command.splitlines() if c.strip()], "",
+             "## Kernel statistics (`--kernel-trace --stats`)", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in csv.DictReader(open(os.path.join(stats_dir, "run_kernel_stats.csv"))):
+        if float(r["Percentage"]) < 0.05:
+            continue
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} % |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    main(*sys.argv[1:6])
+    if sys.argv[1] == "--stats":
+        stats_only(*sys.argv[2:6])
+    else:
+        main(*sys.argv[1:6])
