@@ -270,15 +270,16 @@ hfd_status hfd_fill_ghosts(hfd_ctx* ctx, double* U, void* stream);
  * vertex (the flag is then cleared). */
 hfd_status hfd_check(hfd_ctx* ctx, void* stream);
 
-/* Adjoint of the residual (Euler fluxes only; mu > 0 gives HFD_E_STATE):
- * out = (dR/dU)^T lam, all device [12][nv] float64.  Computed in the
+/* Adjoint of the residual (Section 2.3, inviscid and, with mu > 0, viscous
+ * fluxes): out = (dR/dU)^T lam, all device [12][nv] float64.  Computed in the
  * context's precision: float64, or in HFD_FP32_MIXED float32 arithmetic on
  * the float32 perturbation state of the forward pass, each vertex's sums
  * written in float64.  The
  * branch of eq. 2d_hweno_intp and the WENO weights are differentiated
  * through the branch the forward pass takes, the Rusanov maximum through its
  * larger argument; the Roe and HLLC fluxes by forward-mode dual numbers
- * through the branches they take (entropy fix, wave speeds, HLLC region).
+ * through the branches they take (entropy fix, wave speeds, HLLC region);
+ * the viscous fluxes of a vertex by dual numbers in (w, w_x, w_y).
  * Rows of ghost vertices of out are zero (derivatives with
  * respect to copying ghosts land on their sources; Dirichlet data are
  * constants).  Allocates transposed maps and work buffers on first use. */

@@ -18,10 +18,13 @@
 //   k_adj_vertex:     lambda_U(u) = sum over the edges whose stencils contain
 //                     u of those contributions + A_f(w_u)^T lambda_f(u) +
 //                     A_g(w_u)^T lambda_g(u), lambda_f/g(u) gathered from the
-//                     rows of the vertices whose stencils contain u.
+//                     rows of the vertices whose stencils contain u; with
+//                     viscosity + the viscous flux derivative at
+//                     (w_u, w_x(u), w_y(u)) applied to Lambda_fv/gv(u),
+//                     gathered the same way from the viscous rows.
 // The switch and the WENO weights are differentiated through the branch the
 // forward pass takes; the maximum in the Rusanov flux through its larger
-// argument.  Euler only (viscous fluxes are not differentiated).
+// argument.
 #include <hip/hip_runtime.h>
 
 #include "gas.h"
@@ -604,19 +607,24 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
 // (edge, position) entries of u, summing the 12 edge-pass contributions, and
 // (2) the (v, s) entries with u in S(v), summing lambda_f and lambda_g from
 // the transposed rows dv_t (contiguous per u), two entries per lane and
-// batch.  A transposed DPP reduction leaves the 20 sums in LDS; one lane per
-// vertex applies the flux Jacobians, and the 12 output rows are written in
-// 16-wide runs.
-template <class T>
+// batch.  With viscosity the same entries also sum Lambda_fv and Lambda_gv,
+// the adjoints of the viscous fluxes at u, from the transposed viscous rows
+// dvis_t.  A transposed DPP reduction leaves the 20 (28) sums in LDS; one
+// lane per vertex applies the flux Jacobians, one thread per (vertex, input
+// component) the viscous flux derivative (a dual-number evaluation of the
+// viscous flux seeded at that component), and the 12 output rows are
+// written in 16-wide runs.
+template <class T, bool VISC>
 __global__ void __launch_bounds__(256)
 k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict__ U,
              const int32_t* __restrict__ vtp, const int32_t* __restrict__ vtv,
-             const T* __restrict__ dv_t, const int32_t* __restrict__ ntp,
-             const int32_t* __restrict__ nte, const int8_t* __restrict__ ntj,
-             const T* __restrict__ bnode, const V4<T>* __restrict__ Lv,
-             const V4<T>* __restrict__ Lg, double* __restrict__ out, AdjCombine<T> rc) {
-  constexpr int VPB = 16;
-  __shared__ T sres[VPB][21];
+             const T* __restrict__ dv_t, const T* __restrict__ dvis_t,
+             const int32_t* __restrict__ ntp, const int32_t* __restrict__ nte,
+             const int8_t* __restrict__ ntj, const T* __restrict__ bnode,
+             const V4<T>* __restrict__ Lv, const V4<T>* __restrict__ Lg,
+             double* __restrict__ out, AdjCombine<T> rc) {
+  constexpr int VPB = 16, NS = VISC ? 28 : 20;
+  __shared__ T sres[VPB][NS + 1];
   const int t = threadIdx.x, vl = t / 16, sub = t & 15;
   const int64_t u0 = int64_t(blockIdx.x) * VPB, u = u0 + vl;
   T acc[32];
@@ -658,6 +666,10 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
           v[i] = vtv[kk[i]];
           for (int q = 0; q < 6; ++q) d[i][q] = dv_t[6 * int64_t(kk[i]) + q];
         }
+        T kv[2][5];
+        if (VISC)
+          for (int i = 0; i < 2; ++i)
+            for (int q = 0; q < 5; ++q) kv[i][q] = dvis_t[5 * int64_t(kk[i]) + q];
         V4<T> l0[2], lx[2], ly[2];
         for (int i = 0; i < 2; ++i) {
           l0[i] = Lv[v[i]];
@@ -674,6 +686,15 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
             acc[12 + q] -= dd[0] * a0[q] + dd[2] * ax[q] + dd[4] * ay[q];
             acc[16 + q] -= dd[1] * a0[q] + dd[3] * ax[q] + dd[5] * ay[q];
           }
+          if (VISC) {
+            // the forward adds k0 fv + k1 gv, k2 fv + k3 gv, k3 fv + k4 gv
+            T k[5];
+            for (int q = 0; q < 5; ++q) k[q] = ok[i] ? kv[i][q] : T(0.0);
+            for (int q = 0; q < 4; ++q) {
+              acc[20 + q] += k[0] * a0[q] + k[2] * ax[q] + k[3] * ay[q];
+              acc[24 + q] += k[1] * a0[q] + k[3] * ax[q] + k[4] * ay[q];
+            }
+          }
         }
       }
     }
@@ -684,7 +705,7 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
   reduce_stage<0, 4>(acc, sub);
   // lane sub holds sums 2 sub and 2 sub + 1
   for (int i = 0; i < 2; ++i)
-    if (2 * sub + i < 20) sres[vl][2 * sub + i] = acc[i];
+    if (2 * sub + i < NS) sres[vl][2 * sub + i] = acc[i];
   __syncthreads();
   if (t < VPB && u0 + t < nowned) {
     // A_f^T lambda_f + A_g^T lambda_g at w_u (n = (1, 0) and (0, 1))
@@ -706,7 +727,17 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
     const int64_t uu = u0 + vl2;
     if (uu < nowned) {
       const int64_t o = q * nv + uu;
-      const double x = double(sres[vl2][q]);
+      T xs = sres[vl2][q];
+      if (VISC) {
+        // sum_r Lambda_fv[r] dfv_r/dx_q + Lambda_gv[r] dgv_r/dx_q, x = (w, w_x, w_y)
+        using D = Dual<T>;
+        D x3[12];
+        for (int r = 0; r < 12; ++r) x3[r] = D(T(U[r * nv + uu]), r == q ? T(1) : T(0));
+        D fv[4], gv[4];
+        viscous_flux<D>(x3, x3 + 4, x3 + 8, gp, fv, gv);
+        for (int r = 0; r < 4; ++r) xs += sres[vl2][20 + r] * fv[r].d + sres[vl2][24 + r] * gv[r].d;
+      }
+      const double x = double(xs);
       if (out) out[o] = x;
       if (rc.lam_k) {
         const double lk = rc.lam_k[o];
@@ -787,10 +818,17 @@ hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
       hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_RUSANOV>), grid, dim3(256), 0, st, a.ne, a.ec,
                          a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
   }
-  if (a.nowned > 0)
-    hipLaunchKernelGGL(k_adj_vertex<T>, dim3(unsigned((a.nowned + 15) / 16)), dim3(256), 0, st,
-                       a.nowned, a.nv, a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.ntp, a.nte, a.ntj,
-                       a.bnode, a.Lv, a.Lg, a.out, a.rc);
+  if (a.nowned > 0) {
+    const dim3 grid(unsigned((a.nowned + 15) / 16));
+    if (a.dvis_t)
+      hipLaunchKernelGGL((k_adj_vertex<T, true>), grid, dim3(256), 0, st, a.nowned, a.nv, a.gp,
+                         a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode, a.Lv,
+                         a.Lg, a.out, a.rc);
+    else
+      hipLaunchKernelGGL((k_adj_vertex<T, false>), grid, dim3(256), 0, st, a.nowned, a.nv, a.gp,
+                         a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode, a.Lv,
+                         a.Lg, a.out, a.rc);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_adjoint_residual<double>(const AdjointArgs<double>&, hipStream_t);

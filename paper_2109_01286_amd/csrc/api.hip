@@ -69,7 +69,7 @@ struct hfd_ctx {
   const uint8_t* force = nullptr;
   // adjoint: transposed maps and work buffers (built at first use)
   bool adj_ready = false;
-  bool adj_coef_ready = false;  // de_t, dv_t match the current coefficients
+  bool adj_coef_ready = false;  // de_t, dv_t, dvis_t match the current coefficients
   int32_t *etp = nullptr, *etv = nullptr, *ets = nullptr;
   int32_t *vtp = nullptr, *vtv = nullptr, *vts = nullptr;
   int32_t *ntp = nullptr, *nte = nullptr;
@@ -77,10 +77,10 @@ struct hfd_ctx {
   int32_t *gsp = nullptr, *gsr = nullptr, *gsg = nullptr;  // copy source -> ghosts
   int64_t n_gsrc = 0;
   double *bnode = nullptr, *AL1 = nullptr, *AL2 = nullptr, *AL3 = nullptr;
-  double *de_t = nullptr, *dv_t = nullptr;  // coefficient rows in transposed order
+  double *de_t = nullptr, *dv_t = nullptr, *dvis_t = nullptr;  // rows in transposed order
   // float32 adjoint (mixed form, allocated at its first use)
   bool adj_coef32_ready = false;             // fde_t, fdv_t match de_t, dv_t
-  float *fde_t = nullptr, *fdv_t = nullptr, *bnode32 = nullptr;
+  float *fde_t = nullptr, *fdv_t = nullptr, *fdvis_t = nullptr, *bnode32 = nullptr;
   hfd::V4<float>* lh32 = nullptr;
   hfd::V4<float>* LGv32[2] = {nullptr, nullptr};  // lambda in gather layout,
   hfd::V4<float>* LGg32[2] = {nullptr, nullptr};  // two for successive stages
@@ -468,10 +468,12 @@ hfd_status ensure_adjoint_coefs(hfd_ctx* c) {
   if (c->adj_coef_ready) return HFD_OK;
   const int64_t nes = c->info.n_eslots, nvs = c->info.n_vslots;
   hfd_status s;
-  if (!c->de_t && ((s = dalloc(c, &c->de_t, 3 * nes)) || (s = dalloc(c, &c->dv_t, 6 * nvs))))
+  if (!c->de_t && ((s = dalloc(c, &c->de_t, 3 * nes)) || (s = dalloc(c, &c->dv_t, 6 * nvs)) ||
+                    (c->dvis && (s = dalloc(c, &c->dvis_t, 5 * nvs)))))
     return s;
   HIPCHK(c, hfd::launch_take_rows(nes, 3, c->ets, c->de, c->de_t, nullptr));
   HIPCHK(c, hfd::launch_take_rows(nvs, 6, c->vts, c->dv, c->dv_t, nullptr));
+  if (c->dvis) HIPCHK(c, hfd::launch_take_rows(nvs, 5, c->vts, c->dvis, c->dvis_t, nullptr));
   HIPCHK(c, hipStreamSynchronize(nullptr));
   c->adj_coef_ready = true;
   c->adj_coef32_ready = false;
@@ -577,6 +579,7 @@ hfd_status ensure_adjoint32(hfd_ctx* c) {
   const int64_t nes = c->info.n_eslots, nvs = c->info.n_vslots;
   if (!c->fde_t) {
     if ((s = dalloc(c, &c->fde_t, 3 * nes)) || (s = dalloc(c, &c->fdv_t, 6 * nvs)) ||
+        (c->dvis_t && (s = dalloc(c, &c->fdvis_t, 5 * nvs))) ||
         (s = dalloc(c, &c->bnode32, 72 * ne)) || (s = dalloc(c, &c->lh32, ne)) ||
         (s = dalloc(c, &c->LGv32[0], nv)) || (s = dalloc(c, &c->LGg32[0], 2 * nv)) ||
         (s = dalloc(c, &c->LGv32[1], nv)) || (s = dalloc(c, &c->LGg32[1], 2 * nv)))
@@ -586,6 +589,7 @@ hfd_status ensure_adjoint32(hfd_ctx* c) {
   if (!c->adj_coef32_ready) {
     HIPCHK(c, hfd::launch_cast(3 * nes, c->de_t, c->fde_t, nullptr));
     HIPCHK(c, hfd::launch_cast(6 * nvs, c->dv_t, c->fdv_t, nullptr));
+    if (c->dvis_t) HIPCHK(c, hfd::launch_cast(5 * nvs, c->dvis_t, c->fdvis_t, nullptr));
     HIPCHK(c, hipStreamSynchronize(nullptr));
     c->adj_coef32_ready = true;
   }
@@ -633,9 +637,11 @@ hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<T>* Gv,
   a.out = out;
   a.rc = rc;
   if constexpr (f32) {
-    a.de_t = c->fde_t; a.dv_t = c->fdv_t; a.lh = c->lh32; a.bnode = c->bnode32;
+    a.de_t = c->fde_t; a.dv_t = c->fdv_t; a.dvis_t = c->fdvis_t;
+    a.lh = c->lh32; a.bnode = c->bnode32;
   } else {
-    a.de_t = c->de_t; a.dv_t = c->dv_t; a.lh = c->lh; a.bnode = c->bnode;
+    a.de_t = c->de_t; a.dv_t = c->dv_t; a.dvis_t = c->dvis_t;
+    a.lh = c->lh; a.bnode = c->bnode;
   }
   HIPCHK(c, hfd::launch_adjoint_residual<T>(a, st));
   if (out) HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, out, st));
@@ -1085,7 +1091,6 @@ hfd_status hfd_adjoint_residual(hfd_ctx* c, const double* U, const double* lam, 
   hfd_status s = need_device(c);
   if (s) return s;
   if (!U || !lam || !out) return fail(c, HFD_E_INVAL, "null pointer");
-  if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
   if ((s = ensure_adjoint_t(c))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t nv = c->hs.nv;
@@ -1181,7 +1186,6 @@ hfd_status rk_step_adjoint_impl(hfd_ctx* c, const double* U, const double* U1in,
   hfd_status s = need_device(c);
   if (s) return s;
   if (!U || !lam_np1 || !lam_n) return fail(c, HFD_E_INVAL, "null pointer");
-  if (c->o.mu > 0.0) return fail(c, HFD_E_STATE, "the adjoint covers the Euler residual only (mu == 0)");
   if ((s = ensure_adjoint_t(c))) return s;
   if (mixed(c)) return rk_step_adjoint_t<float>(c, U, U1in, U2in, dt, lam_np1, lam_n, st);
   return rk_step_adjoint_t<double>(c, U, U1in, U2in, dt, lam_np1, lam_n, st);

@@ -238,4 +238,41 @@ __device__ inline void riemann(int kind, const T wl[4], const T wr[4], T nx, T n
   else rusanov<T>(wl, wr, nx, ny, ref, gam, gm1, h);
 }
 
+// Viscous fluxes (f_vis, g_vis) at a vertex from the full state w and the
+// gradients of the conservative variables: Newtonian stress with the Stokes
+// hypothesis, constant mu, Fourier heat flux kappa grad T with
+// kappa = mu c_p / Pr and T = p / (rho R) (Section 2.3, "Computing Viscous
+// Flux").
+template <class T>
+__device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
+                                    const GasParams& gp, T fv[4], T gv[4]) {
+  const T gm1 = T(gp.gamma - 1.0);
+  const T rho = w[0], ir = fdiv(T(1), rho);
+  const T u = w[1] * ir, v = w[2] * ir;
+  const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
+  const T iR = T(1.0 / gp.gas_R);
+  auto grads = [&](const T* d, T& du, T& dv, T& dT) {
+    du = (d[1] - u * d[0]) * ir;
+    dv = (d[2] - v * d[0]) * ir;
+    T dp = gm1 * (d[3] - (u * d[1] + v * d[2]) + T(0.5) * (u * u + v * v) * d[0]);
+    dT = (dp - p * ir * d[0]) * ir * iR;
+  };
+  T ux, vx, Tx, uy, vy, Ty;
+  grads(wx, ux, vx, Tx);
+  grads(wy, uy, vy, Ty);
+  const T mu = T(gp.mu);
+  const T kap = T(gp.mu * gp.gamma * gp.gas_R / ((gp.gamma - 1.0) * gp.prandtl));
+  const T dv3 = T(2.0 / 3.0) * mu * (ux + vy);
+  const T txx = T(2) * mu * ux - dv3, tyy = T(2) * mu * vy - dv3;
+  const T txy = mu * (uy + vx);
+  fv[0] = T(0);
+  fv[1] = txx;
+  fv[2] = txy;
+  fv[3] = u * txx + v * txy + kap * Tx;
+  gv[0] = T(0);
+  gv[1] = txy;
+  gv[2] = tyy;
+  gv[3] = u * txy + v * tyy + kap * Ty;
+}
+
 }  // namespace hfd

@@ -189,6 +189,7 @@ struct AdjointArgs {
   const double* U;                  // state [12][nv]
   const int32_t *vtp, *vtv;         // gather row <- (owner vertex, vertex slot)
   const T* dv_t;                    // dv rows in the order of vtv
+  const T* dvis_t;                  // dvis rows in the order of vtv (null: mu == 0)
   const int32_t *ntp, *nte;         // gather row <- (edge, stencil position)
   const int8_t* ntj;
   double* out;                      // [12][nv], owned rows written, or null

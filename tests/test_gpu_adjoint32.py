@@ -19,6 +19,8 @@ CASES = {
     "vortex21": ("vortex21", None, {"w3_cap": 2.0}, "smooth"),
     "vortex21-paper": ("vortex21", None, {"w3_cap": 2.0}, "paper"),
     "shockvortex": ("shockvortex2049", 17, {"w3_cap": 2.0}, "paper"),
+    "tgv": ("tgv513", 17, {"mu": 0.01}, "smooth"),
+    "couette": ("couette", 31, {"mu": 0.1, "prandtl": 100.0, "gas_R": 20.0 / 7.0}, "smooth"),
 }
 
 
