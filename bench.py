@@ -342,12 +342,38 @@ def viscous_line(steps=12, warmup=1):
     wref = U0[0:4, m.ghost_src == -1].mean(axis=1)
     out = {"workload": "tgv513", "owned": int(m.n_owned()), "steps": steps,
            "steps_per_restart": 1}
+    gen = torch.Generator(device="cuda:0").manual_seed(12)
+    lam = torch.randn(U0d.shape, dtype=torch.float64, device="cuda:0", generator=gen)
     for prec in ("fp32", "fp64"):
         r = time_precision(S, U0d, prec, wref, steps, warmup, 0.3, 1)
         _, kern = roofline(r)
         out[prec] = {"value": m.n_owned() * 3 * steps / r["wall"],
                      "unit": "vertex-stage/s", "ms_per_step": r["wall"] / steps * 1e3,
                      "kernels": kern}
+        # adjoint step (two stages recomputed, three adjoint residuals, the
+        # viscous rows included) against the forward step, both from the
+        # initial state
+        dt = S.stable_dt(U0d, 0.3).item()
+        X = U0d.clone()
+        L = torch.empty_like(U0d)
+        S.rk_step(X, dt)
+        S.rk_step_adjoint(U0d, dt, lam, L)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            X.copy_(U0d)
+            S.rk_step(X, dt)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            S.rk_step_adjoint(U0d, dt, lam, L)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        S.check()
+        out[prec]["adjoint_step_ms"] = t_b / steps * 1e3
+        out[prec]["adjoint_step_over_step"] = t_b / t_f
+        out[prec]["adjoint_finite"] = bool(torch.isfinite(L).all().item())
     del S
     return out
 
@@ -496,7 +522,8 @@ def main():
         section("viscous", viscous_line, lambda v: "[bench] viscous (tgv513): " + ", ".join(
             f"{p} {v[p]['value'] / 1e9:.3f} G vertex-stage/s, vertex "
             f"{v[p]['kernels']['vertex']['avg_ms']:.3f} ms "
-            f"({v[p]['kernels']['vertex']['frac'] * 100:.0f} % of HBM)" for p in ("fp32", "fp64")))
+            f"({v[p]['kernels']['vertex']['frac'] * 100:.0f} % of HBM), adjoint step "
+            f"{v[p]['adjoint_step_over_step']:.2f} x step" for p in ("fp32", "fp64")))
     if not a.no_adjoint:
         del S
         torch.cuda.empty_cache()
