@@ -35,17 +35,36 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum and maximum over a group of G lanes (16 or 64), every lane receiving
+// the same bits: within a 16-lane row by DPP (swap neighbours, swap pairs,
+// mirror the half rows, mirror the row; each step combines two partial
+// results that are equal up to the order of a commutative operation), across
+// rows by lane exchange.
 template <int G>
 __device__ inline double gsum(double x) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  static_assert(G == 16 || G == 64, "group of 16 or 64 lanes");
+  x += dpp_mov<0xB1>(x);
+  x += dpp_mov<0x4E>(x);
+  x += dpp_mov<0x141>(x);
+  x += dpp_mov<0x140>(x);
+  if constexpr (G == 64) {
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+  }
   return x;
 }
 
 template <int G>
 __device__ inline double gmax(double x) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  static_assert(G == 16 || G == 64, "group of 16 or 64 lanes");
+  x = fmax(x, dpp_mov<0xB1>(x));
+  x = fmax(x, dpp_mov<0x4E>(x));
+  x = fmax(x, dpp_mov<0x141>(x));
+  x = fmax(x, dpp_mov<0x140>(x));
+  if constexpr (G == 64) {
+    x = fmax(x, __shfl_xor(x, 16));
+    x = fmax(x, __shfl_xor(x, 32));
+  }
   return x;
 }
 
@@ -68,10 +87,26 @@ __device__ inline double mono(int c, int kind, double x, double y) {
 // One-sided Jacobi on the m x n matrix A (LDS, column-major [n][G*RPL], the
 // group's lane l holds rows l, l+G, ...).  On return A <- A V (orthogonal
 // columns U*sigma) and V (LDS [n][G], lane j holds row j) is orthogonal.
+// A pair is rotated unless its columns are orthogonal to 1e-15 (relative) or
+// one of them has a squared norm below 1e-32 of the squared Frobenius norm
+// of A.  The second test ends the iteration on rank-deficient matrices: the
+// columns of zero singular values shrink geometrically as rounding noise
+// whose angles to the other columns stay of order one, so the relative test
+// alone never holds for them; rotating such a column changes the others
+// below rounding.
 template <int G, int RPL>
 __device__ void jacobi(double* A, double* V, int m, int n, int lane) {
   constexpr int LD = G * RPL;
   for (int c = 0; c < n; ++c) V[c * G + lane] = (lane == c) ? 1.0 : 0.0;
+  double fro = 0.0;
+  for (int c = 0; c < n; ++c) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const double x = A[c * LD + lane + r * G];
+      fro += x * x;
+    }
+  }
+  const double tiny = 1e-32 * gsum<G>(fro);
   wave_sync();
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rotated = false;
@@ -89,7 +124,7 @@ __device__ void jacobi(double* A, double* V, int m, int n, int lane) {
         a = gsum<G>(a);
         b = gsum<G>(b);
         g = gsum<G>(g);
-        if (g == 0.0 || fabs(g) <= 1e-15 * sqrt(a * b)) continue;
+        if (g == 0.0 || fmin(a, b) <= tiny || fabs(g) <= 1e-15 * sqrt(a * b)) continue;
         rotated = true;
         double zeta = (b - a) / (2.0 * g);
         double t = copysign(1.0, zeta) / (fabs(zeta) + hypot(1.0, zeta));
@@ -338,7 +373,6 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
   __shared__ double A[NC5 * LD];
   __shared__ double alpha[NC5];
   __shared__ double vtvs[NC5];
-  __shared__ double Rt[NC5 * NC5];
   __shared__ double yv[3 * NC5];
   const int lane = threadIdx.x;
   const int64_t v = blockIdx.x;
@@ -412,11 +446,7 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
     if (lane == 0) status[v] = 1;
     return;
   }
-  // Rt[c][j] = R[j][c]
-  for (int c = lane; c < NC5; c += 64)
-    for (int j = 0; j < NC5; ++j)
-      Rt[c * NC5 + j] = (j < c) ? A[c * LD + j] : (j == c ? alpha[c] : 0.0);
-  wave_sync();
+  // R[k][j] (k < j) is A[j][k], its diagonal alpha
   // three combinations of unknowns: (a_2 + b_3), (a_4 + b_5), (a_5 + b_6)
   // (1-based, a = f coefficients, b = g coefficients): y = R^-T e
   if (lane < 3) {
@@ -425,8 +455,8 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
     double* y = yv + lane * NC5;
     for (int j = 0; j < NC5; ++j) {
       double s = (j == ia ? 1.0 : 0.0) + (j == ib ? 1.0 : 0.0);
-      for (int k = 0; k < j; ++k) s -= Rt[j * NC5 + k] * y[k];
-      y[j] = s / Rt[j * NC5 + j];
+      for (int k = 0; k < j; ++k) s -= A[j * LD + k] * y[k];
+      y[j] = s / alpha[j];
     }
   }
   wave_sync();
