@@ -123,8 +123,8 @@ hfd_status dalloc(hfd_ctx* c, T** p, int64_t n) {
   return HFD_OK;
 }
 
-template <class T>
-hfd_status upload(hfd_ctx* c, T** p, const std::vector<T>& h) {
+template <class T, class A>
+hfd_status upload(hfd_ctx* c, T** p, const std::vector<T, A>& h) {
   hfd_status s = dalloc(c, p, int64_t(h.size()));
   if (s != HFD_OK) return s;
   if (!h.empty()) HIPCHK(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -160,44 +160,55 @@ bool mixed(const hfd_ctx* c) { return c->o.precision == HFD_FP32_MIXED; }
 // (list[bp[b] .. bp[b+1])); per vertex the first list position among its
 // slots (base), per slot its position minus its vertex's base (loc).
 // longest: longest list; span: largest loc + 1.
-void stage_lists(const std::vector<int64_t>& ptr, const std::vector<int32_t>& ids,
-                 int64_t nid, int64_t nowned, std::vector<int32_t>& bp,
-                 std::vector<int32_t>& list, std::vector<uint16_t>& base,
-                 std::vector<uint16_t>& loc, int& longest, int& span) {
+template <class A>
+void stage_lists(const std::vector<int64_t>& ptr, const std::vector<int32_t, A>& ids,
+                 int64_t nowned, std::vector<int32_t>& bp, std::vector<int32_t>& list,
+                 std::vector<uint16_t>& base, std::vector<uint16_t>& loc, int& longest,
+                 int& span) {
   const int64_t vpb = hfd::kStageVertices, nb = (nowned + vpb - 1) / vpb;
-  std::vector<int32_t> seen(size_t(nid), -1), pos(size_t(nid), 0);
-  std::vector<int32_t> blk;
-  bp.assign(size_t(nb + 1), 0);
+  std::vector<std::vector<int32_t>> blists;
+  blists.resize(size_t(nb));
   base.assign(size_t(nowned), 0);
   loc.assign(ids.size(), 0);
-  list.clear();
-  longest = span = 0;
-  for (int64_t b = 0; b < nb; ++b) {
-    const int64_t v0 = b * vpb, v1 = std::min(nowned, v0 + vpb);
-    blk.clear();
-    for (int64_t k = ptr[v0]; k < ptr[v1]; ++k) {
-      const int32_t u = ids[k];
-      if (seen[u] != int32_t(b)) {
-        seen[u] = int32_t(b);
-        blk.push_back(u);
+  int tl[16] = {0}, ts[16] = {0};
+  hfd::parallel_for(nb, [&](int64_t b0, int64_t b1, unsigned t) {
+    std::vector<uint64_t> key;
+    std::vector<int32_t> pos;
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t v0 = b * vpb, v1 = std::min(nowned, v0 + vpb), k0 = ptr[v0];
+      const int64_t n = ptr[v1] - k0;
+      // (id, slot) pairs in id order give each slot its list position
+      key.resize(size_t(n));
+      pos.resize(size_t(n));
+      for (int64_t k = 0; k < n; ++k) key[k] = (uint64_t(uint32_t(ids[k0 + k])) << 32) | uint64_t(k);
+      std::sort(key.begin(), key.end());
+      std::vector<int32_t>& blk = blists[b];
+      blk.clear();
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t u = int32_t(key[i] >> 32);
+        if (blk.empty() || blk.back() != u) blk.push_back(u);
+        pos[key[i] & 0xffffffffu] = int32_t(blk.size()) - 1;
       }
-    }
-    std::sort(blk.begin(), blk.end());
-    for (size_t k = 0; k < blk.size(); ++k) pos[blk[k]] = int32_t(k);
-    for (int64_t v = v0; v < v1; ++v) {
-      int32_t lo = INT32_MAX;
-      for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) lo = std::min(lo, pos[ids[k]]);
-      if (ptr[v + 1] == ptr[v]) lo = 0;
-      base[v] = uint16_t(lo);
-      for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
-        loc[k] = uint16_t(pos[ids[k]] - lo);
-        span = std::max(span, pos[ids[k]] - lo + 1);
+      for (int64_t v = v0; v < v1; ++v) {
+        int32_t lo = INT32_MAX;
+        for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) lo = std::min(lo, pos[k - k0]);
+        if (ptr[v + 1] == ptr[v]) lo = 0;
+        base[v] = uint16_t(lo);
+        for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+          const int32_t d = pos[k - k0] - lo;
+          loc[k] = uint16_t(d);
+          ts[t] = std::max(ts[t], d + 1);
+        }
       }
+      tl[t] = std::max(tl[t], int(blk.size()));
     }
-    list.insert(list.end(), blk.begin(), blk.end());
-    bp[b + 1] = int32_t(list.size());
-    longest = std::max(longest, int(blk.size()));
-  }
+  });
+  longest = *std::max_element(tl, tl + 16);
+  span = *std::max_element(ts, ts + 16);
+  bp.assign(size_t(nb + 1), 0);
+  for (int64_t b = 0; b < nb; ++b) bp[b + 1] = bp[b] + int32_t(blists[b].size());
+  list.resize(size_t(bp[nb]));
+  for (int64_t b = 0; b < nb; ++b) std::copy(blists[b].begin(), blists[b].end(), list.begin() + bp[b]);
 }
 
 // Staging lists of the vertex pass, kept when a block's data fits in LDS
@@ -210,9 +221,8 @@ void build_stage(hfd_ctx* c) {
   if (!HFD_VERTEX_STAGE || c->o.stage_off || h.n_owned == 0) return;
   std::vector<uint16_t> rb, eb;
   int rspan = 0, espan = 0;
-  stage_lists(h.vptr, h.v_gather, h.nv, h.n_owned, g.rp, g.rows, rb, g.vloc, g.max_rows, rspan);
-  stage_lists(h.eptr, h.v_edges, std::max<int64_t>(h.ne, 1), h.n_owned, g.ep, g.edges, eb,
-              g.eloc, g.max_edges, espan);
+  stage_lists(h.vptr, h.v_gather, h.n_owned, g.rp, g.rows, rb, g.vloc, g.max_rows, rspan);
+  stage_lists(h.eptr, h.v_edges, h.n_owned, g.ep, g.edges, eb, g.eloc, g.max_edges, espan);
   const int64_t lds = ((c->o.mu > 0.0 ? 3 : 1) * int64_t(g.max_rows) + g.max_edges) * 32;
   if (lds > 48 * 1024 || g.max_rows > 65536 || g.max_edges > 65536) {
     g = hfd_ctx::Stage{};
@@ -452,7 +462,8 @@ hfd_status edge_states_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>
 
 // Transposed maps of the adjoint, by counting sort (deterministic order:
 // owner vertex, then slot).
-void transpose(int64_t nrows, const std::vector<int32_t>& key, std::vector<int32_t>& ptr,
+template <class A>
+void transpose(int64_t nrows, const std::vector<int32_t, A>& key, std::vector<int32_t>& ptr,
                std::vector<int32_t>& pos) {
   ptr.assign(nrows + 1, 0);
   for (int32_t k : key) ptr[k + 1]++;
@@ -876,10 +887,10 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
                   (void*)d_vh, (void*)d_vptr64, (void*)d_eptr64, (void*)d_status})
     dfree(c, p);
   // host copies of the frames are no longer needed
-  std::vector<double>().swap(h.e_pts);
-  std::vector<double>().swap(h.v_pts);
-  std::vector<double>().swap(h.m_pts);
-  std::vector<double>().swap(h.m_nrm);
+  hfd::HostArray<double>().swap(h.e_pts);
+  hfd::HostArray<double>().swap(h.v_pts);
+  hfd::HostArray<double>().swap(h.m_pts);
+  hfd::HostArray<double>().swap(h.m_nrm);
   I.setup_ms[2] = ms_since(t2);
   if (mixed(c) && (s = ensure_mixed_buffers(c))) return bail(s);
   I.setup_ms[3] = ms_since(t0);

@@ -26,23 +26,33 @@
 namespace hfd {
 namespace {
 
-template <class F>
-void parallel_for(int64_t n, F&& f) {
-  unsigned nt = std::thread::hardware_concurrency();
-  if (nt == 0) nt = 1;
-  if (nt > 16) nt = 16;
-  if (n < 4096 || nt == 1) {
-    f(int64_t(0), n, 0u);
-    return;
+// Stable LSD radix sort of 64-bit keys below 2^bits, 11 bits per pass, with
+// an optional payload permuted alongside (empty: none).  Equal keys keep
+// their order, so the result equals std::stable_sort by key.
+template <class P>
+void radix_sort(std::vector<uint64_t>& k, std::vector<P>& pay, int bits) {
+  const size_t n = k.size();
+  const bool hp = !pay.empty();
+  std::vector<uint64_t> k2(n);
+  std::vector<P> p2(hp ? n : 0);
+  for (int sh = 0; sh < bits; sh += 11) {
+    std::vector<size_t> cnt(2049, 0);
+    for (size_t i = 0; i < n; ++i) cnt[((k[i] >> sh) & 2047) + 1]++;
+    for (int b = 0; b < 2048; ++b) cnt[b + 1] += cnt[b];
+    for (size_t i = 0; i < n; ++i) {
+      const size_t d = cnt[(k[i] >> sh) & 2047]++;
+      k2[d] = k[i];
+      if (hp) p2[d] = pay[i];
+    }
+    k.swap(k2);
+    if (hp) pay.swap(p2);
   }
-  std::vector<std::thread> th;
-  int64_t chunk = (n + nt - 1) / nt;
-  for (unsigned t = 0; t < nt; ++t) {
-    int64_t b = int64_t(t) * chunk, e = std::min(n, b + chunk);
-    if (b >= e) break;
-    th.emplace_back([&f, b, e, t] { f(b, e, t); });
-  }
-  for (auto& x : th) x.join();
+}
+
+int key_bits(uint64_t maxkey) {
+  int b = 1;
+  while (b < 64 && (maxkey >> b) != 0) ++b;
+  return b;
 }
 
 inline double minimg(double d, double P) {
@@ -122,7 +132,10 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
       keys.push_back(lo * uint64_t(nv) + hi);
     }
   }
-  std::sort(keys.begin(), keys.end());
+  {
+    std::vector<int32_t> none;
+    radix_sort(keys, none, key_bits(uint64_t(nv) * uint64_t(nv)));
+  }
   keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
   const int64_t E = int64_t(keys.size());
   S.ne_mesh = E;
@@ -185,11 +198,9 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
       uint32_t iy = uint32_t(std::min(65535.0, std::max(0.0, (xy[2 * v + 1] - y0) * sc)));
       hk[v] = hilbert(ix, iy);
     }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-      int ca = cls(a), cb = cls(b);
-      if (ca != cb) return ca < cb;
-      return hk[a] < hk[b];
-    });
+    // by (class, Hilbert key), ties in input order
+    for (int64_t v = 0; v < nv; ++v) hk[v] |= uint64_t(cls(v)) << 32;
+    radix_sort(hk, order, 34);
   } else if (o.order == HFD_ORDER_RCM) {
     // Reverse Cuthill-McKee over the owned vertices (edges between owned
     // vertices): from a pseudo-peripheral start (repeated breadth-first
@@ -333,18 +344,21 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
   std::vector<uint8_t> active(E, 0);
   for (int64_t k = 0; k < NO; ++k)
     for (int32_t e : ve[k]) active[e] = 1;
-  std::vector<std::pair<uint64_t, int32_t>> ek;
+  std::vector<uint64_t> ekey;
+  std::vector<int32_t> eid;
   for (int64_t e = 0; e < E; ++e)
     if (active[e]) {
       uint64_t p = uint64_t(S.new_of_old[ea[e]]), q = uint64_t(S.new_of_old[eb[e]]);
       if (p > q) std::swap(p, q);
-      ek.emplace_back(p * uint64_t(nv) + q, int32_t(e));
+      ekey.push_back(p * uint64_t(nv) + q);
+      eid.push_back(int32_t(e));
     }
-  std::sort(ek.begin(), ek.end());
-  const int64_t NE = int64_t(ek.size());
+  // keys are distinct (one per edge)
+  if (!eid.empty()) radix_sort(ekey, eid, key_bits(uint64_t(nv) * uint64_t(nv)));
+  const int64_t NE = int64_t(eid.size());
   S.ne = NE;
   std::vector<int32_t> e_int(E, -1);
-  for (int64_t j = 0; j < NE; ++j) e_int[ek[j].second] = int32_t(j);
+  for (int64_t j = 0; j < NE; ++j) e_int[eid[j]] = int32_t(j);
 
   // ---- six-node edge stencils ---------------------------------------------
   S.e_end.resize(2 * NE);
@@ -352,7 +366,7 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
   std::atomic<int64_t> dead(-1);
   parallel_for(NE, [&](int64_t b0, int64_t b1, unsigned) {
     for (int64_t j = b0; j < b1; ++j) {
-      int32_t e = ek[j].second;
+      int32_t e = eid[j];
       int32_t a = ea[e], b = eb[e];
       int32_t used[6] = {a, b, -1, -1, -1, -1};
       int nused = 2;
@@ -393,7 +407,7 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
     }
   });
   if (dead >= 0) {
-    int32_t e = ek[dead].second;
+    int32_t e = eid[dead];
     *err = "edge (" + std::to_string(ea[e]) + ", " + std::to_string(eb[e]) +
            ") has no six-node stencil (dead end)";
     return HFD_E_MESH;

@@ -6,13 +6,63 @@
 // is reproducible bit for bit.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/hfd.h"
 
 namespace hfd {
+
+// Allocator that default-initialises (leaves trivial elements unset): the
+// large per-slot arrays below are written element by element by parallel
+// loops, and a serial zero fill of several GB would dominate the set-up.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using HostArray = std::vector<T, NoInitAlloc<T>>;
+
+// f(begin, end, thread) over [0, n) in contiguous chunks on up to 16 threads
+// (one call on the calling thread when n is small).
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt == 0) nt = 1;
+  if (nt > 16) nt = 16;
+  if (n < 4096 || nt == 1) {
+    f(int64_t(0), n, 0u);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t b = int64_t(t) * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back([&f, b, e, t] { f(b, e, t); });
+  }
+  for (auto& x : th) x.join();
+}
 
 struct HostSetup {
   int64_t nv = 0, n_owned = 0, n_dir = 0, n_copy = 0;
@@ -28,19 +78,19 @@ struct HostSetup {
   // active edges, internal order
   std::vector<int32_t> e_end;         // [ne][2] input ids (i, i+1)
   std::vector<int32_t> e_st;          // [ne][6] input ids (i-2 .. i+3)
-  std::vector<int32_t> e_stg;         // [6][ne] gather rows
-  std::vector<double> e_pts;          // [ne][6][2] edge frame (midpoint origin, / h_e)
+  HostArray<int32_t> e_stg;           // [6][ne] gather rows
+  HostArray<double> e_pts;            // [ne][6][2] edge frame (midpoint origin, / h_e)
   std::vector<double> e_h;            // [ne] middle-edge length
   std::vector<double> e_n;            // [2][ne] unit direction i -> i+1
 
   // owned vertices, internal order 0..n_owned-1
   std::vector<int64_t> vptr, eptr;    // [n_owned+1]
-  std::vector<int32_t> v_nodes;       // [n_vslots] input ids of S(v)
-  std::vector<int32_t> v_gather;      // [n_vslots] gather rows
-  std::vector<int32_t> v_edges;       // [n_eslots] internal active-edge index
-  std::vector<double> v_pts;          // [n_vslots][2] vertex frame (/ h_v)
-  std::vector<double> m_pts;          // [n_eslots][2] edge midpoints, vertex frame
-  std::vector<double> m_nrm;          // [n_eslots][2] edge directions
+  HostArray<int32_t> v_nodes;         // [n_vslots] input ids of S(v)
+  HostArray<int32_t> v_gather;        // [n_vslots] gather rows
+  HostArray<int32_t> v_edges;         // [n_eslots] internal active-edge index
+  HostArray<double> v_pts;            // [n_vslots][2] vertex frame (/ h_v)
+  HostArray<double> m_pts;            // [n_eslots][2] edge midpoints, vertex frame
+  HostArray<double> m_nrm;            // [n_eslots][2] edge directions
   std::vector<double> v_h;            // [n_owned] mean incident edge length
   std::vector<double> v_hmin;         // [n_owned] shortest incident edge
 };
