@@ -39,10 +39,14 @@ __device__ inline void wave_sync() {
 // the same bits: within a 16-lane row by DPP (swap neighbours, swap pairs,
 // mirror the half rows, mirror the row; each step combines two partial
 // results that are equal up to the order of a commutative operation), across
-// rows by lane exchange.
+// rows by lane exchange.  The lanes branch on these sums, so the bits must
+// agree: the empty asm makes x an opaque register value, which keeps the
+// compiler from fusing the caller's product into the first addition (a lane
+// would then add its neighbour's rounded product to its own unrounded one).
 template <int G>
 __device__ inline double gsum(double x) {
   static_assert(G == 16 || G == 64, "group of 16 or 64 lanes");
+  asm volatile("" : "+v"(x));
   x += dpp_mov<0xB1>(x);
   x += dpp_mov<0x4E>(x);
   x += dpp_mov<0x141>(x);
