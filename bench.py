@@ -162,11 +162,19 @@ def cpu_baseline(m, U0, prm, kw, budget_s):
         n1, el1 = timed(budget_s / 3)
     finally:
         torch.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=sample.size * n / el, unit="vertex-stage/s", cores=cores,
                 kind="oracle",
                 sample=f"{sample.size} owned vertices (a compact patch), {n} residual "
                        f"evaluations in {el:.1f} s; oracle setup {setup:.1f} s not timed",
-                value_1_thread=sample.size * n1 / el1)
+                value_1_thread=sample.size * n1 / el1,
+                host={"cpu": model, "logical_cpus": os.cpu_count(),
+                      "affinity": len(os.sched_getaffinity(0))})
 
 
 def accuracy_runs():
