@@ -8,13 +8,13 @@
 //       projection, uniform WENO5 weights, switch of eq. 2d_hweno_intp);
 //   (2) the vertex pass: R_v = - sum_slots D (f(w_u), g(w_u)) - sum_edges D h_m
 //       (eq. flux_polynomials and the rows d0, dx, dy).
-// Its transpose applied to lambda is computed in three deterministic
-// gathers (no atomics), using transposed maps built at first use:
-//   k_adj_edge_flux:  lambda_h(m) = -sum_{(v,s): m in M(v)} de[s] . lambda(v)
-//                     (de and dv are read from copies in the transposed order)
-//   k_adj_edge:       recompute the edge pass and run it backwards, giving
-//                     the contribution of h_e to the 72 data (w, w_x, w_y at
-//                     the six stencil nodes) of edge e
+// Its transpose applied to lambda is computed in two deterministic
+// gathers (no atomics), using transposed maps built at first use (de and dv
+// are read from copies in the transposed order):
+//   k_adj_edge:       lambda_h(e) = -sum_{(v,s): e in M(v)} de[s] . lambda(v),
+//                     then recompute the edge pass and run it backwards,
+//                     giving the contribution of h_e to the 72 data (w, w_x,
+//                     w_y at the six stencil nodes) of edge e
 //   k_adj_vertex:     lambda_U(u) = sum over the edges whose stencils contain
 //                     u of those contributions + A_f(w_u)^T lambda_f(u) +
 //                     A_g(w_u)^T lambda_g(u), lambda_f/g(u) gathered from the
@@ -160,38 +160,41 @@ __device__ inline T launder(T x) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// lambda_h(m) = - sum over (v, s) of de[s] . lambda(v)
+// Edge pass forward + reverse: out[e][j][12] = d h_e / d(data of node j)^T lambda_h(e)
 // ---------------------------------------------------------------------------
-// Sum over the 8 lanes of a group, every lane gets it: the half-row mirror
-// and the two quad swaps pair disjoint lane sets at each stage.
-template <class T>
-__device__ inline T sum8(T x) {
-  x += dpp_mov<0x141>(x);
-  x += dpp_mov<0x4E>(x);
-  x += dpp_mov<0xB1>(x);
-  return x;
-}
-
-// 8 lanes per edge stride over the edge's (v, s) entries, two per lane and
-// batch with all loads in flight; the coefficients are in the transposed
-// order (de_t, contiguous per edge).  Every active edge has an entry, so
-// k1 - 1 is one: lanes past the end load it again with zero weight.
-template <class T>
-__global__ void __launch_bounds__(256)
-k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __restrict__ tv,
-                const T* __restrict__ de_t, const V4<T>* __restrict__ Lv,
-                const V4<T>* __restrict__ Lg, V4<T>* __restrict__ lh) {
-  const int64_t m = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 8;
-  const int sub = threadIdx.x & 7;
-  T a[4] = {0, 0, 0, 0};
-  if (m < ne) {
-    const int k0 = tptr[m], k1 = tptr[m + 1];
-    for (int b = k0 + sub; b < k1; b += 16) {
+// Two lanes per edge: lane s recomputes side s (left: nodes 0..4, right:
+// nodes 5..1, at positions t = 0..4) and runs it backwards; both lanes hold
+// the Roe average and the flux.  The pair exchanges the interface states,
+// the four scalar gradients of the Roe state (u, v, H, c) and the
+// contributions to the nodes both sides share, then lane 0 writes nodes
+// 0, 1, 2 and lane 1 nodes 5, 4, 3 (positions 0, 1, 2 of each lane).
+// (the Roe and HLLC variants carry the dual-number flux: one wave per SIMD,
+// the whole register file)
+template <class T, int FLUX>
+__global__ void __launch_bounds__(256, FLUX == HFD_FLUX_RUSANOV ? ADJ_EDGE_WAVES : 1)
+k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
+           const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
+           const int32_t* __restrict__ tptr, const int32_t* __restrict__ tv,
+           const T* __restrict__ de_t, const V4<T>* __restrict__ Lv,
+           const V4<T>* __restrict__ Lg, T* __restrict__ out) {
+  const int s = threadIdx.x & 1;
+  const int64_t e = int64_t(blockIdx.x) * (blockDim.x / 2) + threadIdx.x / 2;
+  if (e >= ne) return;  // both lanes of a pair leave together
+  // lambda_h(e) = - sum over the (v, s') entries whose rows read h_e of
+  // de[s'] . (lambda, lambda_x, lambda_y)(v): the lanes take alternate
+  // entries (transposed order, contiguous per edge; every active edge has
+  // one, so k1 - 1 is an entry: a lane past the end loads it again with zero
+  // weight), two per batch, loads issued here so that they overlap the
+  // forward recompute, and add their partial sums with one lane swap
+  T gh[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  {
+    const int k0 = tptr[e], k1 = tptr[e + 1];
+    for (int b = k0 + s; b < k1; b += 4) {
       int kk[2];
       bool ok[2];
       for (int i = 0; i < 2; ++i) {
-        ok[i] = b + 8 * i < k1;
-        kk[i] = ok[i] ? b + 8 * i : k1 - 1;
+        ok[i] = b + 2 * i < k1;
+        kk[i] = ok[i] ? b + 2 * i : k1 - 1;
       }
       int v[2];
       T d[2][3];
@@ -207,37 +210,19 @@ k_adj_edge_flux(int64_t ne, const int32_t* __restrict__ tptr, const int32_t* __r
       }
       for (int i = 0; i < 2; ++i) {
         const T d0 = ok[i] ? d[i][0] : T(0.0), dx = ok[i] ? d[i][1] : T(0.0),
-                     dy = ok[i] ? d[i][2] : T(0.0);
-        a[0] -= d0 * l0[i].x + dx * lx[i].x + dy * ly[i].x;
-        a[1] -= d0 * l0[i].y + dx * lx[i].y + dy * ly[i].y;
-        a[2] -= d0 * l0[i].z + dx * lx[i].z + dy * ly[i].z;
-        a[3] -= d0 * l0[i].w + dx * lx[i].w + dy * ly[i].w;
+                dy = ok[i] ? d[i][2] : T(0.0);
+        gh[0] -= d0 * l0[i].x + dx * lx[i].x + dy * ly[i].x;
+        gh[1] -= d0 * l0[i].y + dx * lx[i].y + dy * ly[i].y;
+        gh[2] -= d0 * l0[i].z + dx * lx[i].z + dy * ly[i].z;
+        gh[3] -= d0 * l0[i].w + dx * lx[i].w + dy * ly[i].w;
       }
     }
+    // the pair's sums agree bit for bit (a + b and b + a)
+    for (int q = 0; q < 4; ++q) {
+      gh[q] = launder(gh[q]);
+      gh[q] += dpp_mov<0xB1>(gh[q]);
+    }
   }
-  for (int q = 0; q < 4; ++q) a[q] = sum8(a[q]);
-  if (m < ne && sub == 0) lh[m] = V4<T>{a[0], a[1], a[2], a[3]};
-}
-
-// ---------------------------------------------------------------------------
-// Edge pass forward + reverse: out[e][j][12] = d h_e / d(data of node j)^T lh
-// ---------------------------------------------------------------------------
-// Two lanes per edge: lane s recomputes side s (left: nodes 0..4, right:
-// nodes 5..1, at positions t = 0..4) and runs it backwards; both lanes hold
-// the Roe average and the flux.  The pair exchanges the interface states,
-// the four scalar gradients of the Roe state (u, v, H, c) and the
-// contributions to the nodes both sides share, then lane 0 writes nodes
-// 0, 1, 2 and lane 1 nodes 5, 4, 3 (positions 0, 1, 2 of each lane).
-// (the Roe and HLLC variants carry the dual-number flux: one wave per SIMD,
-// the whole register file)
-template <class T, int FLUX>
-__global__ void __launch_bounds__(256, FLUX == HFD_FLUX_RUSANOV ? ADJ_EDGE_WAVES : 1)
-k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
-           const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
-           const V4<T>* __restrict__ lh, T* __restrict__ out) {
-  const int s = threadIdx.x & 1;
-  const int64_t e = int64_t(blockIdx.x) * (blockDim.x / 2) + threadIdx.x / 2;
-  if (e >= ne) return;  // both lanes of a pair leave together
   const T gam = gp.gamma, gm1 = gam - T(1.0);
   const T nx = c.n[e], ny = c.n[ne + e];
   const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
@@ -401,8 +386,6 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1.0) / cc;
 
   // ---- reverse: Riemann flux -> this side's state ------------------------------------
-  const V4<T> g4 = lh[e];
-  const T gh[4] = {g4.x, g4.y, g4.z, g4.w};
   T gw[4];
   if constexpr (FLUX == HFD_FLUX_RUSANOV) {
     T glam = T(0.0);
@@ -805,18 +788,16 @@ template hipError_t launch_stage_gathers<float>(int64_t, int64_t, int64_t, const
 template <class T>
 hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
   if (a.ne > 0) {
-    hipLaunchKernelGGL(k_adj_edge_flux<T>, dim3(unsigned((8 * a.ne + 255) / 256)), dim3(256), 0,
-                       st, a.ne, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lh);
     const dim3 grid(unsigned((2 * a.ne + 255) / 256));
     if (a.gp.flux == HFD_FLUX_ROE)
       hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_ROE>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
-                         a.Gv, a.Gg, a.force, a.lh, a.bnode);
+                         a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
     else if (a.gp.flux == HFD_FLUX_HLLC)
       hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_HLLC>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
-                         a.Gv, a.Gg, a.force, a.lh, a.bnode);
+                         a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
     else
       hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_RUSANOV>), grid, dim3(256), 0, st, a.ne, a.ec,
-                         a.gp, a.Gv, a.Gg, a.force, a.lh, a.bnode);
+                         a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
   }
   if (a.nowned > 0) {
     const dim3 grid(unsigned((a.nowned + 15) / 16));

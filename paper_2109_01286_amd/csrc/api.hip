@@ -81,10 +81,8 @@ struct hfd_ctx {
   // float32 adjoint (mixed form, allocated at its first use)
   bool adj_coef32_ready = false;             // fde_t, fdv_t match de_t, dv_t
   float *fde_t = nullptr, *fdv_t = nullptr, *fdvis_t = nullptr, *bnode32 = nullptr;
-  hfd::V4<float>* lh32 = nullptr;
   hfd::V4<float>* LGv32[2] = {nullptr, nullptr};  // lambda in gather layout,
   hfd::V4<float>* LGg32[2] = {nullptr, nullptr};  // two for successive stages
-  hfd::V4<double>* lh = nullptr;
   hfd::V4<double>* LGv[2] = {nullptr, nullptr};
   hfd::V4<double>* LGg[2] = {nullptr, nullptr};
   // measurement: event pairs around the edge (0) and vertex (1) passes
@@ -562,7 +560,6 @@ hfd_status ensure_adjoint(hfd_ctx* c) {
   }
   if ((s = dalloc(c, &c->bnode, 72 * ne)) || (s = dalloc(c, &c->AL1, 12 * nv)) ||
       (s = dalloc(c, &c->AL2, 12 * nv)) || (s = dalloc(c, &c->AL3, 12 * nv)) ||
-      (s = dalloc(c, &c->lh, ne)) ||
       (s = dalloc(c, &c->LGv[0], nv)) || (s = dalloc(c, &c->LGg[0], 2 * nv)) ||
       (s = dalloc(c, &c->LGv[1], nv)) || (s = dalloc(c, &c->LGg[1], 2 * nv)))
     return s;
@@ -591,7 +588,7 @@ hfd_status ensure_adjoint32(hfd_ctx* c) {
   if (!c->fde_t) {
     if ((s = dalloc(c, &c->fde_t, 3 * nes)) || (s = dalloc(c, &c->fdv_t, 6 * nvs)) ||
         (c->dvis_t && (s = dalloc(c, &c->fdvis_t, 5 * nvs))) ||
-        (s = dalloc(c, &c->bnode32, 72 * ne)) || (s = dalloc(c, &c->lh32, ne)) ||
+        (s = dalloc(c, &c->bnode32, 72 * ne)) ||
         (s = dalloc(c, &c->LGv32[0], nv)) || (s = dalloc(c, &c->LGg32[0], 2 * nv)) ||
         (s = dalloc(c, &c->LGv32[1], nv)) || (s = dalloc(c, &c->LGg32[1], 2 * nv)))
       return s;
@@ -649,10 +646,10 @@ hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<T>* Gv,
   a.rc = rc;
   if constexpr (f32) {
     a.de_t = c->fde_t; a.dv_t = c->fdv_t; a.dvis_t = c->fdvis_t;
-    a.lh = c->lh32; a.bnode = c->bnode32;
+    a.bnode = c->bnode32;
   } else {
     a.de_t = c->de_t; a.dv_t = c->dv_t; a.dvis_t = c->dvis_t;
-    a.lh = c->lh; a.bnode = c->bnode;
+    a.bnode = c->bnode;
   }
   HIPCHK(c, hfd::launch_adjoint_residual<T>(a, st));
   if (out) HIPCHK(c, hfd::launch_zero_ghost_rows(h.n_owned, h.nv, out, st));

@@ -179,7 +179,6 @@ struct AdjointArgs {
   const T* de_t;                    // de rows in the order of etv
   const V4<T>* Lv;                  // lambda in gather layout
   const V4<T>* Lg;
-  V4<T>* lh;                        // [ne] flux adjoint
   EdgeCoef<T> ec;
   GasParams gp;                     // float32: with the reference state of Gv
   const V4<T>* Gv;                  // state in gather layout
