@@ -37,6 +37,11 @@
 namespace hfd {
 namespace {
 
+// lambda_h entries per lane and batch in the edge reverse (measured: 4 is
+// faster in float32, 2 in float64, whose registers are scarcer)
+template <class T>
+constexpr int kAdjGatherBatch = sizeof(T) == 4 ? 4 : 2;
+
 // Forward-mode dual number: a value and its derivative along one direction.
 // The adjoint of the Roe and HLLC fluxes runs their code (gas.h) on it, one
 // direction per component of the lane's interface state, so that every
@@ -184,31 +189,33 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // de[s'] . (lambda, lambda_x, lambda_y)(v): the lanes take alternate
   // entries (transposed order, contiguous per edge; every active edge has
   // one, so k1 - 1 is an entry: a lane past the end loads it again with zero
-  // weight), two per batch, loads issued here so that they overlap the
-  // forward recompute, and add their partial sums with one lane swap
+  // weight), kAdjGatherBatch per lane and batch, loads issued here so that
+  // they overlap the forward recompute, and add their partial sums with one
+  // lane swap
   T gh[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
   {
     const int k0 = tptr[e], k1 = tptr[e + 1];
-    for (int b = k0 + s; b < k1; b += 4) {
-      int kk[2];
-      bool ok[2];
-      for (int i = 0; i < 2; ++i) {
+    for (int b = k0 + s; b < k1; b += 2 * kAdjGatherBatch<T>) {
+      constexpr int NB = kAdjGatherBatch<T>;
+      int kk[NB];
+      bool ok[NB];
+      for (int i = 0; i < NB; ++i) {
         ok[i] = b + 2 * i < k1;
         kk[i] = ok[i] ? b + 2 * i : k1 - 1;
       }
-      int v[2];
-      T d[2][3];
-      for (int i = 0; i < 2; ++i) {
+      int v[NB];
+      T d[NB][3];
+      for (int i = 0; i < NB; ++i) {
         v[i] = tv[kk[i]];
         for (int q = 0; q < 3; ++q) d[i][q] = de_t[3 * int64_t(kk[i]) + q];
       }
-      V4<T> l0[2], lx[2], ly[2];
-      for (int i = 0; i < 2; ++i) {
+      V4<T> l0[NB], lx[NB], ly[NB];
+      for (int i = 0; i < NB; ++i) {
         l0[i] = Lv[v[i]];
         lx[i] = Lg[2 * int64_t(v[i])];
         ly[i] = Lg[2 * int64_t(v[i]) + 1];
       }
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < NB; ++i) {
         const T d0 = ok[i] ? d[i][0] : T(0.0), dx = ok[i] ? d[i][1] : T(0.0),
                 dy = ok[i] ? d[i][2] : T(0.0);
         gh[0] -= d0 * l0[i].x + dx * lx[i].x + dy * ly[i].x;
