@@ -17,6 +17,10 @@ CASES = {
     "shockvortex": ("shockvortex2049", 17, {"w3_cap": 2.0}, "paper"),
     "tgv": ("tgv513", 17, {"mu": 0.01}, "smooth"),
     "couette": ("couette", 31, {"mu": 0.1, "prandtl": 100.0, "gas_R": 20.0 / 7.0}, "smooth"),
+    # smallest meshes: 36 owned vertices (a partial vertex block), fewer edges
+    # than one block of the edge reverse; periodic, and with ghost regions
+    "tiny": ("vortex21", 7, {"w3_cap": 2.0}, "paper"),
+    "tiny_ghost": ("riemann201", 6, {"w3_cap": 2.0}, "weno"),
 }
 
 
@@ -108,7 +112,7 @@ def test_adjoint_dot_product_with_finite_differences(key):
     assert errs.max() < 1e-6
 
 
-@pytest.mark.parametrize("key", ["vortex21-weno", "shockvortex", "tgv", "couette"])
+@pytest.mark.parametrize("key", ["vortex21-weno", "shockvortex", "tgv", "couette", "tiny_ghost"])
 def test_rk_step_adjoint_matches_autograd(key):
     m, U, sc, S, sw = setup_case(key, force=False)
     dt = sc.stable_dt(U, 0.3)
