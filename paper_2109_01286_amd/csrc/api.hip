@@ -783,7 +783,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
     ep32[k] = int32_t(h.eptr[k]);
   }
   double *d_pts = nullptr, *d_eh = nullptr, *d_vpts = nullptr, *d_mpts = nullptr,
-         *d_mnrm = nullptr, *d_vh = nullptr;
+         *d_vh = nullptr;
   int64_t *d_vptr64 = nullptr, *d_eptr64 = nullptr;
   int32_t* d_status = nullptr;
   if ((s = upload(c, &c->stg, h.e_stg)) || (s = upload(c, &c->n, h.e_n)) ||
@@ -793,7 +793,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
       (s = upload(c, &c->copy_rows, h.copy_rows)) || (s = upload(c, &c->copy_src, h.copy_src)) ||
       (s = upload(c, &d_pts, h.e_pts)) || (s = upload(c, &d_eh, h.e_h)) ||
       (s = upload(c, &d_vpts, h.v_pts)) || (s = upload(c, &d_mpts, h.m_pts)) ||
-      (s = upload(c, &d_mnrm, h.m_nrm)) || (s = upload(c, &d_vh, h.v_h)) ||
+      (s = upload(c, &d_vh, h.v_h)) ||
       (s = upload(c, &d_vptr64, h.vptr)) || (s = upload(c, &d_eptr64, h.eptr)))
     return bail(s);
   if (c->stage.idx_bytes) {
@@ -844,8 +844,8 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   hipError_t he;
   if ((he = hfd::launch_edge_weights(ne, d_pts, d_eh, op.w3_cap, c->w5, c->w3, c->rank,
                                      c->trunc3, nullptr)) != hipSuccess ||
-      (he = hfd::launch_div_rows(no, rpl, d_vptr64, d_eptr64, d_vpts, d_mpts, d_mnrm,
-                                 d_vh, c->dv, c->de, d_status, nullptr)) != hipSuccess ||
+      (he = hfd::launch_div_rows(no, rpl, d_vptr64, d_eptr64, d_vpts, d_mpts, c->ve, c->n,
+                                 ne, d_vh, c->dv, c->de, d_status, nullptr)) != hipSuccess ||
       (he = hipDeviceSynchronize()) != hipSuccess) {
     c->err = std::string("precompute: ") + hipGetErrorString(he);
     return bail(HFD_E_DEVICE);
@@ -880,14 +880,13 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
     for (int32_t r : rk) I.rank_hist[std::min(15, std::max(0, r))]++;
     for (int8_t t : t3) I.w3_truncated += (t > 0);
   }
-  for (void* p : {(void*)d_pts, (void*)d_eh, (void*)d_vpts, (void*)d_mpts, (void*)d_mnrm,
+  for (void* p : {(void*)d_pts, (void*)d_eh, (void*)d_vpts, (void*)d_mpts,
                   (void*)d_vh, (void*)d_vptr64, (void*)d_eptr64, (void*)d_status})
     dfree(c, p);
   // host copies of the frames are no longer needed
   hfd::HostArray<double>().swap(h.e_pts);
   hfd::HostArray<double>().swap(h.v_pts);
   hfd::HostArray<double>().swap(h.m_pts);
-  hfd::HostArray<double>().swap(h.m_nrm);
   I.setup_ms[2] = ms_since(t2);
   if (mixed(c) && (s = ensure_mixed_buffers(c))) return bail(s);
   I.setup_ms[3] = ms_since(t0);

@@ -50,9 +50,9 @@ hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
                                int32_t* rank, int8_t* trunc3, hipStream_t st);
 hipError_t launch_div_rows(int64_t nowned, int rpl, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
-                           const double* mpts, const double* mnrm,
-                           const double* vh, double* dv, double* de,
-                           int32_t* status, hipStream_t st);
+                           const double* mpts, const int32_t* sedge,
+                           const double* en, int64_t ne, const double* vh, double* dv,
+                           double* de, int32_t* status, hipStream_t st);
 hipError_t launch_visc_rows(int64_t nowned, const int64_t* vptr,
                             const double* vpts, const double* vh, double* dvis,
                             int32_t* status, hipStream_t st);

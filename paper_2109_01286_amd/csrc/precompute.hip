@@ -370,9 +370,10 @@ template <int RPL>
 __global__ void __launch_bounds__(64)
 k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
            const int64_t* __restrict__ eptr, const double* __restrict__ vpts,
-           const double* __restrict__ mpts, const double* __restrict__ mnrm,
-           const double* __restrict__ vh, double* __restrict__ dv,
-           double* __restrict__ de, int32_t* __restrict__ status) {
+           const double* __restrict__ mpts, const int32_t* __restrict__ sedge,
+           const double* __restrict__ en, int64_t ne, const double* __restrict__ vh,
+           double* __restrict__ dv, double* __restrict__ de,
+           int32_t* __restrict__ status) {
   constexpr int LD = 64 * RPL;
   __shared__ double A[NC5 * LD];
   __shared__ double alpha[NC5];
@@ -398,8 +399,10 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
       int k = i - int(2 * N);
       x = mpts[2 * (m0 + k)];
       y = mpts[2 * (m0 + k) + 1];
-      fa = mnrm[2 * (m0 + k)];
-      fb = mnrm[2 * (m0 + k) + 1];
+      // the edge's unit direction (active-edge array, [2][ne])
+      const int64_t je = sedge[m0 + k];
+      fa = en[je];
+      fb = en[ne + je];
     }
     for (int c = 0; c < NB5; ++c) {
       double p = (i < m) ? mono<5>(c, 0, x, y) : 0.0;
@@ -565,16 +568,16 @@ hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
 
 hipError_t launch_div_rows(int64_t nowned, int rpl, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
-                           const double* mpts, const double* mnrm,
-                           const double* vh, double* dv, double* de,
-                           int32_t* status, hipStream_t st) {
+                           const double* mpts, const int32_t* sedge,
+                           const double* en, int64_t ne, const double* vh, double* dv,
+                           double* de, int32_t* status, hipStream_t st) {
   if (nowned == 0) return hipSuccess;
   if (rpl == 2)
-    hipLaunchKernelGGL(k_div_rows<2>, dim3(unsigned(nowned)), dim3(64), 0, st,
-                       nowned, vptr, eptr, vpts, mpts, mnrm, vh, dv, de, status);
+    hipLaunchKernelGGL(k_div_rows<2>, dim3(unsigned(nowned)), dim3(64), 0, st, nowned, vptr,
+                       eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
   else
-    hipLaunchKernelGGL(k_div_rows<3>, dim3(unsigned(nowned)), dim3(64), 0, st,
-                       nowned, vptr, eptr, vpts, mpts, mnrm, vh, dv, de, status);
+    hipLaunchKernelGGL(k_div_rows<3>, dim3(unsigned(nowned)), dim3(64), 0, st, nowned, vptr,
+                       eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
   return hipGetLastError();
 }
 

@@ -450,7 +450,6 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
   S.v_edges.resize(NES);
   S.v_pts.resize(2 * NVS);
   S.m_pts.resize(2 * NES);
-  S.m_nrm.resize(2 * NES);
   S.v_h.resize(NO);
   S.v_hmin.resize(NO);
   // Slot order inside a vertex: by gather row (vertex slots) and by internal
@@ -500,12 +499,9 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
         double ax, ay, dx, dy;
         geo.disp(v, ea[e], ax, ay);
         geo.disp(ea[e], eb[e], dx, dy);
-        double l = std::hypot(dx, dy);
         S.v_edges[m0 + i] = e_int[e];
         S.m_pts[2 * (m0 + i)] = (ax + 0.5 * dx) / h;
         S.m_pts[2 * (m0 + i) + 1] = (ay + 0.5 * dy) / h;
-        S.m_nrm[2 * (m0 + i)] = dx / l;
-        S.m_nrm[2 * (m0 + i) + 1] = dy / l;
       }
     }
   });

@@ -90,7 +90,6 @@ struct HostSetup {
   HostArray<int32_t> v_edges;         // [n_eslots] internal active-edge index
   HostArray<double> v_pts;            // [n_vslots][2] vertex frame (/ h_v)
   HostArray<double> m_pts;            // [n_eslots][2] edge midpoints, vertex frame
-  HostArray<double> m_nrm;            // [n_eslots][2] edge directions
   std::vector<double> v_h;            // [n_owned] mean incident edge length
   std::vector<double> v_hmin;         // [n_owned] shortest incident edge
 };
