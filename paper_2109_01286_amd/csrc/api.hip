@@ -974,7 +974,7 @@ hfd_status hfd_import_weights(hfd_ctx* c, const double* w5, const double* w3,
   if (w3 && (s = aos_to_soa(w3, 18, c->w3))) return s;
   if (dv) HIPCHK(c, hipMemcpy(c->dv, dv, 6 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
   if (de) HIPCHK(c, hipMemcpy(c->de, de, 3 * c->info.n_eslots * 8, hipMemcpyHostToDevice));
-  if (dv || de) c->adj_coef_ready = false;
+  if (dv || de || dvis) c->adj_coef_ready = false;
   if (dvis) {
     if (!c->dvis) return fail(c, HFD_E_STATE, "no viscous rows (mu == 0)");
     HIPCHK(c, hipMemcpy(c->dvis, dvis, 5 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
