@@ -840,11 +840,10 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   I.setup_ms[1] = ms_since(t1);
   auto t2 = std::chrono::steady_clock::now();
   // ---- precompute ----------------------------------------------------------
-  const int rpl = (2 * h.max_vs + h.max_es) <= 128 ? 2 : 3;
   hipError_t he;
   if ((he = hfd::launch_edge_weights(ne, d_pts, d_eh, op.w3_cap, c->w5, c->w3, c->rank,
                                      c->trunc3, nullptr)) != hipSuccess ||
-      (he = hfd::launch_div_rows(no, rpl, d_vptr64, d_eptr64, d_vpts, d_mpts, c->ve, c->n,
+      (he = hfd::launch_div_rows(no, int(msys), d_vptr64, d_eptr64, d_vpts, d_mpts, c->ve, c->n,
                                  ne, d_vh, c->dv, c->de, d_status, nullptr)) != hipSuccess ||
       (he = hipDeviceSynchronize()) != hipSuccess) {
     c->err = std::string("precompute: ") + hipGetErrorString(he);

@@ -48,7 +48,8 @@ __device__ inline void reduce_stage(T* a, int sub) {
 hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
                                double w3_cap, double* w5, double* w3,
                                int32_t* rank, int8_t* trunc3, hipStream_t st);
-hipError_t launch_div_rows(int64_t nowned, int rpl, const int64_t* vptr,
+// msys: the largest system's row count over the owned vertices (1..192)
+hipError_t launch_div_rows(int64_t nowned, int msys, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
                            const double* mpts, const int32_t* sedge,
                            const double* en, int64_t ne, const double* vh, double* dv,

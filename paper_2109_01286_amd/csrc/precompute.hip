@@ -22,6 +22,8 @@
 // exactly one wavefront, so synchronisation inside a group is wave-local.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace hfd {
@@ -366,19 +368,23 @@ k_edge_weights(int64_t ne, const double* __restrict__ pts,
 constexpr int NB5 = 21;       // degree-5 terms
 constexpr int NC5 = 2 * NB5;  // unknowns (a, b)
 
+// LD (a multiple of 8, at least the largest system's row count and NC5, at
+// most 64 RPL) is the row stride of the matrix in dynamic LDS: sized to the mesh
+// rather than to 64 RPL, it lets more blocks share a CU.  Rows i >= LD are
+// never touched (they would be zero padding).
 template <int RPL>
 __global__ void __launch_bounds__(64)
-k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
+k_div_rows(int64_t nowned, int LD, const int64_t* __restrict__ vptr,
            const int64_t* __restrict__ eptr, const double* __restrict__ vpts,
            const double* __restrict__ mpts, const int32_t* __restrict__ sedge,
            const double* __restrict__ en, int64_t ne, const double* __restrict__ vh,
            double* __restrict__ dv, double* __restrict__ de,
            int32_t* __restrict__ status) {
-  constexpr int LD = 64 * RPL;
-  __shared__ double A[NC5 * LD];
-  __shared__ double alpha[NC5];
-  __shared__ double vtvs[NC5];
-  __shared__ double yv[3 * NC5];
+  extern __shared__ double div_lds[];
+  double* A = div_lds;              // [NC5][LD]
+  double* alpha = A + NC5 * LD;     // [NC5]
+  double* vtvs = alpha + NC5;       // [NC5]
+  double* yv = vtvs + NC5;          // [3][NC5]
   const int lane = threadIdx.x;
   const int64_t v = blockIdx.x;
   if (v >= nowned) return;
@@ -388,6 +394,7 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
   // ---- assemble (rows over lanes) ---------------------------------------------
   for (int rr = 0; rr < RPL; ++rr) {
     int i = lane + rr * 64;
+    if (i >= LD) continue;
     double x = 0.0, y = 0.0, fa = 0.0, fb = 0.0;
     if (i < 2 * N) {
       int nd = i >> 1;
@@ -418,7 +425,7 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
     double s2 = 0.0;
     for (int rr = 0; rr < RPL; ++rr) {
       int i = lane + rr * 64;
-      double x = (i >= j) ? A[j * LD + i] : 0.0;
+      double x = (i >= j && i < LD) ? A[j * LD + i] : 0.0;
       s2 += x * x;
     }
     s2 = gsum<64>(s2);
@@ -437,13 +444,13 @@ k_div_rows(int64_t nowned, const int64_t* __restrict__ vptr,
         double d = 0.0;
         for (int rr = 0; rr < RPL; ++rr) {
           int i = lane + rr * 64;
-          if (i >= j) d += A[j * LD + i] * A[c * LD + i];
+          if (i >= j && i < LD) d += A[j * LD + i] * A[c * LD + i];
         }
         d = gsum<64>(d);
         double f = 2.0 * d / vtv;
         for (int rr = 0; rr < RPL; ++rr) {
           int i = lane + rr * 64;
-          if (i >= j) A[c * LD + i] -= f * A[j * LD + i];
+          if (i >= j && i < LD) A[c * LD + i] -= f * A[j * LD + i];
         }
       }
     }
@@ -566,18 +573,22 @@ hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
   return hipGetLastError();
 }
 
-hipError_t launch_div_rows(int64_t nowned, int rpl, const int64_t* vptr,
+hipError_t launch_div_rows(int64_t nowned, int msys, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
                            const double* mpts, const int32_t* sedge,
                            const double* en, int64_t ne, const double* vh, double* dv,
                            double* de, int32_t* status, hipStream_t st) {
   if (nowned == 0) return hipSuccess;
-  if (rpl == 2)
-    hipLaunchKernelGGL(k_div_rows<2>, dim3(unsigned(nowned)), dim3(64), 0, st, nowned, vptr,
-                       eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
+  if (msys < 1 || msys > 192) return hipErrorInvalidValue;
+  // at least NC5 rows, so that the diagonal A[j][j] (j < NC5) lies in column j
+  const int LD = (std::max(msys, NC5) + 7) / 8 * 8;
+  const size_t lds = size_t(NC5 * LD + 5 * NC5) * sizeof(double);
+  if (LD <= 128)
+    hipLaunchKernelGGL(k_div_rows<2>, dim3(unsigned(nowned)), dim3(64), lds, st, nowned, LD,
+                       vptr, eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
   else
-    hipLaunchKernelGGL(k_div_rows<3>, dim3(unsigned(nowned)), dim3(64), 0, st, nowned, vptr,
-                       eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
+    hipLaunchKernelGGL(k_div_rows<3>, dim3(unsigned(nowned)), dim3(64), lds, st, nowned, LD,
+                       vptr, eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
   return hipGetLastError();
 }
 
