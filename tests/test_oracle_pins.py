@@ -8,6 +8,7 @@ polynomial data, the Runge-Kutta stability polynomial, finite differences of
 the flux, and the Monte-Carlo order statistic of Section 2.2.
 """
 import math
+import os
 
 import numpy as np
 import numpy.polynomial.polynomial as npp
@@ -40,11 +41,23 @@ def test_basis_is_taylor_scaled():
 
 
 def test_basis_degree4_terms_match_paper_listing():
-    # the paper lists x^2 y/2, x y^2/2, x^3 y/6, x^2 y^2/4, ... : check three
-    x, y = 0.7, -1.3
-    p = basis.p(x, y, 4)
-    assert np.isclose(p[7], x * x * y / 2) and np.isclose(p[12], x * x * y * y / 4)
-    assert np.isclose(p[11], x ** 3 * y / 6) and basis.nterms(4) == 15
+    """All 15 terms of p, p_x and p_y as printed in Section 2.2 (fixture
+    tests/golden/hermite_basis_deg4.txt), at seeded points."""
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(__file__), "golden", "hermite_basis_deg4.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert [int(r[0]) for r in rows] == list(range(15)) and basis.nterms(4) == 15
+
+    def term(t, x, y):
+        c, a, b = t.split(":")
+        return float(Fraction(c)) * x ** int(a) * y ** int(b)
+
+    rng = np.random.default_rng(9)
+    for x, y in rng.uniform(-2.0, 2.0, size=(6, 2)):
+        got = (basis.p(x, y, 4), basis.px(x, y, 4), basis.py(x, y, 4))
+        for col in range(3):
+            want = np.array([term(r[1 + col], x, y) for r in rows])
+            assert np.allclose(np.asarray(got[col], dtype=float), want, rtol=1e-14, atol=1e-14)
 
 
 # ---------------------------------------------------------------------------
