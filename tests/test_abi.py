@@ -36,8 +36,15 @@ def test_struct_sizes_match_header_layout():
 
 def test_default_opts():
     o = hfd.default_opts()
-    assert o.gamma == 1.4 and o.weno_eps == 1e-6 and o.sw_lo == 0.01 and o.sw_hi == 0.79
+    assert o.gamma == 1.4 and o.weno_eps == 1e-6
     assert o.switch_mode == 0 and o.precision == 0 and o.order == 1
+    # the switch interval printed with eq. 2d_hweno_intp, in the library and the oracle
+    import os
+    from oracle import scheme as osch
+    path = os.path.join(os.path.dirname(__file__), "golden", "switch_interval.txt")
+    lo, hi = (float(x) for x in next(ln for ln in open(path) if not ln.startswith("#")).split())
+    assert (o.sw_lo, o.sw_hi) == (lo, hi)
+    assert (osch.Options().sw_lo, osch.Options().sw_hi) == (lo, hi)
 
 
 def _mesh():
