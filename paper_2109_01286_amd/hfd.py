@@ -129,11 +129,10 @@ def _ptr(a):
 
 
 def _dptr(t):
-    """Device pointer of a contiguous torch tensor (or None)."""
+    """Device pointer of a torch tensor already checked by Solver._dev (or
+    None)."""
     if t is None:
         return None
-    import torch
-    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -205,6 +204,31 @@ class Solver:
     def _chk(self, st):
         if st != 0:
             raise HfdError(st, lib().hfd_last_error(self._h).decode())
+
+    def _dev(self, t, name, dtype="float64", shape=None, min_numel=None):
+        """Check one device argument before anything is launched: a torch
+        tensor of the given dtype and shape (or at least ``min_numel``
+        elements), contiguous, on this solver's GPU.  The C ABI takes bare
+        pointers and cannot see any of this, so a wrong tensor would make
+        the kernels read or write past its end.  Raises ValueError."""
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        want = getattr(torch, dtype)
+        if t.dtype != want:
+            raise ValueError(f"{name}: dtype {t.dtype}, expected {want}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if min_numel is not None and t.numel() < min_numel:
+            raise ValueError(f"{name}: {t.numel()} elements, at least {min_numel} expected")
+        if t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name}: on {t.device}, expected cuda:{self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: not contiguous")
+        return _dptr(t)
+
+    def _state(self, t, name="U"):
+        return self._dev(t, name, shape=(12, self.nv))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -288,94 +312,109 @@ class Solver:
         self.opts.flux = f
 
     # -- hot path -------------------------------------------------------------------
+    # Every device argument is checked by _dev / _state before the call.
     def residual(self, U, out=None):
         import torch
+        pU = self._state(U)
         if out is None:
             out = torch.empty_like(U)
-        self._chk(lib().hfd_residual(self._h, _dptr(U), _dptr(out), _stream()))
+        self._chk(lib().hfd_residual(self._h, pU, self._state(out, "out"), _stream()))
         return out
 
     def rk_step(self, U, dt):
         """One RK3 step in place; ``dt`` a float or a 1-element device tensor."""
         import torch
+        pU = self._state(U)
         if isinstance(dt, torch.Tensor):
-            self._chk(lib().hfd_rk_step_dev(self._h, _dptr(U), _dptr(dt), _stream()))
+            pdt = self._dev(dt, "dt", min_numel=1)
+            self._chk(lib().hfd_rk_step_dev(self._h, pU, pdt, _stream()))
         else:
-            self._chk(lib().hfd_rk_step(self._h, _dptr(U), float(dt), _stream()))
+            self._chk(lib().hfd_rk_step(self._h, pU, float(dt), _stream()))
         return U
 
     def rk_steps(self, U, nsteps, cfl, dts=None):
         """nsteps x (stable_dt then rk_step) in place; returns the device
         tensor [nsteps] of step sizes (no host sync)."""
         import torch
+        nsteps = int(nsteps)
+        if nsteps < 0:
+            raise ValueError(f"nsteps = {nsteps} < 0")
+        pU = self._state(U)
         if dts is None:
-            dts = torch.empty(max(int(nsteps), 1), dtype=torch.float64, device=U.device)
-        self._chk(lib().hfd_rk_steps(self._h, _dptr(U), int(nsteps), float(cfl), _dptr(dts),
-                                     _stream()))
+            dts = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U.device)
+        pd = self._dev(dts, "dts", min_numel=max(nsteps, 1))
+        self._chk(lib().hfd_rk_steps(self._h, pU, nsteps, float(cfl), pd, _stream()))
         return dts
 
     def stable_dt(self, U, cfl, out=None):
         """Device tensor [1] with cfl * min h/(|u|+c) (no host sync)."""
         import torch
+        pU = self._state(U)
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=U.device)
-        self._chk(lib().hfd_stable_dt(self._h, _dptr(U), float(cfl), _dptr(out),
-                                      _stream()))
+        self._chk(lib().hfd_stable_dt(self._h, pU, float(cfl),
+                                      self._dev(out, "out", min_numel=1), _stream()))
         return out
 
     def edge_states(self, U, want_mask=True, want_flux=True):
         import torch
+        pU = self._state(U)
         wlr = torch.empty(8, self.ne, dtype=torch.float64, device=U.device)
         mask = torch.empty(self.ne, dtype=torch.uint8, device=U.device) if want_mask else None
         h = torch.empty(4, self.ne, dtype=torch.float64, device=U.device) if want_flux else None
-        self._chk(lib().hfd_edge_states(self._h, _dptr(U), _dptr(wlr), _dptr(mask),
+        self._chk(lib().hfd_edge_states(self._h, pU, _dptr(wlr), _dptr(mask),
                                         _dptr(h), _stream()))
         return wlr, mask, h
 
     def force_switch_mask(self, mask):
-        """Force the Hermite/WENO branch per edge (uint8 device tensor) or
-        return to the configured switch (None)."""
+        """Force the Hermite/WENO branch per edge (uint8 device tensor [ne])
+        or return to the configured switch (None)."""
+        p = None if mask is None else self._dev(mask, "mask", dtype="uint8", shape=(self.ne,))
         self._force = mask
-        self._chk(lib().hfd_force_switch_mask(self._h, _dptr(mask)))
+        self._chk(lib().hfd_force_switch_mask(self._h, p))
 
     def adjoint_residual(self, U, lam, out=None):
         """(dR/dU)^T lam (float64 device tensors [12, V], internal order),
         computed in the context's precision."""
         import torch
+        pU, pl = self._state(U), self._state(lam, "lam")
         if out is None:
             out = torch.empty_like(U)
-        self._chk(lib().hfd_adjoint_residual(self._h, _dptr(U), _dptr(lam), _dptr(out),
+        self._chk(lib().hfd_adjoint_residual(self._h, pU, pl, self._state(out, "out"),
                                              _stream()))
         return out
 
     def rk_step_adjoint(self, U_n, dt, lam_np1, out=None):
         """(dU_{n+1}/dU_n)^T lam_np1 for one RK3 step of size dt from U_n."""
         import torch
+        pU, pl = self._state(U_n, "U_n"), self._state(lam_np1, "lam_np1")
         if out is None:
             out = torch.empty_like(U_n)
-        self._chk(lib().hfd_rk_step_adjoint(self._h, _dptr(U_n), float(dt), _dptr(lam_np1),
-                                            _dptr(out), _stream()))
+        self._chk(lib().hfd_rk_step_adjoint(self._h, pU, float(dt), pl,
+                                            self._state(out, "out"), _stream()))
         return out
 
     def rk_step_stages(self, U, dt, U1, U2):
         """One RK3 step in place (the context's precision) that also writes
         its intermediate stages into U1, U2 (device tensors shaped like U)."""
-        self._chk(lib().hfd_rk_step_stages(self._h, _dptr(U), float(dt), _dptr(U1), _dptr(U2),
+        self._chk(lib().hfd_rk_step_stages(self._h, self._state(U), float(dt),
+                                           self._state(U1, "U1"), self._state(U2, "U2"),
                                            _stream()))
         return U
 
     def rk_step_adjoint_stages(self, U_n, U1, U2, dt, lam_np1, out=None):
         """rk_step_adjoint with the step's stages (from rk_step_stages) given."""
         import torch
+        p = [self._state(U_n, "U_n"), self._state(U1, "U1"), self._state(U2, "U2")]
+        pl = self._state(lam_np1, "lam_np1")
         if out is None:
             out = torch.empty_like(U_n)
-        self._chk(lib().hfd_rk_step_adjoint_stages(self._h, _dptr(U_n), _dptr(U1), _dptr(U2),
-                                                   float(dt), _dptr(lam_np1), _dptr(out),
-                                                   _stream()))
+        self._chk(lib().hfd_rk_step_adjoint_stages(self._h, *p, float(dt), pl,
+                                                   self._state(out, "out"), _stream()))
         return out
 
     def fill_ghosts(self, U):
-        self._chk(lib().hfd_fill_ghosts(self._h, _dptr(U), _stream()))
+        self._chk(lib().hfd_fill_ghosts(self._h, self._state(U), _stream()))
         return U
 
     def check(self):

@@ -140,3 +140,39 @@ def test_vertex_stage_lists_and_byte_model():
     for k in ("n_vslots", "n_eslots", "bytes_edge_launch", "bytes_vertex_launch", "max_vslots",
               "max_eslots"):
         assert i[k] == i0[k]
+
+
+def test_binding_refuses_wrong_device_arguments_before_any_launch():
+    """The C ABI takes bare pointers, so the binding checks dtype, shape,
+    device and layout of every device argument and raises ValueError before
+    calling the library (a host-only context: nothing could run anyway)."""
+    import torch
+    m = _mesh()
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=-1)
+    good = torch.zeros(12, S.nv, dtype=torch.float64)
+    cases = [
+        (lambda: S.residual(good.float()), "dtype"),
+        (lambda: S.residual(torch.zeros(4, S.nv, dtype=torch.float64)), "shape"),
+        (lambda: S.residual(torch.zeros(12, S.nv + 1, dtype=torch.float64)), "shape"),
+        (lambda: S.residual(good), "expected cuda:-1"),
+        (lambda: S.residual(good.numpy()), "torch tensor"),
+        (lambda: S.rk_step(good, 1e-3), "expected cuda"),
+        (lambda: S.rk_steps(good, -1, 0.3), "nsteps"),
+        (lambda: S.stable_dt(good, 0.3), "expected cuda"),
+        (lambda: S.edge_states(good), "expected cuda"),
+        (lambda: S.force_switch_mask(torch.zeros(S.ne, dtype=torch.int32)), "dtype"),
+        (lambda: S.force_switch_mask(torch.zeros(S.ne - 1, dtype=torch.uint8)), "shape"),
+        (lambda: S.adjoint_residual(good[:, ::2], good), "shape"),
+        (lambda: S.rk_step_adjoint(good.float(), 1e-3, good), "dtype"),
+        (lambda: S.rk_step_stages(good[:4], 1e-3, good, good), "shape"),
+        (lambda: S.rk_step_adjoint_stages(good, good, good, 1e-3, good), "expected cuda"),
+        (lambda: S.fill_ghosts(good), "expected cuda"),
+    ]
+    for call, msg in cases:
+        with pytest.raises(ValueError) as e:
+            call()
+        assert msg in str(e.value), (msg, str(e.value))
+    # a transposed view has the right shape but not the layout
+    with pytest.raises(ValueError) as e:
+        S._state(torch.zeros(S.nv, 12, dtype=torch.float64).t())
+    assert "contiguous" in str(e.value) or "expected cuda" in str(e.value)
