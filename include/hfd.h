@@ -248,6 +248,19 @@ hfd_status hfd_rk_steps(hfd_ctx* ctx, double* U, int64_t nsteps, double cfl, dou
 hfd_status hfd_stable_dt(hfd_ctx* ctx, const double* U, double cfl,
                          double* dt_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * *dt_dev as hfd_stable_dt, bit for bit, with the per-block partial minima
+ * in a scratch array of the library (16384 doubles = 128 KiB per GPU, held
+ * until the process ends) instead of the context's buffer.  Calls no
+ * allocating routine.  Limit: n_owned <= 4194304 (one partial per 256 owned
+ * vertices), else HFD_E_INVAL with a message.  Every call on one GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (different streams or
+ * host threads, any contexts) race and must be serialised by the caller.
+ * No sync. */
+hfd_status hfd_stable_dt_noalloc(hfd_ctx* ctx, const double* U, double cfl,
+                                 double* dt_dev, void* stream);
+
 /* Midpoint states and flux of every active edge (device outputs, float64):
  *   wlr[8][n_edges]  rows 0-3 left state (from i-2..i+2), 4-7 right state
  *   mask[n_edges]    NULL or bit (4*side + component) set where the WENO

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,14 @@
 #endif
 
 using hfd::GasParams;
+
+// Scratch of hfd_stable_dt_noalloc: the per-block partial minima of the time
+// step (one per 256 owned vertices).  A file-scope device array: every GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never passes this name to a kernel; it uses the per-device address that
+// hipGetSymbolAddress returns (scratch_setup below).
+constexpr int64_t kNoallocDtPartials = 16384;
+static __device__ __align__(256) double scratch[kNoallocDtPartials];
 
 struct hfd_ctx {
   hfd_opts o{};
@@ -65,6 +74,7 @@ struct hfd_ctx {
   Bufs<float> b32;
   double* dtpart = nullptr;
   int64_t ndtpart = 0;
+  double* scratch_dev = nullptr;  // this device's address of `scratch`
   int32_t* flag = nullptr;
   const uint8_t* force = nullptr;
   // adjoint: transposed maps and work buffers (built at first use)
@@ -315,6 +325,26 @@ hfd::VertexCoef<float> vcoef32(const hfd_ctx* c) {
           c->hrp,  c->hrow, c->hep,  c->hedge, c->lbase,    c->vloc,     c->eloc,
           g.idx_bytes,
           g.max_rows, g.max_edges};
+}
+
+// Device address of `scratch` on the context's device, taken once per device
+// with that device current and kept for every later context on it.
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;
+
+hfd_status scratch_setup(hfd_ctx* c) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (c->device >= int(g_scratch_dev.size())) g_scratch_dev.resize(c->device + 1, nullptr);
+  if (!g_scratch_dev[c->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, HFD_E_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[c->device] = static_cast<double*>(p);
+  }
+  c->scratch_dev = g_scratch_dev[c->device];
+  return HFD_OK;
 }
 
 hfd_status need_device(const hfd_ctx* c) {
@@ -775,6 +805,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
     c->err = "hipSetDevice failed";
     return bail(HFD_E_DEVICE);
   }
+  if ((s = scratch_setup(c))) return bail(s);
   auto t1 = std::chrono::steady_clock::now();
   const int64_t ne = h.ne, no = h.n_owned, nvs = I.n_vslots, nes = I.n_eslots;
   std::vector<int32_t> vp32(no + 1), ep32(no + 1);
@@ -1046,6 +1077,26 @@ hfd_status hfd_stable_dt(hfd_ctx* c, const double* U, double cfl, double* dt_dev
   if (!U || !dt_dev || !(cfl > 0.0)) return fail(c, HFD_E_INVAL, "null pointer or cfl <= 0");
   HIPCHK(c, hfd::launch_stable_dt(c->hs.n_owned, c->hs.nv, U, c->hmin, c->o.gamma, cfl,
                                   c->dtpart, c->ndtpart, dt_dev,
+                                  static_cast<hipStream_t>(stream)));
+  return HFD_OK;
+}
+
+hfd_status hfd_stable_dt_noalloc(hfd_ctx* c, const double* U, double cfl, double* dt_dev,
+                                 void* stream) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!U || !dt_dev || !(cfl > 0.0)) return fail(c, HFD_E_INVAL, "null pointer or cfl <= 0");
+  if (!c->scratch_dev) return fail(c, HFD_E_STATE, "scratch address not set up");
+  // one partial minimum per 256 owned vertices, all in the shared scratch
+  const int64_t np = std::max<int64_t>(1, (c->hs.n_owned + 255) / 256);
+  if (np > kNoallocDtPartials)
+    return fail(c, HFD_E_INVAL,
+                "hfd_stable_dt_noalloc: " + std::to_string(c->hs.n_owned) +
+                    " owned vertices, more than the " +
+                    std::to_string(kNoallocDtPartials * 256) +
+                    " its scratch covers (use hfd_stable_dt)");
+  HIPCHK(c, hfd::launch_stable_dt(c->hs.n_owned, c->hs.nv, U, c->hmin, c->o.gamma, cfl,
+                                  c->scratch_dev, np, dt_dev,
                                   static_cast<hipStream_t>(stream)));
   return HFD_OK;
 }

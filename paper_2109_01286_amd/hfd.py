@@ -89,6 +89,7 @@ SIGNATURES = {
     "hfd_rk_step_dev": (ctypes.c_int, [_P, _P, _P, _P]),
     "hfd_rk_steps": (ctypes.c_int, [_P, _P, _I64, _D, _P, _P]),
     "hfd_stable_dt": (ctypes.c_int, [_P, _P, _D, _P, _P]),
+    "hfd_stable_dt_noalloc": (ctypes.c_int, [_P, _P, _D, _P, _P]),
     "hfd_edge_states": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "hfd_force_switch_mask": (ctypes.c_int, [_P, _P]),
     "hfd_fill_ghosts": (ctypes.c_int, [_P, _P, _P]),
@@ -354,6 +355,14 @@ class Solver:
             out = torch.empty(1, dtype=torch.float64, device=U.device)
         self._chk(lib().hfd_stable_dt(self._h, pU, float(cfl),
                                       self._dev(out, "out", min_numel=1), _stream()))
+        return out
+
+    def stable_dt_noalloc(self, U, cfl, out):
+        """stable_dt into the caller's device tensor ``out`` [>= 1] through
+        the entry point that allocates nothing (library scratch; calls on
+        one GPU must not overlap)."""
+        self._chk(lib().hfd_stable_dt_noalloc(self._h, self._state(U), float(cfl),
+                                              self._dev(out, "out", min_numel=1), _stream()))
         return out
 
     def edge_states(self, U, want_mask=True, want_flux=True):
