@@ -95,7 +95,10 @@ typedef struct hfd_opts {
                           neighbour data from HBM instead of staging each
                           block's distinct rows and fluxes in LDS (same
                           results bit for bit)                            */
-  int32_t reserved[3];
+  int32_t edge_grad;   /* 1: also compute and keep (float64, 96 doubles per
+                          edge) the midpoint-derivative rows that
+                          hfd_edge_states needs for its grad output; 0: no */
+  int32_t reserved[2];
 } hfd_opts;
 
 typedef struct hfd_info {
@@ -209,6 +212,18 @@ hfd_status hfd_import_weights(hfd_ctx* ctx, const double* w5, const double* w3,
                               const double* dv, const double* de,
                               const double* dvis);
 
+/* Midpoint-derivative rows (contexts with edge_grad = 1; host arrays,
+ * physical units, any may be NULL; synchronise):
+ *   w5g[n_edges][2][2][15]   per side and direction (d/dx, d/dy) the
+ *                            derivative row of the 5-node operator on
+ *                            (value, d/dx, d/dy) of the side's nodes
+ *   w3g[n_edges][2][3][2][3] per side, substencil and direction the
+ *                            derivative row of the 3-node interpolant
+ * Export copies them out; import replaces them (for parity runs with
+ * another implementation's rows).  HFD_E_STATE without edge_grad. */
+hfd_status hfd_export_grad_weights(const hfd_ctx* ctx, double* w5g, double* w3g);
+hfd_status hfd_import_grad_weights(hfd_ctx* ctx, const double* w5g, const double* w3g);
+
 /* Switch the hot path between float64 and the mixed form (float32
  * arithmetic on w - w_ref, float64 Runge-Kutta accumulation).  w_ref[4]
  * (host) is the reference state subtracted before rounding to float32 (NULL
@@ -261,12 +276,23 @@ hfd_status hfd_stable_dt(hfd_ctx* ctx, const double* U, double cfl,
 hfd_status hfd_stable_dt_noalloc(hfd_ctx* ctx, const double* U, double cfl,
                                  double* dt_dev, void* stream);
 
-/* Midpoint states and flux of every active edge (device outputs, float64):
- *   wlr[8][n_edges]  rows 0-3 left state (from i-2..i+2), 4-7 right state
- *   mask[n_edges]    NULL or bit (4*side + component) set where the WENO
- *                    value was used
- *   h[4][n_edges]    NULL or Riemann flux along the edge direction */
-hfd_status hfd_edge_states(hfd_ctx* ctx, const double* U, double* wlr,
+/* Midpoint states, their derivatives and the flux of every active edge
+ * (Section 2.2 / Algorithm 1; device outputs, float64):
+ *   wlr[8][n_edges]   rows 0-3 left state (from i-2..i+2), 4-7 right state
+ *   grad[16][n_edges] NULL or the derivatives of those states at the edge
+ *                     midpoint: row 8 side + 4 d + q = d/dx (d = 0) or d/dy
+ *                     (d = 1) of component q of side 0 (left) or 1 (right).
+ *                     Per characteristic component, the branch its value
+ *                     takes: rows 2 and 3 of the 5-node Hermite operator
+ *                     (eq. hintp_5) applied to (c, c_x, c_y), or the
+ *                     omega-weighted gradients of the three 3-node
+ *                     interpolants (eq. 3nodes_intp); back-projected with R.
+ *                     Needs a context created with hfd_opts.edge_grad = 1
+ *                     (else HFD_E_STATE).  Not used by the residual.
+ *   mask[n_edges]     NULL or bit (4*side + component) set where the WENO
+ *                     value was used
+ *   h[4][n_edges]     NULL or Riemann flux along the edge direction */
+hfd_status hfd_edge_states(hfd_ctx* ctx, const double* U, double* wlr, double* grad,
                            uint8_t* mask, double* h, void* stream);
 
 /* Force the branch of eq. 2d_hweno_intp per edge, side and component:

@@ -39,6 +39,13 @@ Readings:
 Modes: ``switch`` = "paper" (the rule above), "smooth" (always the 5-node
 value), "weno" (always the WENO value), or an explicit per-edge mask
 (uint8, bit 4*side + component set = WENO value).
+
+Alternative readings (Options), for comparison with the defaults:
+``branch="algorithm"`` takes the branches as Algorithm 1 prints them (the
+omega-weighted 3-node values when 0.01 < omega_1 < 0.79, the 5-node value
+otherwise); ``hermite``/``drop`` select the weight readings of
+weights.edge_weights; ``deg_inv``/``deg_vis`` the degrees of the divergence
+and viscous fits.
 """
 from __future__ import annotations
 
@@ -64,6 +71,11 @@ class Options:
     switch: object = "paper"
     w3_cap: float = 0.0     # 0: no dropping rule for the 3-node systems
     flux: str = "rusanov"   # Riemann flux: "rusanov", "roe" or "hllc"
+    branch: str = "equation"  # "equation" (eq. 2d_hweno_intp) or "algorithm"
+    hermite: str = "graded"   # weight reading: "graded" or "physical"
+    drop: str = "value"       # entries the 5-node dropping rule tests
+    deg_inv: int = 5          # degree of the inviscid divergence fit
+    deg_vis: int = 4          # degree of the viscous vertex-only fit
 
 
 def weno_omega(c, eps):
@@ -99,11 +111,15 @@ class Scheme:
         self.topo = topo or omesh.build(self.xy, tri, ghost_src, self.period,
                                         verts)
         t = self.topo
-        self.ew = ow.edge_weights(t, self.xy, self.period,
-                                  w3_cap=self.opts.w3_cap)
-        viscous = self.opts.mu > 0.0
+        o = self.opts
+        if o.branch not in ("equation", "algorithm"):
+            raise ValueError(o.branch)
+        self.ew = ow.edge_weights(t, self.xy, self.period, w3_cap=o.w3_cap,
+                                  reading=o.hermite, drop=o.drop)
+        viscous = o.mu > 0.0
         self.vr = ow.vertex_rows(t, self.xy, self.period, t.verts,
-                                 viscous=viscous)
+                                 viscous=viscous, deg=o.deg_inv,
+                                 deg_vis=o.deg_vis)
         self._flatten()
 
     # -- layout -------------------------------------------------------------
@@ -116,6 +132,8 @@ class Scheme:
         self.n = _t(ew.n)
         self.w5 = _t(ew.w5)
         self.w3 = _t(ew.w3)
+        self.w5g = _t(ew.w5g)
+        self.w3g = _t(ew.w3g)
         vs_own, vs_node, vs_c, vs_v = [], [], [], []
         es_own, es_edge, es_c = [], [], []
         for j, v in enumerate(vr.verts):
@@ -154,10 +172,15 @@ class Scheme:
         return W
 
     # -- step 2 -------------------------------------------------------------
-    def edge_states(self, U, switch=None):
-        """Left/right midpoint states, WENO mask and Rusanov flux of every
+    def edge_states(self, U, switch=None, grad=False):
+        """Left/right midpoint states, WENO mask and Riemann flux of every
         edge of the scheme.  Returns (wl [E,4], wr [E,4], mask [E] uint8,
-        h [E,4])."""
+        h [E,4]); with ``grad`` also the midpoint derivatives gl, gr
+        [E, 2, 4] (d/dx, d/dy of each conservative component) of both sides:
+        per characteristic component the derivative rows of the branch it
+        takes -- the 5-node operator applied to (c, c_x, c_y), or the
+        omega-weighted gradients of the three 3-node interpolants with the
+        weights of the value -- then back-projected with R."""
         o = self.opts
         sw = o.switch if switch is None else switch
         W = self.fill_ghosts(U)
@@ -172,7 +195,7 @@ class Scheme:
         cy = torch.einsum("eqr,ejr->ejq", L, wy)
         E = w.shape[0]
         mask = torch.zeros(E, dtype=torch.uint8)
-        out = []
+        out, gout = [], []
         for s, nodes in enumerate(ow.SIDE_NODES):
             idx = list(nodes)
             cs, cxs, cys = c[:, idx], cx[:, idx], cy[:, idx]     # [E, 5, 4]
@@ -188,7 +211,8 @@ class Scheme:
             if isinstance(sw, str):
                 if sw == "paper":
                     o1 = om[..., 0]
-                    use = ~((o1 > o.sw_lo) & (o1 < o.sw_hi))
+                    inside = (o1 > o.sw_lo) & (o1 < o.sw_hi)
+                    use = inside if o.branch == "algorithm" else ~inside
                 elif sw == "smooth":
                     use = torch.zeros_like(smooth, dtype=torch.bool)
                 elif sw == "weno":
@@ -203,8 +227,23 @@ class Scheme:
                 mask |= (use[:, q].to(torch.uint8) << (4 * s + q))
             C = torch.where(use, weno, smooth)
             out.append(torch.einsum("eqr,er->eq", R, C))
+            if grad:
+                gs = []
+                for d in range(2):
+                    g5 = self.w5g[:, s, d]                        # [E, 15]
+                    gsm = (torch.einsum("ej,ejq->eq", g5[:, 0::3], cs)
+                           + torch.einsum("ej,ejq->eq", g5[:, 1::3], cxs)
+                           + torch.einsum("ej,ejq->eq", g5[:, 2::3], cys))
+                    gsub = torch.stack([torch.einsum("et,etq->eq", self.w3g[:, s, j, d],
+                                                     cs[:, j:j + 3]) for j in range(3)],
+                                       dim=-1)
+                    gw = (om * gsub).sum(dim=-1)
+                    gs.append(torch.einsum("eqr,er->eq", R, torch.where(use, gw, gsm)))
+                gout.append(torch.stack(gs, dim=1))               # [E, 2, 4]
         wl, wr = out
         h = gas.riemann_flux(o.flux, wl, wr, self.n, o.gamma)
+        if grad:
+            return wl, wr, mask, h, gout[0], gout[1]
         return wl, wr, mask, h
 
     # -- step 3 -------------------------------------------------------------

@@ -41,6 +41,22 @@ each one):
 * Divergence: polynomial degree 5 for the inviscid fit (vertices + edge
   midpoints), degree 4 for the viscous vertex-only fit; the centre vertex
   is part of the stencil; no weighting.
+
+Alternative readings, kept as options so that they can be compared with the
+ones above (``reading``/``drop`` of edge_weights, ``deg``/``deg_vis`` of
+vertex_rows):
+
+* ``reading="physical"``: Section 2.2 taken literally.  P is built in
+  physical units with the origin at the edge midpoint; every numerically
+  non-zero singular value (above sigma_1 * 15 * eps, the usual rank
+  tolerance) is kept at first; while any of the 15 entries of the stored
+  row P^+(1,:) has magnitude >= 1 the smallest kept one is dropped; the row
+  of the plain pseudo-inverse is stored, with no graded correction and no
+  fold.  The 3-node rows are the plain minimum-norm pseudo-inverse of the
+  3 x 6 system in physical units (eq. 3nodes_intp), again with no fold.
+* ``drop="all"``: the dropping rule tested on all 15 entries of the stored
+  row (value and derivative weights in the edge frame), not only on the
+  five value weights.
 """
 from __future__ import annotations
 
@@ -93,12 +109,18 @@ def hermite_matrix(pts):
     return P
 
 
-def hermite_weights(pts, anchor=2, rank_cap=14):
+def hermite_weights(pts, anchor=2, rank_cap=14, drop="value", grad=False):
     """Row of the graded Hermite pseudo-inverse with the dropping rule.
 
-    ``pts`` [b, 5, 2] in the edge frame.  Returns (w [b, 15] in the edge
-    frame: (value, d/dx, d/dy) per node, rank [b]).
+    ``pts`` [b, 5, 2] in the edge frame.  ``drop``: "value" tests the five
+    value weights, "all" every entry of the row.  Returns (w [b, 15] in the
+    edge frame: (value, d/dx, d/dy) per node, rank [b]); with ``grad`` also
+    g [b, 2, 15], rows 2 and 3 of the same operator (the x- and
+    y-derivative of the fitted quartic at the midpoint, edge frame) at the
+    final rank, their anchor value weight absorbing minus the sum of their
+    value weights so that a constant has zero gradient.
     """
+    tested = slice(0, 15, 3) if drop == "value" else slice(0, 15)
     pts = np.asarray(pts, dtype=np.float64)
     b = pts.shape[0]
     U, s, V = svd_full(hermite_matrix(pts))
@@ -111,20 +133,71 @@ def hermite_weights(pts, anchor=2, rank_cap=14):
             idx = np.nonzero(todo & (r == rv))[0]
             wi = graded_rows(U[idx], s[idx], V[idx], int(rv), top, [0])[:, 0, :]
             w[idx] = wi
-            drop = (np.max(np.abs(wi[:, 0::3]), axis=1) >= 1.0) & (rv > 1)
-            r[idx[drop]] -= 1
-            todo[idx[~drop]] = False
+            big = (np.max(np.abs(wi[:, tested]), axis=1) >= 1.0) & (rv > 1)
+            r[idx[big]] -= 1
+            todo[idx[~big]] = False
     w[:, 3 * anchor] += 1.0 - w[:, 0::3].sum(axis=1)
-    return w, r
+    if not grad:
+        return w, r
+    g = np.empty((b, 2, 15))
+    for rv in np.unique(r):
+        idx = np.nonzero(r == rv)[0]
+        g[idx] = graded_rows(U[idx], s[idx], V[idx], int(rv), top, [1, 2])
+    g[:, :, 3 * anchor] -= g[:, :, 0::3].sum(axis=2)
+    return w, r, g
 
 
-def three_node_weights(pts, anchor, cap=0.0):
+def hermite_weights_physical(pts, grad=False):
+    """First row of the plain pseudo-inverse of P in physical units with the
+    dropping rule on all 15 entries (the literal reading of Section 2.2).
+
+    ``pts`` [b, 5, 2] physical offsets from the edge midpoint.  Returns
+    (w [b, 15] physical units: (value, d/dx, d/dy) per node, rank [b]); with
+    ``grad`` also rows 2 and 3 at the final rank, g [b, 2, 15].
+    """
+    pts = np.asarray(pts, dtype=np.float64)
+    U, s, V = svd_full(hermite_matrix(pts))
+    r = np.count_nonzero(s > s[:, :1] * 15 * np.finfo(np.float64).eps, axis=1)
+    w = np.empty((pts.shape[0], 15))
+    g = np.empty((pts.shape[0], 2, 15))
+    todo = np.ones(pts.shape[0], dtype=bool)
+    while np.any(todo):
+        for rv in np.unique(r[todo]):
+            idx = np.nonzero(todo & (r == rv))[0]
+            rv = int(rv)
+            # rows 1..3 of V_r S_r^-1 U_r^T
+            K = np.einsum("bjr,bmr->bjm", V[idx, 0:3, :rv] / s[idx, None, :rv],
+                          U[idx, :, :rv])
+            w[idx] = K[:, 0]
+            g[idx] = K[:, 1:3]
+            big = (np.max(np.abs(K[:, 0]), axis=1) >= 1.0) & (rv > 1)
+            r[idx[big]] -= 1
+            todo[idx[~big]] = False
+    return (w, r, g) if grad else (w, r)
+
+
+def three_node_weights_physical(pts, grad=False):
+    """Value weights of the 3 x 6 system of eq. 3nodes_intp by the plain
+    minimum-norm pseudo-inverse in physical units (no fold, no dropping);
+    ``pts`` [b, 3, 2] physical offsets from the edge midpoint.  With
+    ``grad`` also the x- and y-derivative rows at the midpoint [b, 2, 3]."""
+    pts = np.asarray(pts, dtype=np.float64)
+    A = basis.p(pts[..., 0], pts[..., 1], 2)                # [b, 3, 6]
+    K = np.linalg.pinv(A)
+    return (K[:, 0, :], K[:, 1:3, :]) if grad else K[:, 0, :]
+
+
+def three_node_weights(pts, anchor, cap=0.0, grad=False):
     """Value weights of the graded 3 x 6 system (eq. 3nodes_intp) at the
     origin; ``pts`` [b, 3, 2], ``anchor`` local index of the side anchor.
 
     ``cap`` > 0 switches on a dropping rule for these systems (not in the
     paper, off by default): while a weight exceeds ``cap`` in magnitude the
-    smallest kept singular value is dropped, as the 5-node rule does."""
+    smallest kept singular value is dropped, as the 5-node rule does.  With
+    ``grad`` also the x- and y-derivative rows of the same operator at the
+    final rank [b, 2, 3] (the gradient of the fitted planar interpolant, or
+    of the 1D quadratic along collinear nodes), the anchor absorbing minus
+    their sums."""
     pts = np.asarray(pts, dtype=np.float64)
     A = basis.p(pts[..., 0], pts[..., 1], 2)                # [b, 3, 6]
     U, s, V = svd_full(A)
@@ -138,13 +211,20 @@ def three_node_weights(pts, anchor, cap=0.0):
             wi = graded_rows(U[idx], s[idx], V[idx], int(rv), top, [0])[:, 0, :]
             w[idx] = wi
             if cap > 0.0:
-                drop = (np.max(np.abs(wi), axis=1) > cap) & (rv > 1)
+                big = (np.max(np.abs(wi), axis=1) > cap) & (rv > 1)
             else:
-                drop = np.zeros(idx.size, dtype=bool)
-            r[idx[drop]] -= 1
-            todo[idx[~drop]] = False
+                big = np.zeros(idx.size, dtype=bool)
+            r[idx[big]] -= 1
+            todo[idx[~big]] = False
     w[:, anchor] += 1.0 - w.sum(axis=1)
-    return w
+    if not grad:
+        return w
+    g = np.empty((w.shape[0], 2, 3))
+    for rv in np.unique(r):
+        idx = np.nonzero(r == rv)[0]
+        g[idx] = graded_rows(U[idx], s[idx], V[idx], int(rv), top, [1, 2])
+    g[:, :, anchor] -= g.sum(axis=2)
+    return w, g
 
 
 def divergence_rows(node_pts, mid_pts, normals, h, deg=5):
@@ -197,14 +277,24 @@ class EdgeWeights:
     w5: np.ndarray        # [Ea, 2, 15] physical units: (value, d/dx, d/dy) per node
     w3: np.ndarray        # [Ea, 2, 3, 3] value weights per side and substencil
     rank: np.ndarray      # [Ea, 2]
+    # midpoint derivatives, physical units: d/dx and d/dy rows of the 5-node
+    # operator [Ea, 2 sides, 2, 15] and of each 3-node one [Ea, 2, 3 subs, 2, 3]
+    w5g: np.ndarray = None
+    w3g: np.ndarray = None
 
 
 # node order of each side within the six-node stencil (i-2 .. i+3)
 SIDE_NODES = ((0, 1, 2, 3, 4), (5, 4, 3, 2, 1))
 
 
-def edge_weights(topo, xy, period, edges=None, w3_cap=0.0):
-    """Weights of the given (active) edges, both sides."""
+def edge_weights(topo, xy, period, edges=None, w3_cap=0.0, reading="graded",
+                 drop="value"):
+    """Weights of the given (active) edges, both sides.  ``reading``:
+    "graded" (edge frame, graded pseudo-inverse, fold) or "physical" (the
+    literal reading, see the module header); ``drop``: entries the 5-node
+    dropping rule tests in the graded reading ("value" or "all")."""
+    if reading not in ("graded", "physical") or drop not in ("value", "all"):
+        raise ValueError((reading, drop))
     if edges is None:
         edges = np.nonzero(topo.active)[0]
     edges = np.asarray(edges)
@@ -222,17 +312,32 @@ def edge_weights(topo, xy, period, edges=None, w3_cap=0.0):
     w5 = np.empty((Ea, 2, 15))
     rank = np.empty((Ea, 2), dtype=np.int64)
     w3 = np.empty((Ea, 2, 3, 3))
+    w5g = np.empty((Ea, 2, 2, 15))
+    w3g = np.empty((Ea, 2, 3, 2, 3))
     for s_, nodes in enumerate(SIDE_NODES):
         pts = P[:, list(nodes), :]
-        w, r = hermite_weights(pts)
+        if reading == "physical":
+            phys = pts * h[:, None, None]
+            w, r, g = hermite_weights_physical(phys, grad=True)
+            w5[:, s_], w5g[:, s_] = w, g
+            rank[:, s_] = r
+            for j in range(3):
+                w3[:, s_, j], w3g[:, s_, j] = three_node_weights_physical(
+                    phys[:, j:j + 3, :], grad=True)
+            continue
+        w, r, g = hermite_weights(pts, drop=drop, grad=True)
+        # edge frame -> physical units: data (c, h c_x, h c_y), d/dx = d/dx_hat / h
         w[:, 1::3] *= h[:, None]
         w[:, 2::3] *= h[:, None]
-        w5[:, s_] = w
+        g[:, :, 0::3] /= h[:, None, None]
+        w5[:, s_], w5g[:, s_] = w, g
         rank[:, s_] = r
         for j in range(3):
-            w3[:, s_, j] = three_node_weights(pts[:, j:j + 3, :], anchor=2 - j,
-                                              cap=w3_cap)
-    return EdgeWeights(edges=edges, n=n, h=h, w5=w5, w3=w3, rank=rank)
+            w3[:, s_, j], g3 = three_node_weights(pts[:, j:j + 3, :], anchor=2 - j,
+                                                  cap=w3_cap, grad=True)
+            w3g[:, s_, j] = g3 / h[:, None, None]
+    return EdgeWeights(edges=edges, n=n, h=h, w5=w5, w3=w3, rank=rank, w5g=w5g,
+                       w3g=w3g)
 
 
 @dataclasses.dataclass

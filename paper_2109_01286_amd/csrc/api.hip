@@ -8,6 +8,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hfd.h"
@@ -41,6 +42,8 @@ struct hfd_ctx {
   // float64 coefficients
   int32_t* stg = nullptr;
   double *n = nullptr, *w5 = nullptr, *w3 = nullptr;
+  double *w5g = nullptr, *w3g = nullptr;  // midpoint-derivative rows (edge_grad)
+  uint8_t* gmask = nullptr;               // branch mask for them when none is asked
   int32_t* rank = nullptr;
   int8_t* trunc3 = nullptr;
   int32_t *vptr = nullptr, *eptr = nullptr, *vg = nullptr, *ve = nullptr;
@@ -477,13 +480,18 @@ hfd_status residual_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& e
 
 template <class T>
 hfd_status edge_states_t(hfd_ctx* c, hfd_ctx::Bufs<T>& B, const hfd::EdgeCoef<T>& ec,
-                         bool mx, const double* U, double* wlr, uint8_t* mask, double* hout,
-                         hipStream_t st) {
+                         bool mx, const double* U, double* wlr, double* grad, uint8_t* mask,
+                         double* hout, hipStream_t st) {
   const hfd::HostSetup& h = c->hs;
   const GasParams gp = gas_params(c, mx);
+  // the derivatives take the branches the edge pass records
+  uint8_t* m = mask ? mask : (grad ? c->gmask : nullptr);
   HIPCHK(c, hfd::launch_to_gather<T>(h.nv, U, gp, B.Gv[0], B.Gg[0], st));
   HIPCHK(c, hfd::launch_edge<T>(h.ne, ec, gp, B.Gv[0], B.Gg[0], c->force, B.H, hout, wlr,
-                                mask, st));
+                                m, st));
+  if (grad)
+    HIPCHK(c, hfd::launch_edge_grad<T>(h.ne, ec, c->w5g, c->w3g, gp, B.Gv[0], B.Gg[0], m, grad,
+                                       st));
   return HFD_OK;
 }
 
@@ -756,7 +764,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   if (!(op.gamma > 1.0) || op.mu < 0.0 || !(op.weno_eps > 0.0) || op.w3_cap < 0.0 ||
       op.switch_mode < 0 || op.switch_mode > 2 || op.precision < 0 || op.precision > 1 ||
       op.flux < HFD_FLUX_RUSANOV || op.flux > HFD_FLUX_HLLC || op.order < HFD_ORDER_NONE ||
-      op.order > HFD_ORDER_RCM ||
+      op.order > HFD_ORDER_RCM || op.edge_grad < 0 || op.edge_grad > 1 ||
       op.period[0] < 0.0 || op.period[1] < 0.0 ||
       (op.mu > 0.0 && (!(op.prandtl > 0.0) || !(op.gas_R > 0.0)))) {
     c->err = "invalid options";
@@ -862,6 +870,9 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
       (s = dalloc(c, &c->flag, 1)))
     return bail(s);
   if (op.mu > 0.0 && (s = dalloc(c, &c->dvis, 5 * nvs))) return bail(s);
+  if (op.edge_grad && ((s = dalloc(c, &c->w5g, 60 * ne)) || (s = dalloc(c, &c->w3g, 36 * ne)) ||
+                       (s = dalloc(c, &c->gmask, ne))))
+    return bail(s);
   c->ndtpart = std::max<int64_t>(1, std::min<int64_t>(1024, (no + 255) / 256));
   if ((s = dalloc(c, &c->dtpart, c->ndtpart))) return bail(s);
   if (hipMemset(c->flag, 0, sizeof(int32_t)) != hipSuccess) {
@@ -873,7 +884,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   // ---- precompute ----------------------------------------------------------
   hipError_t he;
   if ((he = hfd::launch_edge_weights(ne, d_pts, d_eh, op.w3_cap, c->w5, c->w3, c->rank,
-                                     c->trunc3, nullptr)) != hipSuccess ||
+                                     c->trunc3, c->w5g, c->w3g, nullptr)) != hipSuccess ||
       (he = hfd::launch_div_rows(no, int(msys), d_vptr64, d_eptr64, d_vpts, d_mpts, c->ve, c->n,
                                  ne, d_vh, c->dv, c->de, d_status, nullptr)) != hipSuccess ||
       (he = hipDeviceSynchronize()) != hipSuccess) {
@@ -1013,6 +1024,43 @@ hfd_status hfd_import_weights(hfd_ctx* c, const double* w5, const double* w3,
   return HFD_OK;
 }
 
+hfd_status hfd_export_grad_weights(const hfd_ctx* ctx, double* w5g, double* w3g) {
+  hfd_status s = need_device(ctx);
+  if (s) return s;
+  hfd_ctx* c = const_cast<hfd_ctx*>(ctx);
+  if (!c->w5g) return fail(c, HFD_E_STATE, "context created without hfd_opts.edge_grad");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  const int64_t ne = c->hs.ne;
+  for (auto [d, rows, out] : {std::tuple<const double*, int64_t, double*>{c->w5g, 60, w5g},
+                              std::tuple<const double*, int64_t, double*>{c->w3g, 36, w3g}}) {
+    if (!out) continue;
+    std::vector<double> tmp(rows * ne);
+    HIPCHK(c, hipMemcpy(tmp.data(), d, tmp.size() * 8, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < ne; ++e)
+      for (int64_t r = 0; r < rows; ++r) out[e * rows + r] = tmp[r * ne + e];
+  }
+  return HFD_OK;
+}
+
+hfd_status hfd_import_grad_weights(hfd_ctx* c, const double* w5g, const double* w3g) {
+  hfd_status s = need_device(c);
+  if (s) return s;
+  if (!c->w5g) return fail(c, HFD_E_STATE, "context created without hfd_opts.edge_grad");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  const int64_t ne = c->hs.ne;
+  for (auto [in, rows, d] : {std::tuple<const double*, int64_t, double*>{w5g, 60, c->w5g},
+                             std::tuple<const double*, int64_t, double*>{w3g, 36, c->w3g}}) {
+    if (!in) continue;
+    std::vector<double> tmp(rows * ne);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int64_t r = 0; r < rows; ++r) tmp[r * ne + e] = in[e * rows + r];
+    HIPCHK(c, hipMemcpy(d, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
+  }
+  return HFD_OK;
+}
+
 hfd_status hfd_set_precision(hfd_ctx* c, int32_t precision, const double* w_ref) {
   hfd_status s = need_device(c);
   if (s) return s;
@@ -1101,14 +1149,18 @@ hfd_status hfd_stable_dt_noalloc(hfd_ctx* c, const double* U, double cfl, double
   return HFD_OK;
 }
 
-hfd_status hfd_edge_states(hfd_ctx* c, const double* U, double* wlr, uint8_t* mask,
-                           double* hout, void* stream) {
+hfd_status hfd_edge_states(hfd_ctx* c, const double* U, double* wlr, double* grad,
+                           uint8_t* mask, double* hout, void* stream) {
   hfd_status s = need_device(c);
   if (s) return s;
   if (!U || !wlr) return fail(c, HFD_E_INVAL, "null state or output");
+  if (grad && !c->w5g)
+    return fail(c, HFD_E_STATE,
+                "midpoint derivatives need a context created with hfd_opts.edge_grad = 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (mixed(c)) return edge_states_t<float>(c, c->b32, ecoef32(c), true, U, wlr, mask, hout, st);
-  return edge_states_t<double>(c, c->b64, ecoef64(c), false, U, wlr, mask, hout, st);
+  if (mixed(c))
+    return edge_states_t<float>(c, c->b32, ecoef32(c), true, U, wlr, grad, mask, hout, st);
+  return edge_states_t<double>(c, c->b64, ecoef64(c), false, U, wlr, grad, mask, hout, st);
 }
 
 hfd_status hfd_force_switch_mask(hfd_ctx* c, const uint8_t* mask_dev) {

@@ -45,9 +45,11 @@ __device__ inline void reduce_stage(T* a, int sub) {
 }
 
 // ---- geometric precompute (float64) ----------------------------------------
+// w5g, w3g: null, or the midpoint-derivative rows [2][2][15][ne], [2][3][2][3][ne]
 hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
                                double w3_cap, double* w5, double* w3,
-                               int32_t* rank, int8_t* trunc3, hipStream_t st);
+                               int32_t* rank, int8_t* trunc3, double* w5g, double* w3g,
+                               hipStream_t st);
 // msys: the largest system's row count over the owned vertices (1..192)
 hipError_t launch_div_rows(int64_t nowned, int msys, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
@@ -122,6 +124,14 @@ hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
                        const V4<T>* Gv, const V4<T>* Gg, const uint8_t* force, V4<T>* H,
                        double* hsoa, double* wlr, uint8_t* mask, hipStream_t st);
 
+// Midpoint derivatives of both sides of every edge, grad[16][ne] float64
+// (row 8 side + 4 d + q: d/dx (d = 0) or d/dy of component q), with the
+// branches recorded in mask (written by launch_edge before).
+template <class T>
+hipError_t launch_edge_grad(int64_t ne, const EdgeCoef<T>& c, const double* w5g,
+                            const double* w3g, const GasParams& gp, const V4<T>* Gv,
+                            const V4<T>* Gg, const uint8_t* mask, double* grad,
+                            hipStream_t st);
 // Vertex pass.  mode 0: dU = R (float64 rows [12][nv], owned vertices);
 // mode 1: Unew = a*Un + b*(Uk + dt*R) in float64 (dt from dt_dev when
 // non-null), plus the gather-layout copy of Unew when Gv_new is non-null.

@@ -348,6 +348,82 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, s == 0, s == 1);
 }
 
+// Midpoint derivatives of the two interface states (hfd_edge_states only, not
+// on the residual's path).  Two lanes per edge, lane s takes side s.  Per
+// characteristic component, the branch recorded in the mask: the 5-node
+// derivative rows applied to the side's physical data and projected (L_q G,
+// the rows being the same for the four components), or the omega-weighted
+// derivative rows of the three 3-node interpolants applied to the projected
+// values; then back-projected with R.  The rows are float64 and annihilate
+// constants, so the mixed form's perturbation data give the same sums.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
+            const double* __restrict__ w3g, GasParams gp, const V4<T>* __restrict__ Gv,
+            const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ mask,
+            double* __restrict__ grad) {
+  const int64_t e = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / 2;
+  const int s = int(threadIdx.x & 1);
+  if (e >= ne) return;
+  const Ref<T> ref = make_ref<T>(gp);
+  const T gm1 = T(gp.gamma - 1.0);
+  const T nx = c.n[e], ny = c.n[ne + e];
+  const Frame<T> F = roe_frame<T>(Gv[c.stg[2 * ne + e]], Gv[c.stg[3 * ne + e]], nx, ny, ref, gm1);
+  const uint8_t fm = mask[e];
+  T cv[4][5], G[2][4];
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) G[d][q] = T(0);
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const int64_t id = c.stg[int64_t(s == 0 ? j : 5 - j) * ne + e];
+    const V4<T> a = Gv[id], bx = Gg[2 * id], by = Gg[2 * id + 1];
+    const T w[4] = {a.x, a.y, a.z, a.w};
+    const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
+    const T wy[4] = {by.x, by.y, by.z, by.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      cv[q][j] = F.L[q][0] * w[0] + F.L[q][1] * w[1] + F.L[q][2] * w[2] + F.L[q][3] * w[3];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const double* r = w5g + int64_t((s * 2 + d) * 15 + 3 * j) * ne + e;
+      const T gv = T(r[0]), gx = T(r[ne]), gy = T(r[2 * ne]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) G[d][q] += gv * w[q] + gx * wx[q] + gy * wy[q];
+    }
+  }
+  T gc[2][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T o[3];
+    const bool weno = comp_switch<T>(cv[q], gp, s, q, true, fm, o);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      if (weno) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double* r = w3g + int64_t(((s * 3 + k) * 2 + d) * 3) * ne + e;
+          acc += o[k] * (T(r[0]) * cv[q][k] + T(r[ne]) * cv[q][k + 1] +
+                         T(r[2 * ne]) * cv[q][k + 2]);
+        }
+        gc[d][q] = acc;
+      } else {
+        gc[d][q] = F.L[q][0] * G[d][0] + F.L[q][1] * G[d][1] + F.L[q][2] * G[d][2] +
+                   F.L[q][3] * G[d][3];
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    T out[4];
+    back_project<T>(F, gc[d], out);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) grad[int64_t(8 * s + 4 * d + q) * ne + e] = double(out[q]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Vertex pass
 // ---------------------------------------------------------------------------
@@ -794,6 +870,25 @@ template hipError_t launch_edge<double>(int64_t, const EdgeCoef<double>&, const 
 template hipError_t launch_edge<float>(int64_t, const EdgeCoef<float>&, const GasParams&,
                                        const V4<float>*, const V4<float>*, const uint8_t*,
                                        V4<float>*, double*, double*, uint8_t*, hipStream_t);
+
+template <class T>
+hipError_t launch_edge_grad(int64_t ne, const EdgeCoef<T>& c, const double* w5g,
+                            const double* w3g, const GasParams& gp, const V4<T>* Gv,
+                            const V4<T>* Gg, const uint8_t* mask, double* grad,
+                            hipStream_t st) {
+  if (ne == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_grad<T>, dim3(nblocks(2 * ne, 256)), dim3(256), 0, st, ne, c, w5g,
+                     w3g, gp, Gv, Gg, mask, grad);
+  return hipGetLastError();
+}
+template hipError_t launch_edge_grad<double>(int64_t, const EdgeCoef<double>&, const double*,
+                                             const double*, const GasParams&,
+                                             const V4<double>*, const V4<double>*,
+                                             const uint8_t*, double*, hipStream_t);
+template hipError_t launch_edge_grad<float>(int64_t, const EdgeCoef<float>&, const double*,
+                                            const double*, const GasParams&, const V4<float>*,
+                                            const V4<float>*, const uint8_t*, double*,
+                                            hipStream_t);
 
 template <class T>
 hipError_t launch_vertex(int64_t nowned, int64_t nv, const VertexCoef<T>& c,

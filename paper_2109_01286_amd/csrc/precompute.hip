@@ -12,6 +12,8 @@
 //    1 - sum(value weights).
 //  * 3-node rows (eq. 3nodes_intp): the same on the 3 x 6 degree-2 system,
 //    graded on the degree-2 block; optional dropping above a cap.
+//  * On request, the midpoint derivatives: rows 2 and 3 (d/dx, d/dy) of the
+//    same 5-node and 3-node operators at the final rank.
 //  * Divergence rows (eq. flux_polynomials, rows d0, dx, dy): full-rank
 //    least squares of degree 5 solved by Householder QR; a pseudo-inverse row
 //    is Q [R^-T e; 0].  A rank-deficient system is reported as a mesh error.
@@ -263,6 +265,7 @@ struct EdgeLds {
   double Bt[5 * EG];
   double W[5 * EG];
   double out[EG];
+  double outg[2 * EG];
   double sig[16];
   double sb[8];
   int perm[16];
@@ -273,7 +276,8 @@ __global__ void __launch_bounds__(64)
 k_edge_weights(int64_t ne, const double* __restrict__ pts,
                const double* __restrict__ eh, double w3_cap,
                double* __restrict__ w5, double* __restrict__ w3,
-               int32_t* __restrict__ rank, int8_t* __restrict__ trunc3) {
+               int32_t* __restrict__ rank, int8_t* __restrict__ trunc3,
+               double* __restrict__ w5g, double* __restrict__ w3g) {
   __shared__ EdgeLds lds_all[4];
   const int grp = threadIdx.x / EG, lane = threadIdx.x % EG;
   const int64_t item = int64_t(blockIdx.x) * 4 + grp;
@@ -323,6 +327,24 @@ k_edge_weights(int64_t ne, const double* __restrict__ pts,
       w5[int64_t(side * 15 + lane) * ne + e] = w;
     }
     if (lane == 0) rank[int64_t(side) * ne + e] = r;
+    // midpoint derivatives: rows 2 and 3 of the same operator at the final
+    // rank; the anchor absorbs minus their value-weight sums (a constant has
+    // zero gradient); value weights / h for physical units
+    if (w5g) {
+      const int grows[2] = {1, 2};
+      graded_rows<EG, 1>(L.A, L.V, L.sig, L.perm, 15, 15, r, top, 5, grows, 2, ws,
+                         L.outg, lane);
+      for (int d = 0; d < 2; ++d) {
+        double g = (lane < 15) ? L.outg[d * EG + lane] : 0.0;
+        const double sg = gsum<EG>((lane < 15 && lane % 3 == 0) ? g : 0.0);
+        if (lane == 6) g -= sg;
+        if (lane < 15) {
+          if (lane % 3 == 0) g /= eh[e];
+          w5g[int64_t((side * 2 + d) * 15 + lane) * ne + e] = g;
+        }
+      }
+      wave_sync();
+    }
   }
 
   // ---- 3-node substencils (eq. 3nodes_intp) -----------------------------------
@@ -358,6 +380,17 @@ k_edge_weights(int64_t ne, const double* __restrict__ pts,
     if (lane == 2 - j) w += 1.0 - sv;  // the side's anchor (node 2)
     if (lane < 3) w3[int64_t((side * 3 + j) * 3 + lane) * ne + e] = w;
     if (lane == 0) trunc3[int64_t(side * 3 + j) * ne + e] = int8_t(dropped);
+    if (w3g) {  // gradient of the interpolant at the midpoint, as for w5g
+      const int grows[2] = {1, 2};
+      graded_rows<EG, 1>(L.A, L.V, L.sig, L.perm, 3, 6, r, top, 3, grows, 2, ws, L.outg,
+                         lane);
+      for (int d = 0; d < 2; ++d) {
+        double g = (lane < 3) ? L.outg[d * EG + lane] : 0.0;
+        const double sg = gsum<EG>(g);
+        if (lane == 2 - j) g -= sg;
+        if (lane < 3) w3g[int64_t(((side * 3 + j) * 2 + d) * 3 + lane) * ne + e] = g / eh[e];
+      }
+    }
     wave_sync();
   }
 }
@@ -565,11 +598,12 @@ k_visc_rows(int64_t nowned, const int64_t* __restrict__ vptr,
 
 hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
                                double w3_cap, double* w5, double* w3,
-                               int32_t* rank, int8_t* trunc3, hipStream_t st) {
+                               int32_t* rank, int8_t* trunc3, double* w5g, double* w3g,
+                               hipStream_t st) {
   if (ne == 0) return hipSuccess;
   int64_t blocks = (2 * ne + 3) / 4;
   hipLaunchKernelGGL(k_edge_weights, dim3(unsigned(blocks)), dim3(64), 0, st, ne,
-                     pts, eh, w3_cap, w5, w3, rank, trunc3);
+                     pts, eh, w3_cap, w5, w3, rank, trunc3, w5g, w3g);
   return hipGetLastError();
 }
 

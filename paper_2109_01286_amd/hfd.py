@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("period", ctypes.c_double * 2), ("w_ref", ctypes.c_double * 4),
                 ("switch_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("flux", ctypes.c_int32),
-                ("stage_off", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("stage_off", ctypes.c_int32), ("edge_grad", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Info(ctypes.Structure):
@@ -90,7 +91,9 @@ SIGNATURES = {
     "hfd_rk_steps": (ctypes.c_int, [_P, _P, _I64, _D, _P, _P]),
     "hfd_stable_dt": (ctypes.c_int, [_P, _P, _D, _P, _P]),
     "hfd_stable_dt_noalloc": (ctypes.c_int, [_P, _P, _D, _P, _P]),
-    "hfd_edge_states": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "hfd_edge_states": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "hfd_export_grad_weights": (ctypes.c_int, [_P, _P, _P]),
+    "hfd_import_grad_weights": (ctypes.c_int, [_P, _P, _P]),
     "hfd_force_switch_mask": (ctypes.c_int, [_P, _P]),
     "hfd_fill_ghosts": (ctypes.c_int, [_P, _P, _P]),
     "hfd_check": (ctypes.c_int, [_P, _P]),
@@ -299,6 +302,21 @@ class Solver:
         self._chk(lib().hfd_import_weights(self._h, _ptr(w5), _ptr(w3), _ptr(dv),
                                            _ptr(de), _ptr(dvis)))
 
+    def export_grad_weights(self):
+        ne = self.ne
+        w5g = np.empty((ne, 2, 2, 15))
+        w3g = np.empty((ne, 2, 3, 2, 3))
+        self._chk(lib().hfd_export_grad_weights(self._h, _ptr(w5g), _ptr(w3g)))
+        return dict(w5g=w5g, w3g=w3g)
+
+    def import_grad_weights(self, w5g=None, w3g=None):
+        c = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        w5g, w3g = c(w5g), c(w3g)
+        for a, shp in ((w5g, (self.ne, 2, 2, 15)), (w3g, (self.ne, 2, 3, 2, 3))):
+            if a is not None and a.shape != shp:
+                raise ValueError(f"shape {a.shape}, expected {shp}")
+        self._chk(lib().hfd_import_grad_weights(self._h, _ptr(w5g), _ptr(w3g)))
+
     def set_precision(self, precision, w_ref=None):
         p = {"fp64": 0, "fp32": 1}[precision] if isinstance(precision, str) else precision
         wr = None if w_ref is None else np.ascontiguousarray(w_ref, dtype=np.float64)
@@ -365,15 +383,18 @@ class Solver:
                                               self._dev(out, "out", min_numel=1), _stream()))
         return out
 
-    def edge_states(self, U, want_mask=True, want_flux=True):
+    def edge_states(self, U, want_mask=True, want_flux=True, want_grad=False):
+        """(wlr [8, ne], mask [ne] or None, h [4, ne] or None), and with
+        ``want_grad`` also grad [16, ne] (needs ``edge_grad=1``)."""
         import torch
         pU = self._state(U)
         wlr = torch.empty(8, self.ne, dtype=torch.float64, device=U.device)
         mask = torch.empty(self.ne, dtype=torch.uint8, device=U.device) if want_mask else None
         h = torch.empty(4, self.ne, dtype=torch.float64, device=U.device) if want_flux else None
-        self._chk(lib().hfd_edge_states(self._h, pU, _dptr(wlr), _dptr(mask),
+        g = torch.empty(16, self.ne, dtype=torch.float64, device=U.device) if want_grad else None
+        self._chk(lib().hfd_edge_states(self._h, pU, _dptr(wlr), _dptr(g), _dptr(mask),
                                         _dptr(h), _stream()))
-        return wlr, mask, h
+        return (wlr, mask, h, g) if want_grad else (wlr, mask, h)
 
     def force_switch_mask(self, mask):
         """Force the Hermite/WENO branch per edge (uint8 device tensor [ne])
