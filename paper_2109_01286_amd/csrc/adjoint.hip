@@ -236,7 +236,6 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   int id[5];
   for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
   const T eps = gp.eps;
-  const T dw[3] = {T(1.0) / T(16.0), T(10.0) / T(16.0), T(5.0) / T(16.0)};
   const uint8_t fm = force ? force[e] : uint8_t(0);
   // The float32 form stores the perturbation w - w_ref of the values (the
   // gradients unchanged); the reverse works on the full state.
@@ -313,20 +312,9 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       cq[t] = L[q][0] * W[t][0] + L[q][1] * W[t][1] + L[q][2] * W[t][2] + L[q][3] * W[t][3];
   };
   // smoothness indicators, WENO weights and 3-node values of component q
-  auto weno_parts = [&](const T w3[9], const T cq[5], T be[3], T al[3],
-                        T& sal, T om[3], T Sk[3]) {
-    const T t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
-    const T t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
-    const T t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
-    be[0] = T(13.0) / T(12.0) * t1 * t1 + T(0.25) * t2 * t2;
-    be[1] = T(13.0) / T(12.0) * t3 * t3 + T(0.25) * t4 * t4;
-    be[2] = T(13.0) / T(12.0) * t5 * t5 + T(0.25) * t6 * t6;
-    sal = T(0.0);
-    for (int k = 0; k < 3; ++k) {
-      al[k] = dw[k] / ((eps + be[k]) * (eps + be[k]));
-      sal += al[k];
-    }
-    for (int k = 0; k < 3; ++k) om[k] = al[k] / sal;
+  // the forward passes' weights (shared code: the same decisions)
+  auto weno_parts = [&](const T w3[9], const T cq[5], T be[3], T om[3], T Sk[3]) {
+    weno_weights<T>(cq, eps, be, om);
     for (int k = 0; k < 3; ++k) {
       T sk = T(0.0);
       for (int t = 0; t < 3; ++t) sk += w3[3 * k + t] * cq[k + t];
@@ -351,9 +339,9 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       for (int q = 0; q < 4; ++q) hs[q] += w5[t][0] * W[t][q] + w5[t][1] * X[q] + w5[t][2] * Y[q];
     }
     for (int q = 0; q < 4; ++q) {
-      T cq[5], be[3], al[3], sal, om[3], Sk[3];
+      T cq[5], be[3], om[3], Sk[3];
       proj(L, W, q, cq);
-      weno_parts(w3, cq, be, al, sal, om, Sk);
+      weno_parts(w3, cq, be, om, Sk);
       bool wq;
       if (force) wq = (fm >> (4 * s + q)) & 1;
       else if (gp.sw == HFD_SWITCH_PAPER) wq = !(om[0] > T(gp.sw_lo) && om[0] < T(gp.sw_hi));
@@ -483,9 +471,9 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       foldL(q, z);
       continue;
     }
-    T cq[5], be[3], al[3], sal, om[3], Sk[3];
+    T cq[5], be[3], om[3], Sk[3];
     proj(L, W, q, cq);
-    weno_parts(w3, cq, be, al, sal, om, Sk);
+    weno_parts(w3, cq, be, om, Sk);
     T gcv[5] = {0, 0, 0, 0, 0}, gS[3], gom[3];
     for (int k = 0; k < 3; ++k) {
       gS[k] = gCq * om[k];
@@ -493,14 +481,14 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     }
     for (int k = 0; k < 3; ++k)
       for (int t = 0; t < 3; ++t) gcv[k + t] += gS[k] * w3[3 * k + t];
-    // omega = alpha / sum(alpha), alpha = d / (eps + beta)^2
+    // omega = alpha / sum(alpha), alpha = d / (eps + beta)^2: d omega_j /
+    // d alpha_k = (delta_jk - omega_j) / sum(alpha) and d alpha_k / d beta_k
+    // = -2 alpha_k / (eps + beta_k), so with alpha_k / sum(alpha) = omega_k
+    // the adjoint of beta_k is -2 (g_k - sum_j g_j omega_j) omega_k / (eps + beta_k)
     T dot = T(0.0);
     for (int k = 0; k < 3; ++k) dot += gom[k] * om[k];
     T gbe[3];
-    for (int k = 0; k < 3; ++k) {
-      const T gal = (gom[k] - dot) / sal;
-      gbe[k] = -T(2.0) * gal * al[k] / (eps + be[k]);
-    }
+    for (int k = 0; k < 3; ++k) gbe[k] = -T(2.0) * (gom[k] - dot) * om[k] / (eps + be[k]);
     const T t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
     const T t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
     const T t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];

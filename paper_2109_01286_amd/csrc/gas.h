@@ -34,6 +34,33 @@ __device__ inline float fsqrt<float>(float x) {
   return __builtin_amdgcn_sqrtf(x);
 }
 
+// Nonlinear weights of uniform WENO5 interpolation from the five projected
+// values c of one side (order c_{-2} .. c_2): Jiang-Shu smoothness indicators
+// beta, alpha_j = d_j / (eps + beta_j)^2 with d = (1/16, 10/16, 5/16), and
+// omega = alpha / sum(alpha).  With t_j = (eps + beta_j)^2 the weights are
+// omega_j = d_j t_k t_l / (d_1 t_2 t_3 + d_2 t_1 t_3 + d_3 t_1 t_2): the same
+// numbers with one reciprocal instead of six divisions (t >= eps^2, so the
+// products neither underflow nor, for any finite state of these problems,
+// overflow).  Shared by the edge passes and the adjoint, so that both take
+// the same decisions.
+template <class T>
+__device__ inline void weno_weights(const T c[5], T eps, T be[3], T o[3]) {
+  const T d1 = T(1.0 / 16.0), d2 = T(10.0 / 16.0), d3 = T(5.0 / 16.0);
+  const T t1 = c[0] - T(2) * c[1] + c[2], t2 = c[0] - T(4) * c[1] + T(3) * c[2];
+  const T t3 = c[1] - T(2) * c[2] + c[3], t4 = c[1] - c[3];
+  const T t5 = c[2] - T(2) * c[3] + c[4], t6 = T(3) * c[2] - T(4) * c[3] + c[4];
+  be[0] = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
+  be[1] = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
+  be[2] = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
+  const T q1 = (eps + be[0]) * (eps + be[0]), q2 = (eps + be[1]) * (eps + be[1]);
+  const T q3 = (eps + be[2]) * (eps + be[2]);
+  const T n1 = d1 * (q2 * q3), n2 = d2 * (q1 * q3), n3 = d3 * (q1 * q2);
+  const T r = fdiv(T(1), n1 + n2 + n3);
+  o[0] = n1 * r;
+  o[1] = n2 * r;
+  o[2] = n3 * r;
+}
+
 // Fluxes minus the reference fluxes, from the perturbation w' and the full
 // density/momenta.  With a zero reference these are the plain fluxes.
 template <class T>
@@ -104,8 +131,9 @@ template <class T>
 __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
                                      const Ref<T>& ref, T gm1) {
   const T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
-  const T ua = fdiv(ref.w[1] + A.y, ra), ub = fdiv(ref.w[1] + B.y, rb);
-  const T va = fdiv(ref.w[2] + A.z, ra), vb = fdiv(ref.w[2] + B.z, rb);
+  const T ira = fdiv(T(1), ra), irb = fdiv(T(1), rb);
+  const T ua = (ref.w[1] + A.y) * ira, ub = (ref.w[1] + B.y) * irb;
+  const T va = (ref.w[2] + A.z) * ira, vb = (ref.w[2] + B.z) * irb;
   const T Ea = ref.w[3] + A.w, Eb = ref.w[3] + B.w;
   const T pa = gm1 * (Ea - T(0.5) * ra * (ua * ua + va * va));
   const T pb = gm1 * (Eb - T(0.5) * rb * (ub * ub + vb * vb));
@@ -113,7 +141,7 @@ __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
   const T iw = fdiv(T(1), sa + sb);
   const T u = (sa * ua + sb * ub) * iw;
   const T v = (sa * va + sb * vb) * iw;
-  const T hh = (fdiv(sa * (Ea + pa), ra) + fdiv(sb * (Eb + pb), rb)) * iw;
+  const T hh = (sa * (Ea + pa) * ira + sb * (Eb + pb) * irb) * iw;
   const T cc = fsqrt(gm1 * (hh - T(0.5) * (u * u + v * v)));
   const T q2 = u * u + v * v;
   const T un = u * nx + v * ny, ut = -u * ny + v * nx;

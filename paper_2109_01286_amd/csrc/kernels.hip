@@ -82,21 +82,9 @@ __device__ inline int64_t xcd_block() {
 template <class T>
 __device__ inline bool comp_switch(const T c[5], const GasParams& gp, int s, int q,
                                    bool forced, uint8_t fm, T o[3]) {
-  const T eps = T(gp.eps), lo = T(gp.sw_lo), hi = T(gp.sw_hi);
-  const T d1 = T(1.0 / 16.0), d2 = T(10.0 / 16.0), d3 = T(5.0 / 16.0);
-  const T t1 = c[0] - T(2) * c[1] + c[2], t2 = c[0] - T(4) * c[1] + T(3) * c[2];
-  const T t3 = c[1] - T(2) * c[2] + c[3], t4 = c[1] - c[3];
-  const T t5 = c[2] - T(2) * c[3] + c[4], t6 = T(3) * c[2] - T(4) * c[3] + c[4];
-  const T be1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
-  const T be2 = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
-  const T be3 = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
-  const T a1 = fdiv(d1, (eps + be1) * (eps + be1));
-  const T a2 = fdiv(d2, (eps + be2) * (eps + be2));
-  const T a3 = fdiv(d3, (eps + be3) * (eps + be3));
-  const T sa = a1 + a2 + a3;
-  o[0] = fdiv(a1, sa);
-  o[1] = fdiv(a2, sa);
-  o[2] = fdiv(a3, sa);
+  const T lo = T(gp.sw_lo), hi = T(gp.sw_hi);
+  T be[3];
+  weno_weights<T>(c, T(gp.eps), be, o);
   if (forced) return (fm >> (4 * s + q)) & 1;
   if (gp.sw == HFD_SWITCH_PAPER) return !(o[0] > lo && o[0] < hi);
   return gp.sw == HFD_SWITCH_WENO_ONLY;
