@@ -114,8 +114,11 @@ def cancellation_scale(sc, U, switch):
     return out
 
 
-def residual_within(got, ref, scale, owned, rel=1e-12, abs_rel=1e-14):
-    """Per block (w, w_x, w_y): ||got - ref|| <= rel ||ref|| + abs_rel ||scale||."""
+def residual_within(got, ref, scale, owned, rel=1e-12, abs_rel=1e-14, elem=4.0):
+    """Per block (w, w_x, w_y): ||got - ref|| <= rel ||ref|| + abs_rel ||scale||
+    (L2 over the block), and element by element |got - ref| <= elem (rel
+    max|ref| + abs_rel scale), so that an error at a few vertices is not
+    diluted by the norm.  Returns the largest fraction of a bound used."""
     worst = 0.0
     for k in range(3):
         x = got[4 * k:4 * k + 4][:, owned]
@@ -125,5 +128,8 @@ def residual_within(got, ref, scale, owned, rel=1e-12, abs_rel=1e-14):
         tol = rel * np.linalg.norm(y[f]) + abs_rel * np.linalg.norm(s[f])
         q = np.linalg.norm((x - y)[f]) / tol
         assert np.isfinite(q)
-        worst = max(worst, q)
+        tol_e = elem * (rel * np.abs(y[f]).max() + abs_rel * s[f])
+        q_e = np.max(np.abs((x - y)[f]) / tol_e)
+        assert np.isfinite(q_e)
+        worst = max(worst, q, q_e)
     return worst
