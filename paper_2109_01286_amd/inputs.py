@@ -139,6 +139,81 @@ def jittered_grid(nx, ny, Lx, Ly, periodic=(True, True), ghost_layers=0,
                 shape=(nxv, nyv), h=(hx, hy), ij=np.stack([I, J], 1))
 
 
+def equilateral_grid(nx, ny, Lx, jitter=0.0, seed=0):
+    """Periodic lattice of equilateral triangles (every vertex of valence
+    six, the ideal of an isotropic Delaunay mesh): ``nx`` points per row at
+    spacing h = Lx/nx, ``ny`` rows (even) at spacing h sqrt(3)/2, odd rows
+    shifted by h/2; period (Lx, ny h sqrt(3)/2).  ``jitter`` moves every
+    vertex by U(-jitter h, jitter h) per direction
+    (``numpy.random.default_rng(seed)``)."""
+    if ny % 2:
+        raise ValueError("ny must be even for a periodic equilateral lattice")
+    h = Lx / nx
+    hy = h * math.sqrt(3.0) / 2.0
+    Ly = ny * hy
+    J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-jitter, jitter, size=(I.size, 2)) * h
+    xy = np.stack([np.mod((I + 0.5 * (J % 2)) * h + jit[:, 0], Lx),
+                   np.mod(J * hy + jit[:, 1], Ly)], 1)
+    vid = lambda i, j: (j % ny) * nx + (i % nx)
+    tri = []
+    for j in range(ny):
+        for i in range(nx):
+            if j % 2 == 0:
+                tri.append((vid(i, j), vid(i + 1, j), vid(i, j + 1)))
+                tri.append((vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)))
+            else:
+                tri.append((vid(i, j), vid(i + 1, j), vid(i + 1, j + 1)))
+                tri.append((vid(i, j), vid(i + 1, j + 1), vid(i, j + 1)))
+    return Mesh(xy=xy, tri=np.asarray(tri, dtype=np.int32),
+                ghost_src=np.full(I.size, -1, dtype=np.int32), period=(Lx, Ly),
+                shape=(nx, ny), h=(h, hy), ij=np.stack([I, J], 1))
+
+
+def embedded_circle_grid(n, L=2.0, center=(1.0, 1.0), radius=0.5, ghost_layers=5, seed=7,
+                         clearance=0.6):
+    """The jittered lattice G(n, n, L, L, non-periodic, ghost_layers, seed)
+    with a circle embedded in it (Section 3.3: the meshes of the circular Sod
+    problem carry the circle r = radius so that the initial discontinuity
+    lies on mesh edges).  Lattice vertices (owned, not on a boundary line)
+    closer than ``clearance`` h to the circle are removed, round(2 pi r / h)
+    vertices are placed on the circle at equal angles, and the whole point
+    set is triangulated by Delaunay (scipy.spatial).  The circle vertices
+    follow the lattice vertices; ``circle`` (returned with the mesh) lists
+    them in angular order.  Ghost vertices keep their sources."""
+    import scipy.spatial
+
+    base = jittered_grid(n, n, L, L, (False, False), ghost_layers, seed=seed)
+    h = base.h[0]
+    c = np.asarray(center, dtype=np.float64)
+    dist = np.abs(np.hypot(base.xy[:, 0] - c[0], base.xy[:, 1] - c[1]) - radius)
+    I, J = base.ij[:, 0], base.ij[:, 1]
+    interior = (base.ghost_src == -1) & (I > 0) & (I < n - 1) & (J > 0) & (J < n - 1)
+    keep = ~(interior & (dist < clearance * h))
+    old = np.nonzero(keep)[0]
+    new_of_old = -np.ones(base.nv, dtype=np.int64)
+    new_of_old[old] = np.arange(old.size)
+    nc = int(round(2.0 * math.pi * radius / h))
+    th = 2.0 * math.pi * np.arange(nc) / nc
+    circ = np.stack([c[0] + radius * np.cos(th), c[1] + radius * np.sin(th)], 1)
+    xy = np.concatenate([base.xy[old], circ])
+    gs = base.ghost_src[old].astype(np.int64)
+    gs = np.where(gs >= 0, new_of_old[np.maximum(gs, 0)], gs)
+    if np.any(gs[base.ghost_src[old] >= 0] < 0):
+        raise ValueError("a ghost source was removed")
+    ghost_src = np.concatenate([gs, np.full(nc, -1)]).astype(np.int32)
+    tri = scipy.spatial.Delaunay(xy).simplices.astype(np.int64)
+    a, b, cc = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    cross = (b[:, 0] - a[:, 0]) * (cc[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (cc[:, 0] - a[:, 0])
+    tri = np.where((cross < 0)[:, None], tri[:, [0, 2, 1]], tri).astype(np.int32)
+    ij = np.concatenate([base.ij[old], np.full((nc, 2), np.iinfo(np.int64).min)])
+    m = Mesh(xy=xy, tri=tri, ghost_src=ghost_src, period=(0.0, 0.0),
+             shape=base.shape, h=base.h, ij=ij)
+    return m, np.arange(old.size, old.size + nc)
+
+
 def shuffled(mesh: Mesh, seed=0):
     """Same mesh with vertices renumbered by a seeded random permutation.
 
@@ -294,11 +369,15 @@ def couette(mesh: Mesh, L=10.0, y0=5.0, u0=0.5, T_top=1.5, T_bottom=1.0, p=1.0,
 
 
 def circular_sod(mesh: Mesh, center=(1.0, 1.0), radius=0.5, gamma=1.4,
-                 inner=(1.0, 0.0, 0.0, 1.0), outer=(0.125, 0.0, 0.0, 0.1)):
+                 inner=(1.0, 0.0, 0.0, 1.0), outer=(0.125, 0.0, 0.0, 0.1), on_circle=None):
     """Circular Sod problem (Section 3.3): (rho, u, v, p) = ``inner`` for
-    |x - c| < r, ``outer`` elsewhere, zero gradients."""
+    |x - c| < r, ``outer`` elsewhere, zero gradients.  ``on_circle``: ids of
+    vertices placed on the circle itself, which take the outer state (the
+    strict inequality) whatever their rounded distance."""
     d = mesh.xy - np.asarray(center)[None, :]
     inside = (d * d).sum(axis=1) < radius * radius
+    if on_circle is not None:
+        inside[np.asarray(on_circle)] = False
     S = np.where(inside[:, None], np.asarray(inner)[None, :], np.asarray(outer)[None, :])
     z = np.zeros(mesh.nv)
     return prim_to_state(gamma, S[:, 0], S[:, 1], S[:, 2], S[:, 3], (z, z), (z, z), (z, z),
@@ -414,10 +493,11 @@ def workload(name, scale=None):
         prm = dict(gamma=gamma, mu=mu, prandtl=mu * cp / K, gas_R=cp * (gamma - 1.0) / gamma,
                    switch="smooth", cfl=0.3, steps=20)
     elif name == "sod_circle":
-        # the 2 x 2 square of the paper's circular Sod problem, transmissive
+        # the 2 x 2 square of the paper's circular Sod problem with the circle
+        # r = 0.5 embedded in the mesh, transmissive
         n = scale or 101
-        m = jittered_grid(n, n, 2.0, 2.0, (False, False), 5, seed=7)
-        U = circular_sod(m)
+        m, circle = embedded_circle_grid(n, 2.0, (1.0, 1.0), 0.5, 5, seed=7)
+        U = circular_sod(m, on_circle=circle)
         prm = dict(gamma=1.4, mu=0.0, switch="paper", cfl=0.3, steps=40, t_end=0.2)
     else:
         raise KeyError(name)

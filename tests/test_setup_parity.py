@@ -11,7 +11,9 @@ from ._helpers import edge_map, lib_solver
 
 CASES = [("vortex21", None, {}), ("riemann201", 31, {}), ("shockvortex2049", 25, {}),
          ("tgv513", 33, {}), ("vortex257", 33, {"order": "none"}),
-         ("riemann201", 31, {"order": "rcm"}), ("vortex21", None, {"order": "rcm"})]
+         ("riemann201", 31, {"order": "rcm"}), ("vortex21", None, {"order": "rcm"}),
+         # the Delaunay mesh with the embedded circle of the circular Sod case
+         ("sod_circle", 31, {})]
 
 
 @pytest.mark.parametrize("name,scale,opts", CASES)
@@ -85,3 +87,39 @@ def test_sizes_match_the_lattice_recipe():
     S = lib_solver(m, -1)
     assert S.info["n_owned"] == 40401 and S.info["nv"] == 44521
     assert S.info["n_edges_mesh"] == 132720
+
+
+def test_embedded_circle_mesh():
+    """The circular Sod meshes (Section 3.3) carry the circle r = 0.5: every
+    chord between consecutive circle vertices is a mesh edge, the circle
+    vertices take the outer state and every other vertex the state its
+    distance gives, and the triangles around owned vertices are not
+    degenerate (smallest angle above 20 degrees)."""
+    for n in (25, 51):
+        m, circle = inputs.embedded_circle_grid(n)
+        edges = set()
+        for t in m.tri:
+            for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
+                edges.add((min(a, b), max(a, b)))
+        nc = circle.size
+        assert nc == round(np.pi / m.h[0])
+        r = np.hypot(m.xy[circle, 0] - 1.0, m.xy[circle, 1] - 1.0)
+        assert np.allclose(r, 0.5, atol=1e-15)
+        for k in range(nc):
+            a, b = circle[k], circle[(k + 1) % nc]
+            assert (min(a, b), max(a, b)) in edges
+        U = inputs.circular_sod(m, on_circle=circle)
+        assert np.all(U[0, circle] == 0.125)
+        d = np.hypot(m.xy[:, 0] - 1.0, m.xy[:, 1] - 1.0)
+        other = np.ones(m.nv, bool)
+        other[circle] = False
+        assert np.all(U[0, other & (d < 0.5)] == 1.0) and np.all(U[0, other & (d > 0.5)] == 0.125)
+        x = m.xy[m.tri]
+        ang = []
+        for i in range(3):
+            u = x[:, (i + 1) % 3] - x[:, i]
+            v = x[:, (i + 2) % 3] - x[:, i]
+            ang.append(np.degrees(np.arccos(np.clip(
+                (u * v).sum(1) / np.linalg.norm(u, axis=1) / np.linalg.norm(v, axis=1), -1, 1))))
+        near = (m.ghost_src[m.tri] == -1).any(1)
+        assert np.min(np.minimum.reduce(ang)[near]) > 20.0
