@@ -98,7 +98,9 @@ typedef struct hfd_opts {
   int32_t edge_grad;   /* 1: also compute and keep (float64, 96 doubles per
                           edge) the midpoint-derivative rows that
                           hfd_edge_states needs for its grad output; 0: no */
-  int32_t reserved[2];
+  int32_t deg_inv;     /* degree of the inviscid divergence fit of
+                          eq. flux_polynomials: 4 or 5                     */
+  int32_t reserved[1];
 } hfd_opts;
 
 typedef struct hfd_info {

@@ -23,6 +23,11 @@
 
 using hfd::GasParams;
 
+// Degree of the inviscid divergence fit when the caller does not choose one.
+#ifndef HFD_DEFAULT_DEG_INV
+#define HFD_DEFAULT_DEG_INV 5
+#endif
+
 // Scratch of hfd_stable_dt_noalloc: the per-block partial minima of the time
 // step (one per 256 owned vertices).  A file-scope device array: every GPU
 // the library runs on holds its own copy until the process ends.  Host code
@@ -712,6 +717,7 @@ void hfd_default_opts(hfd_opts* o) {
   o->switch_mode = HFD_SWITCH_PAPER;
   o->precision = HFD_FP64;
   o->order = HFD_ORDER_HILBERT;
+  o->deg_inv = HFD_DEFAULT_DEG_INV;
 }
 
 const char* hfd_status_string(hfd_status s) {
@@ -765,6 +771,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
       op.switch_mode < 0 || op.switch_mode > 2 || op.precision < 0 || op.precision > 1 ||
       op.flux < HFD_FLUX_RUSANOV || op.flux > HFD_FLUX_HLLC || op.order < HFD_ORDER_NONE ||
       op.order > HFD_ORDER_RCM || op.edge_grad < 0 || op.edge_grad > 1 ||
+      (op.deg_inv != 4 && op.deg_inv != 5) ||
       op.period[0] < 0.0 || op.period[1] < 0.0 ||
       (op.mu > 0.0 && (!(op.prandtl > 0.0) || !(op.gas_R > 0.0)))) {
     c->err = "invalid options";
@@ -885,7 +892,7 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
   hipError_t he;
   if ((he = hfd::launch_edge_weights(ne, d_pts, d_eh, op.w3_cap, c->w5, c->w3, c->rank,
                                      c->trunc3, c->w5g, c->w3g, nullptr)) != hipSuccess ||
-      (he = hfd::launch_div_rows(no, int(msys), d_vptr64, d_eptr64, d_vpts, d_mpts, c->ve, c->n,
+      (he = hfd::launch_div_rows(no, int(msys), op.deg_inv, d_vptr64, d_eptr64, d_vpts, d_mpts, c->ve, c->n,
                                  ne, d_vh, c->dv, c->de, d_status, nullptr)) != hipSuccess ||
       (he = hipDeviceSynchronize()) != hipSuccess) {
     c->err = std::string("precompute: ") + hipGetErrorString(he);

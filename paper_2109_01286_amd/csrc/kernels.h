@@ -50,8 +50,9 @@ hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
                                double w3_cap, double* w5, double* w3,
                                int32_t* rank, int8_t* trunc3, double* w5g, double* w3g,
                                hipStream_t st);
-// msys: the largest system's row count over the owned vertices (1..192)
-hipError_t launch_div_rows(int64_t nowned, int msys, const int64_t* vptr,
+// msys: the largest system's row count over the owned vertices (1..192);
+// deg: degree of the fit (4 or 5)
+hipError_t launch_div_rows(int64_t nowned, int msys, int deg, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
                            const double* mpts, const int32_t* sedge,
                            const double* en, int64_t ne, const double* vh, double* dv,

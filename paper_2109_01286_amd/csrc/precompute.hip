@@ -15,7 +15,7 @@
 //  * On request, the midpoint derivatives: rows 2 and 3 (d/dx, d/dy) of the
 //    same 5-node and 3-node operators at the final rank.
 //  * Divergence rows (eq. flux_polynomials, rows d0, dx, dy): full-rank
-//    least squares of degree 5 solved by Householder QR; a pseudo-inverse row
+//    least squares of degree 4 or 5 solved by Householder QR; a pseudo-inverse row
 //    is Q [R^-T e; 0].  A rank-deficient system is reported as a mesh error.
 //  * Viscous rows (vertex-only fit of degree 4): SVD + graded pseudo-inverse.
 //
@@ -398,14 +398,15 @@ k_edge_weights(int64_t ne, const double* __restrict__ pts,
 // ---------------------------------------------------------------------------
 // Divergence rows: one wavefront per owned vertex, Householder QR.
 // ---------------------------------------------------------------------------
-constexpr int NB5 = 21;       // degree-5 terms
-constexpr int NC5 = 2 * NB5;  // unknowns (a, b)
+// Terms of the divergence fit of degree DEG and its unknowns (a, b).
+template <int DEG> constexpr int kDivTerms = (DEG + 1) * (DEG + 2) / 2;
+template <int DEG> constexpr int kDivUnknowns = 2 * kDivTerms<DEG>;
 
 // LD (a multiple of 8, at least the largest system's row count and NC5, at
 // most 64 RPL) is the row stride of the matrix in dynamic LDS: sized to the mesh
 // rather than to 64 RPL, it lets more blocks share a CU.  Rows i >= LD are
 // never touched (they would be zero padding).
-template <int RPL>
+template <int RPL, int DEG>
 __global__ void __launch_bounds__(64)
 k_div_rows(int64_t nowned, int LD, const int64_t* __restrict__ vptr,
            const int64_t* __restrict__ eptr, const double* __restrict__ vpts,
@@ -413,6 +414,7 @@ k_div_rows(int64_t nowned, int LD, const int64_t* __restrict__ vptr,
            const double* __restrict__ en, int64_t ne, const double* __restrict__ vh,
            double* __restrict__ dv, double* __restrict__ de,
            int32_t* __restrict__ status) {
+  constexpr int NB5 = kDivTerms<DEG>, NC5 = kDivUnknowns<DEG>;
   extern __shared__ double div_lds[];
   double* A = div_lds;              // [NC5][LD]
   double* alpha = A + NC5 * LD;     // [NC5]
@@ -445,7 +447,7 @@ k_div_rows(int64_t nowned, int LD, const int64_t* __restrict__ vptr,
       fb = en[ne + je];
     }
     for (int c = 0; c < NB5; ++c) {
-      double p = (i < m) ? mono<5>(c, 0, x, y) : 0.0;
+      double p = (i < m) ? mono<DEG>(c, 0, x, y) : 0.0;
       A[c * LD + i] = p * fa;
       A[(NB5 + c) * LD + i] = p * fb;
     }
@@ -607,22 +609,28 @@ hipError_t launch_edge_weights(int64_t ne, const double* pts, const double* eh,
   return hipGetLastError();
 }
 
-hipError_t launch_div_rows(int64_t nowned, int msys, const int64_t* vptr,
+hipError_t launch_div_rows(int64_t nowned, int msys, int deg, const int64_t* vptr,
                            const int64_t* eptr, const double* vpts,
                            const double* mpts, const int32_t* sedge,
                            const double* en, int64_t ne, const double* vh, double* dv,
                            double* de, int32_t* status, hipStream_t st) {
   if (nowned == 0) return hipSuccess;
-  if (msys < 1 || msys > 192) return hipErrorInvalidValue;
-  // at least NC5 rows, so that the diagonal A[j][j] (j < NC5) lies in column j
-  const int LD = (std::max(msys, NC5) + 7) / 8 * 8;
-  const size_t lds = size_t(NC5 * LD + 5 * NC5) * sizeof(double);
-  if (LD <= 128)
-    hipLaunchKernelGGL(k_div_rows<2>, dim3(unsigned(nowned)), dim3(64), lds, st, nowned, LD,
-                       vptr, eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
-  else
-    hipLaunchKernelGGL(k_div_rows<3>, dim3(unsigned(nowned)), dim3(64), lds, st, nowned, LD,
-                       vptr, eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status);
+  if (msys < 1 || msys > 192 || (deg != 4 && deg != 5)) return hipErrorInvalidValue;
+  // at least NC rows, so that the diagonal A[j][j] (j < NC) lies in column j
+  const int NC = deg == 5 ? kDivUnknowns<5> : kDivUnknowns<4>;
+  const int LD = (std::max(msys, NC) + 7) / 8 * 8;
+  const size_t lds = size_t(NC * LD + 5 * NC) * sizeof(double);
+#define HFD_LAUNCH_DIV(R, D)                                                                \
+  hipLaunchKernelGGL((k_div_rows<R, D>), dim3(unsigned(nowned)), dim3(64), lds, st, nowned, \
+                     LD, vptr, eptr, vpts, mpts, sedge, en, ne, vh, dv, de, status)
+  if (deg == 5) {
+    if (LD <= 128) HFD_LAUNCH_DIV(2, 5);
+    else HFD_LAUNCH_DIV(3, 5);
+  } else {
+    if (LD <= 128) HFD_LAUNCH_DIV(2, 4);
+    else HFD_LAUNCH_DIV(3, 4);
+  }
+#undef HFD_LAUNCH_DIV
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
                 ("switch_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("flux", ctypes.c_int32),
                 ("stage_off", ctypes.c_int32), ("edge_grad", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("deg_inv", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Info(ctypes.Structure):

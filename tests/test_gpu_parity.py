@@ -32,6 +32,10 @@ CASES = {
     # edges than one edge block (108 periodic; 249 with ghost regions)
     "tiny": ("vortex21", 7, {"w3_cap": 2.0}, "paper"),
     "tiny_ghost": ("riemann201", 6, {"w3_cap": 2.0}, "weno"),
+    # the Delaunay mesh with the circle of the circular Sod case embedded
+    "sod": ("sod_circle", 25, {"w3_cap": 2.0}, "paper"),
+    # the degree-4 divergence fit (reading option)
+    "vortex21-deg4": ("vortex21", None, {"deg_inv": 4}, "paper"),
 }
 
 
@@ -181,7 +185,7 @@ def test_residual_with_gpu_weights_close_to_oracle():
 # Same form as the float64 bound, at float32 rounding: 2e-7 (about 3 units
 # of float32 rounding) of sum |coefficient| |flux|.
 @pytest.mark.parametrize("key", ["vortex21", "shockvortex", "riemann", "tgv", "couette", "tiny",
-                                 "tiny_ghost"])
+                                 "tiny_ghost", "sod"])
 def test_mixed_precision_residual(key):
     P = pair(key)
     P.import_oracle()
