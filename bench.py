@@ -232,6 +232,114 @@ def accuracy_runs():
     return out
 
 
+# the five configurations: workload, lattice size (None = full), options
+CONFIGS = {
+    "vortex21": ("vortex21", None, dict(switch="paper")),
+    "riemann201": ("riemann201", None, dict(switch="paper", w3_cap=2.0)),
+    "tgv513": ("tgv513", None, dict(switch="smooth", mu=0.01, prandtl=0.72, gas_R=1.0)),
+    "vortex257": ("vortex257", None, dict(switch="weno", w3_cap=2.0)),
+    "shockvortex2049": ("shockvortex2049", None, dict(switch="paper", w3_cap=2.0)),
+}
+
+
+def fp32_residual_errors():
+    """Per configuration, the residual of the float32 mixed form at the
+    initial state against the float64 form's on the same GPU weights, at
+    every owned vertex, with the branch of eq. 2d_hweno_intp forced to the
+    float64 decisions (the decisions that differ are counted): per block
+    (w, w_x, w_y) the relative L2 error and the largest element error over
+    the block's largest value, the worst block reported.  The float64 form
+    itself agrees with the oracle to 1e-12 on imported weights and to the
+    precompute's conditioning (<= 1e-8) at these sizes (GPU tests).
+    ``input_rounding`` is the floor float32 data alone impose: the float64
+    residual's relative change when the state is rounded to float32 (the
+    same relative perturbation the mixed form's inputs carry), worst block."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+
+    def worst(a, b, own):
+        # finite entries of both (the method can produce non-positive
+        # pressure at an edge midpoint, e.g. the Riemann case's first
+        # residual; those entries are counted, not compared)
+        l2, el, bad = 0.0, 0.0, 0
+        for k in range(3):
+            x, y = a[4 * k:4 * k + 4, own], b[4 * k:4 * k + 4, own]
+            f = torch.isfinite(x) & torch.isfinite(y)
+            bad += int((~f).sum().item())
+            x, y = x[f], y[f]
+            l2 = max(l2, float(torch.linalg.norm(x - y) / torch.linalg.norm(y)))
+            el = max(el, float((x - y).abs().max() / y.abs().max()))
+        return l2, el, bad
+
+    out = {}
+    for key, (name, scale, kw) in CONFIGS.items():
+        m, U0, prm = inputs.workload(name, scale)
+        S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, **kw)
+        Ud = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+        own = slice(0, S.n_owned)
+        R64 = S.residual(Ud)
+        _, mask64, _ = S.edge_states(Ud, want_mask=True, want_flux=False)
+        Ur = Ud.float().double()
+        l2r, elr, _ = worst(S.residual(Ur), R64, own)
+        S.set_precision("fp32", U0[0:4, m.ghost_src == -1].mean(axis=1))
+        _, mask32, _ = S.edge_states(Ud, want_mask=True, want_flux=False)
+        flips = int((mask32 != mask64).sum().item())
+        S.force_switch_mask(mask64)
+        R32 = S.residual(Ud)
+        S.force_switch_mask(None)
+        try:
+            S.check()
+            numeric = "ok"
+        except hfd.HfdError:
+            numeric = "non-finite or non-positive state met (property of the case)"
+        l2, el, bad = worst(R32, R64, own)
+        out[key] = {"switch": kw["switch"], "owned": int(S.n_owned), "fp32_rel_l2": l2,
+                    "fp32_max_elem_rel": el, "input_rounding_rel_l2": l2r,
+                    "switch_flips": flips, "nonfinite_entries": bad, "check": numeric}
+        del S
+    return out
+
+
+def adjoint_fd(S, Ud, dt, steps, xy, area, g, ndir=32, seed=4242):
+    """Central differences of the objective in ``ndir`` seeded directions
+    delta ~ N(0, 1), step eps = 1e-6 ||U0||_inf / ||delta||_inf and eps / 4,
+    against the adjoint's <g, delta>; errors relative to the rms directional
+    derivative, for eps, eps / 4 and the Richardson combination
+    (16 D(eps / 4) - D(eps)) / 15 (the WENO weights make the O(eps^2) term
+    of the central difference visible at the configured step)."""
+    import numpy as np
+    import torch
+
+    from paper_2109_01286_amd.adjoint import pressure_disk_objective
+    gen = torch.Generator(device="cuda:0").manual_seed(seed)
+    fd, ad = [], []
+    u_inf = Ud.abs().max()
+    for _ in range(ndir):
+        d = torch.randn(Ud.shape, dtype=torch.float64, device="cuda:0", generator=gen)
+        row = []
+        for f in (1.0, 0.25):
+            eps = float(1e-6 * u_inf / d.abs().max()) * f
+            Js = []
+            for sgn in (1.0, -1.0):
+                X = Ud + sgn * eps * d
+                for _ in range(steps):
+                    S.rk_step(X, dt)
+                Js.append(pressure_disk_objective(X, xy, (7.0, 7.0), 1.0, area))
+            row.append(float((Js[0] - Js[1]) / (2.0 * eps)))
+        fd.append(row)
+        ad.append(float(torch.sum(g * d)))
+    fd, ad = np.array(fd), np.array(ad)
+    rms = float(np.sqrt(np.mean(ad ** 2)))
+    rich = (16.0 * fd[:, 1] - fd[:, 0]) / 15.0
+    e = lambda x: {"max": float(np.max(np.abs(x - ad)) / rms),
+                   "median": float(np.median(np.abs(x - ad)) / rms)}
+    return {"directions": ndir, "seed": seed, "eps": e(fd[:, 0]), "eps_quarter": e(fd[:, 1]),
+            "richardson": e(rich), "switch_flips": 0,
+            "note": "WENO-only switch: no branch of eq. 2d_hweno_intp to flip"}
+
+
 def adjoint_ratio(steps=200, ckpt=20):
     """Adjoint/forward time of the isentropic vortex on the 257 x 257 periodic
     jittered lattice: gradient of J = sum A_v [|x - (7,7)| < 1] p^2 after
@@ -282,6 +390,7 @@ def adjoint_ratio(steps=200, ckpt=20):
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
     S.check()
+    fd = adjoint_fd(S, Ud, dt, steps, xy, area, g)
     # the binomial schedule with 10 snapshot slots (memory: 10 states and one
     # step's stages, against 10 + 3 x 20 for the uniform schedule)
     from paper_2109_01286_amd.adjoint import RKStepsRevolve
@@ -330,7 +439,7 @@ def adjoint_ratio(steps=200, ckpt=20):
             "forward_with_checkpoints_ms": t_fwd_ck * 1e3, "backward_ms": t_bwd * 1e3,
             "adjoint_setup_ms": t_setup * 1e3,
             "adjoint_over_forward": t_bwd / t_fwd, "J": J.item(),
-            "grad_finite": bool(torch.isfinite(g).all().item())}
+            "grad_finite": bool(torch.isfinite(g).all().item()), "fd_check": fd}
 
 
 def viscous_line(steps=12, warmup=1):
@@ -402,6 +511,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-viscous", action="store_true")
     ap.add_argument("--no-flux-variants", action="store_true")
+    ap.add_argument("--no-config-errors", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (a "
                          "known-size kernel for calibrating HBM byte counters)")
@@ -526,6 +636,10 @@ def main():
         section("accuracy", accuracy_runs, lambda r: "[bench] accuracy: " + ", ".join(
             f"{k} rho L2 fp64 {v['fp64']['rho']['l2']:.3e} fp32 {v['fp32']['rho']['l2']:.3e}"
             for k, v in r.items()))
+    if not a.no_config_errors:
+        section("fp32_error", fp32_residual_errors, lambda r: "[bench] fp32 residual error: " +
+                ", ".join(f"{k} {v['fp32_rel_l2']:.1e} (input rounding {v['input_rounding_rel_l2']:.1e})"
+                          for k, v in r.items()))
     if not a.no_viscous:
         section("viscous", viscous_line, lambda v: "[bench] viscous (tgv513): " + ", ".join(
             f"{p} {v[p]['value'] / 1e9:.3f} G vertex-stage/s, vertex "
@@ -538,7 +652,9 @@ def main():
         section("adjoint", adjoint_ratio, lambda r: (
             f"[bench] adjoint/forward (vortex257, 200 steps): f64 "
             f"{r['adjoint_over_forward']:.2f}, f32 {r['fp32']['adjoint_over_forward']:.2f} "
-            f"(f32 gradient vs f64: {r['fp32']['grad_rel_l2_diff_vs_fp64']:.1e} rel L2)"))
+            f"(f32 gradient vs f64: {r['fp32']['grad_rel_l2_diff_vs_fp64']:.1e} rel L2); FD "
+            f"agreement {r['fd_check']['eps']['max']:.1e} at eps, "
+            f"{r['fd_check']['richardson']['max']:.1e} extrapolated"))
     if not a.no_cpu:
         log("[bench] timing the CPU oracle on a sample ...")
         section("cpu_baseline", lambda: cpu_baseline(m, U0, prm, kw, a.cpu_budget),
