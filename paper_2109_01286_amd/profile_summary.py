@@ -3,8 +3,11 @@ table (kernel statistics, and HBM traffic from FETCH_SIZE / WRITE_SIZE runs
 calibrated on k_cast, a streaming kernel of known size: it reads 8 bytes and
 writes 4 bytes per element).
 
-    python -m paper_2109_01286_amd.profile_summary STATS_DIR FETCH_DIR WRITE_DIR OUT.md "COMMAND"
+    python -m paper_2109_01286_amd.profile_summary STATS_DIR FETCH_DIR WRITE_DIR OUT.md "COMMAND" [VALU_DIR]
     python -m paper_2109_01286_amd.profile_summary --stats STATS_DIR OUT.md "COMMAND" "TITLE"
+
+VALU_DIR (optional) holds a ``--pmc VALUBusy`` run: the percentage of the
+kernel's time the vector ALUs were busy, per hot-path kernel.
 
 The second form writes the kernel statistics alone.
 """
@@ -39,7 +42,7 @@ def _agg(path):
     return a
 
 
-def main(stats_dir, fetch_dir, write_dir, out, command):
+def main(stats_dir, fetch_dir, write_dir, out, command, valu_dir=None):
     lines = ["# rocprofv3 summary: shock-vortex 2049 x 1025 (2.1 M owned vertices, 6.33 M active edges)", "",
              "Commands (on the MI355X box, from the repository root, `export TMPDIR=/tmp`):", "",
              *["    " + c.strip() for c in command.splitlines() if c.strip()], "",
@@ -66,10 +69,21 @@ def main(stats_dir, fetch_dir, write_dir, out, command):
             w = sum(W[k]) / len(W[k]) * 1024 * fw
             lines.append(f"| `{k[0]}` | {len(F[k])} | {f / 1e9:.3f} | {w / 1e9:.3f} | {(f + w) / 1e9:.3f} |")
             traffic[k[0]] = {"fetch_bytes": f, "write_bytes": w, "bytes": f + w}
+    valu = {}
+    if valu_dir:
+        V = _agg(os.path.join(valu_dir, "run_counter_collection.csv"))
+        lines += ["", "## Vector ALU busy (`--pmc VALUBusy`)", "",
+                  "| kernel | launches | VALU busy (%) |", "|---|---|---|"]
+        for k in sorted(V, key=lambda k: -sum(V[k])):
+            if k[0].startswith(("k_vertex", "k_edge1<", "k_edge2<")):
+                b = sum(V[k]) / len(V[k])
+                lines.append(f"| `{k[0]}` | {len(V[k])} | {b:.1f} |")
+                valu[k[0]] = b
     open(out, "w").write("\n".join(lines) + "\n")
     js = os.path.splitext(out)[0] + "_traffic.json"
     json.dump({"workload": "shockvortex2049", "kernel_sources_sha256": source_digest(),
-               "fetch_factor": ff, "write_factor": fw, "per_launch": traffic},
+               "fetch_factor": ff, "write_factor": fw, "per_launch": traffic,
+               "valu_busy_percent": valu},
               open(js, "w"), indent=1)
 
 
@@ -92,4 +106,4 @@ if __name__ == "__main__":
     if sys.argv[1] == "--stats":
         stats_only(*sys.argv[2:6])
     else:
-        main(*sys.argv[1:6])
+        main(*sys.argv[1:7])
