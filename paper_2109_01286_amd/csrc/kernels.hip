@@ -39,6 +39,15 @@
 #ifndef HFD_EDGE_WAVES
 #define HFD_EDGE_WAVES 2      // waves per SIMD of the float32 edge kernel
 #endif
+#ifndef HFD_EDGE2_WAVES64
+#define HFD_EDGE2_WAVES64 2   // waves per SIMD of the two-lane edge kernel, float64
+#endif
+#ifndef HFD_EDGE2_WAVES32
+#define HFD_EDGE2_WAVES32 4   // the same in float32 (used when HFD_EDGE32_TWO_LANES)
+#endif
+#ifndef HFD_EDGE32_TWO_LANES
+#define HFD_EDGE32_TWO_LANES 0 // 1: the float32 edge pass uses the two-lane kernel
+#endif
 #ifndef HFD_XCD_REMAP
 #define HFD_XCD_REMAP 1       // 1: contiguous block ranges per XCD
 #endif
@@ -56,6 +65,20 @@ __device__ inline const P* at(const P* base, int64_t uoff, uint32_t byte_off) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
   const char* b = reinterpret_cast<const char*>(base) + (uint64_t(lo) | (uint64_t(hi) << 32));
   return reinterpret_cast<const P*>(b + byte_off);
+}
+
+// Record k of vertex `id` in a gather array of R V4 records per vertex.
+#ifndef HFD_GATHER32
+#define HFD_GATHER32 0
+#endif
+template <int R, class T>
+__device__ inline V4<T> gat(const V4<T>* base, int id, int k) {
+#if HFD_GATHER32
+  const uint32_t off = (uint32_t(id) * uint32_t(R) + uint32_t(k)) * uint32_t(sizeof(V4<T>));
+  return *reinterpret_cast<const V4<T>*>(reinterpret_cast<const char*>(base) + off);
+#else
+  return base[int64_t(id) * R + k];
+#endif
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -134,24 +157,6 @@ __device__ inline void side_finish(const T cv[4][5], const T hs[4], const T w3[9
   back_project<T>(F, C, out);
 }
 
-// Both in one pass per component (fewer live values; w3 already loaded).
-template <class T>
-__device__ inline uint8_t side_state(const T cv[4][5], const T hs[4], const T w3[9],
-                                     const Frame<T>& F, const GasParams& gp, int s,
-                                     bool forced, uint8_t fm, T out[4]) {
-  uint8_t bits = 0;
-  T C[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    T o[3];
-    const bool weno = comp_switch<T>(cv[q], gp, s, q, forced, fm, o);
-    C[q] = comp_value<T>(weno, cv[q], o, w3, F.L[q], hs);
-    bits |= uint8_t(weno ? 1 : 0) << (4 * s + q);
-  }
-  back_project<T>(F, C, out);
-  return bits;
-}
-
 template <class T>
 __device__ inline void store_edge(int64_t ne, int64_t e, const T h[4], const T wl[4],
                                   const T wr[4], uint8_t bits, const GasParams& gp,
@@ -177,6 +182,8 @@ __device__ inline void store_edge(int64_t ne, int64_t e, const T h[4], const T w
 // Waves per SIMD each edge kernel is compiled for (register budget 512/waves).
 template <class T> struct EdgeWaves { static constexpr int value = 2; };
 template <> struct EdgeWaves<float> { static constexpr int value = HFD_EDGE_WAVES; };
+template <class T> struct Edge2Waves { static constexpr int value = HFD_EDGE2_WAVES64; };
+template <> struct Edge2Waves<float> { static constexpr int value = HFD_EDGE2_WAVES32; };
 
 // One lane per edge.  The six stencil nodes are gathered and projected once
 // and serve both sides: the left state interpolates from nodes 0..4
@@ -214,7 +221,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   T w[6][4], wx[6][4], wy[6][4];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
-    const V4<T> a = Gv[id[t]], bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
+    const V4<T> a = gat<1>(Gv, id[t], 0), bx = gat<2>(Gg, id[t], 0), by = gat<2>(Gg, id[t], 1);
     w[t][0] = a.x, w[t][1] = a.y, w[t][2] = a.z, w[t][3] = a.w;
     wx[t][0] = bx.x, wx[t][1] = bx.y, wx[t][2] = bx.z, wx[t][3] = bx.w;
     wy[t][0] = by.x, wy[t][1] = by.y, wy[t][2] = by.z, wy[t][3] = by.w;
@@ -272,11 +279,17 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, true, true);
 }
 
-// Two lanes per edge (lane side s = tid & 1 interpolates one state), for the
-// float64 form where one lane's registers cannot hold both sides: the pair
-// swaps states and both evaluate the flux (lane 0 stores it).
+// Two lanes per edge, lane s interpolating side s.  Each stencil node is
+// gathered and projected once: lane 0 takes nodes 0, 1, 2 and lane 1 nodes
+// 5, 4, 3 (its j-th node is node 5 - j), which are the first three nodes of
+// each side in the side's own order.  The partner supplies the side's last
+// two projected nodes and its partial Hermite sum over them (its own nodes
+// j = 1, 2 lie on the other side, side-local nodes 4 and 3), and the edge's
+// other end for the Roe average (node j = 2 of both lanes); the pair then
+// swaps the interface states and both evaluate the flux (lane 0 stores it).
+// All exchanges are DPP moves between lanes 2k and 2k+1.
 template <class T>
-__global__ void __launch_bounds__(256, EdgeWaves<T>::value)
+__global__ void __launch_bounds__(256, Edge2Waves<T>::value)
 k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
         V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
@@ -284,53 +297,107 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   const int64_t e0 = xcd_block() * (blockDim.x / 2);
   const int s = int(threadIdx.x & 1);
   const int64_t e = e0 + threadIdx.x / 2;
-  if (e >= ne) return;
+  if (e >= ne) return;  // (both lanes of an edge leave together)
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
-  // coefficient rows as in k_edge1, the pair of lanes sharing the edge
+  // coefficient rows as in k_edge1, the pair of lanes sharing the edge; the
+  // row offset given to at() must be wave-uniform, so a lane-dependent row
+  // is a select between two loads
   const uint32_t lo = (threadIdx.x / 2) * uint32_t(sizeof(T));
   const uint32_t li = (threadIdx.x / 2) * 4u;
   auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
-  const int ia = *at(c.stg, 2 * ne + e0, li), ib = *at(c.stg, 3 * ne + e0, li);
+  auto row2 = [&](const T* a, int r0, int r1) { return s == 0 ? row(a, r0) : row(a, r1); };
+  int id[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    id[j] = s == 0 ? *at(c.stg, j * ne + e0, li) : *at(c.stg, (5 - j) * ne + e0, li);
   const T nx = row(c.n, 0), ny = row(c.n, 1);
-  const Frame<T> F = roe_frame<T>(Gv[ia], Gv[ib], nx, ny, ref, gm1);
-  const uint8_t fm = force ? force[e] : uint8_t(0);
-  int id[5];
-#pragma unroll
-  for (int t = 0; t < 5; ++t)  // (the row offset given to at() must be wave-uniform)
-    id[t] = s == 0 ? *at(c.stg, t * ne + e0, li) : *at(c.stg, (5 - t) * ne + e0, li);
   const bool forced = force != nullptr;
-  T w5[15];
+  const uint8_t fm = forced ? force[e] : uint8_t(0);
+  // Hermite rows: own side at its nodes 0..2; other side at its nodes 3 + m,
+  // which are own nodes j = 2 - m (m = 0, 1)
+  T wo[9], wt[6];
 #pragma unroll
-  for (int j = 0; j < 15; ++j) w5[j] = s == 0 ? row(c.w5, j) : row(c.w5, 15 + j);
-  T cv[4][5], hs[4] = {T(0), T(0), T(0), T(0)};
+  for (int j = 0; j < 3; ++j) {
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
-    const T w[4] = {a.x, a.y, a.z, a.w};
-    const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
-    const T wy[4] = {by.x, by.y, by.z, by.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cv[q][j] = F.L[q][0] * w[0] + F.L[q][1] * w[1] + F.L[q][2] * w[2] + F.L[q][3] * w[3];
-      hs[q] += w5[3 * j] * w[q] + w5[3 * j + 1] * wx[q] + w5[3 * j + 2] * wy[q];
-    }
+    for (int k = 0; k < 3; ++k) wo[3 * j + k] = row2(c.w5, 3 * j + k, 15 + 3 * j + k);
   }
-  // (unconditional here: a late conditional load costs the float64 kernel
-  // more registers than its 2 waves per SIMD allow)
-  T w3[9];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) w3[j] = s == 0 ? row(c.w3, j) : row(c.w3, 9 + j);
+  for (int m = 0; m < 2; ++m) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      wt[3 * m + k] = row2(c.w5, 15 + 3 * (3 + m) + k, 3 * (3 + m) + k);
+  }
+  T w[3][4], gx[3][4], gy[3][4];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const V4<T> a = gat<1>(Gv, id[j], 0), bx = gat<2>(Gg, id[j], 0), by = gat<2>(Gg, id[j], 1);
+    w[j][0] = a.x, w[j][1] = a.y, w[j][2] = a.z, w[j][3] = a.w;
+    gx[j][0] = bx.x, gx[j][1] = bx.y, gx[j][2] = bx.z, gx[j][3] = bx.w;
+    gy[j][0] = by.x, gy[j][1] = by.y, gy[j][2] = by.z, gy[j][3] = by.w;
+  }
+  // Hermite partial sums in physical variables: own side over own nodes,
+  // other side over own nodes j = 1, 2
+  T hso[4], hst[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    hso[q] = T(0);
+    hst[q] = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      hso[q] += wo[3 * j] * w[j][q] + wo[3 * j + 1] * gx[j][q] + wo[3 * j + 2] * gy[j][q];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+      hst[q] += wt[3 * m] * w[2 - m][q] + wt[3 * m + 1] * gx[2 - m][q] +
+                wt[3 * m + 2] * gy[2 - m][q];
+  }
+  // Roe frame of the edge's end states: lane 0 holds node 2, lane 1 node 3
+  T oth[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) oth[q] = dpp_mov<0xB1>(w[2][q]);
+  const V4<T> A = s == 0 ? V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]}
+                         : V4<T>{oth[0], oth[1], oth[2], oth[3]};
+  const V4<T> B = s == 0 ? V4<T>{oth[0], oth[1], oth[2], oth[3]}
+                         : V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]};
+  const Frame<T> F = roe_frame<T>(A, B, nx, ny, ref, gm1);
+  T hs[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) hs[q] = hso[q] + dpp_mov<0xB1>(hst[q]);
+  // projected values of the side's five nodes: own j = 0..2, then the
+  // partner's j = 2 and 1
+  T cv[4][5];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      cv[q][j] = F.L[q][0] * w[j][0] + F.L[q][1] * w[j][1] + F.L[q][2] * w[j][2] +
+                 F.L[q][3] * w[j][3];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cv[q][3] = dpp_mov<0xB1>(cv[q][2]);
+    cv[q][4] = dpp_mov<0xB1>(cv[q][1]);
+  }
+  // decisions, then the 3-node rows only where some component of the side
+  // takes that branch
+  T o[4][3], w3[9];
+  const uint8_t b = side_weights<T>(cv, gp, s, forced, fm, o);
+#pragma unroll
+  for (int j = 0; j < 9; ++j) w3[j] = T(0);
+  if (b) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) w3[j] = row2(c.w3, j, 9 + j);
+  }
   T wm[4];
-  uint8_t bits = side_state<T>(cv, hs, w3, F, gp, s, forced, fm, wm);
+  side_finish<T>(cv, hs, w3, o, b, s, F, wm);
   T wl[4], wr[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const T o = __shfl_xor(wm[q], 1);
-    wl[q] = s == 0 ? wm[q] : o;
-    wr[q] = s == 0 ? o : wm[q];
+    const T x = dpp_mov<0xB1>(wm[q]);
+    wl[q] = s == 0 ? wm[q] : x;
+    wr[q] = s == 0 ? x : wm[q];
   }
-  bits |= uint8_t(__shfl_xor(int(bits), 1));
+  const uint8_t bits = uint8_t(b | uint8_t(__builtin_amdgcn_update_dpp(0, int(b), 0xB1, 0xF, 0xF, false)));
   T h[4];
   riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, s == 0, s == 1);
@@ -844,7 +911,7 @@ hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
                        double* hsoa, double* wlr, uint8_t* mask, hipStream_t st) {
   if (ne == 0) return hipSuccess;
   // float: one lane per edge; double: two (one per side), register budget
-  if constexpr (sizeof(T) == 8)
+  if constexpr (sizeof(T) == 8 || HFD_EDGE32_TWO_LANES)
     hipLaunchKernelGGL(k_edge2<T>, dim3(nblocks(2 * ne, 256)), dim3(256), 0, st, ne, c, gp,
                        Gv, Gg, force, H, hsoa, wlr, mask);
   else
