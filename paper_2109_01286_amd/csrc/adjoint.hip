@@ -344,7 +344,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       weno_parts(w3, cq, be, om, Sk);
       bool wq;
       if (force) wq = (fm >> (4 * s + q)) & 1;
-      else if (gp.sw == HFD_SWITCH_PAPER) wq = !(om[0] > T(gp.sw_lo) && om[0] < T(gp.sw_hi));
+      else if (gp.sw == HFD_SWITCH_PAPER) wq = !weno_in<T>(be, eps, T(gp.sw_lo), T(gp.sw_hi));
       else wq = (gp.sw == HFD_SWITCH_WENO_ONLY);
       weno[q] = wq;
       C[q] = wq ? om[0] * Sk[0] + om[1] * Sk[1] + om[2] * Sk[2]
@@ -400,6 +400,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     // direction k of this lane's state (full states, zero reference)
     GasParams gz = gp;
     for (int q = 0; q < 4; ++q) gz.wref[q] = 0.0;
+    gz.uref = gz.vref = gz.etr_ref = 0.0;
     const Ref<Dual<T>> rz = make_ref<Dual<T>>(gz);
     for (int k = 0; k < 4; ++k) {
       Dual<T> Ld[4], Rd[4], hd[4];

@@ -164,6 +164,11 @@ GasParams gas_params(const hfd_ctx* c, bool mixed) {
   g.sw_lo = c->o.sw_lo;
   g.sw_hi = c->o.sw_hi;
   for (int q = 0; q < 4; ++q) g.wref[q] = mixed ? c->o.w_ref[q] : 0.0;
+  const double rho = g.wref[0];
+  g.uref = rho > 0 ? g.wref[1] / rho : 0.0;
+  g.vref = rho > 0 ? g.wref[2] / rho : 0.0;
+  const double p = (g.gamma - 1.0) * (g.wref[3] - 0.5 * rho * (g.uref * g.uref + g.vref * g.vref));
+  g.etr_ref = g.wref[3] + p;
   g.sw = c->o.switch_mode;
   g.flux = c->o.flux;
   return g;

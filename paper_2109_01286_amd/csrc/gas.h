@@ -9,6 +9,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace hfd {
@@ -38,27 +40,80 @@ __device__ inline float fsqrt<float>(float x) {
 // values c of one side (order c_{-2} .. c_2): Jiang-Shu smoothness indicators
 // beta, alpha_j = d_j / (eps + beta_j)^2 with d = (1/16, 10/16, 5/16), and
 // omega = alpha / sum(alpha).  With t_j = (eps + beta_j)^2 the weights are
-// omega_j = d_j t_k t_l / (d_1 t_2 t_3 + d_2 t_1 t_3 + d_3 t_1 t_2): the same
-// numbers with one reciprocal instead of six divisions (t >= eps^2, so the
-// products neither underflow nor, for any finite state of these problems,
-// overflow).  Shared by the edge passes and the adjoint, so that both take
-// the same decisions.
+// omega_j = n_j / (n_1 + n_2 + n_3), n_j = d_j t_k t_l: the same numbers with
+// one reciprocal instead of six divisions (t >= eps^2, so the products
+// neither underflow nor, for any finite state of these problems, overflow).
+// The switch tests omega_1 in (lo, hi) as lo S < n_1 < hi S (S > 0), with no
+// division; the weights themselves are formed only where the 3-node branch
+// is taken.  Shared by the edge passes and the adjoint, so that both take the
+// same decisions.
 template <class T>
-__device__ inline void weno_weights(const T c[5], T eps, T be[3], T o[3]) {
-  const T d1 = T(1.0 / 16.0), d2 = T(10.0 / 16.0), d3 = T(5.0 / 16.0);
+__device__ inline void weno_beta(const T c[5], T be[3]) {
   const T t1 = c[0] - T(2) * c[1] + c[2], t2 = c[0] - T(4) * c[1] + T(3) * c[2];
   const T t3 = c[1] - T(2) * c[2] + c[3], t4 = c[1] - c[3];
   const T t5 = c[2] - T(2) * c[3] + c[4], t6 = T(3) * c[2] - T(4) * c[3] + c[4];
   be[0] = T(13.0 / 12.0) * t1 * t1 + T(0.25) * t2 * t2;
   be[1] = T(13.0 / 12.0) * t3 * t3 + T(0.25) * t4 * t4;
   be[2] = T(13.0 / 12.0) * t5 * t5 + T(0.25) * t6 * t6;
+}
+
+// Both sides' indicators from an edge's six projected node values v, side 0
+// reading v[0..4] and side 1 v[5..1].  With d_k = v_{k+1} - v_k and
+// D_k = d_{k+1} - d_k, the second differences of the substencils are the D_k
+// and the other terms D_k +- 2 d (one-sided) or d + d' (central), so the
+// 13/12 D_k^2 serve both sides.
+template <class T>
+__device__ inline void weno_beta_pair(const T v[6], T b0[3], T b1[3]) {
+  T d[5], D[4], A[4];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) d[k] = v[k + 1] - v[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    D[k] = d[k + 1] - d[k];
+    A[k] = T(13.0 / 12.0) * D[k] * D[k];
+  }
+  const T s0 = D[0] + T(2) * d[1], s1 = d[1] + d[2], s2 = D[2] - T(2) * d[2];
+  const T r0 = D[3] - T(2) * d[3], r1 = d[2] + d[3], r2 = D[1] + T(2) * d[2];
+  b0[0] = A[0] + T(0.25) * s0 * s0;
+  b0[1] = A[1] + T(0.25) * s1 * s1;
+  b0[2] = A[2] + T(0.25) * s2 * s2;
+  b1[0] = A[3] + T(0.25) * r0 * r0;
+  b1[1] = A[2] + T(0.25) * r1 * r1;
+  b1[2] = A[1] + T(0.25) * r2 * r2;
+}
+
+template <class T>
+__device__ inline void weno_num(const T be[3], T eps, T n[3]) {
   const T q1 = (eps + be[0]) * (eps + be[0]), q2 = (eps + be[1]) * (eps + be[1]);
   const T q3 = (eps + be[2]) * (eps + be[2]);
-  const T n1 = d1 * (q2 * q3), n2 = d2 * (q1 * q3), n3 = d3 * (q1 * q2);
-  const T r = fdiv(T(1), n1 + n2 + n3);
-  o[0] = n1 * r;
-  o[1] = n2 * r;
-  o[2] = n3 * r;
+  n[0] = T(1.0 / 16.0) * (q2 * q3);
+  n[1] = T(10.0 / 16.0) * (q1 * q3);
+  n[2] = T(5.0 / 16.0) * (q1 * q2);
+}
+
+// omega_1 in (lo, hi) (false for a non-finite indicator)
+template <class T>
+__device__ inline bool weno_in(const T be[3], T eps, T lo, T hi) {
+  T n[3];
+  weno_num<T>(be, eps, n);
+  const T S = n[0] + n[1] + n[2];
+  return n[0] > lo * S && n[0] < hi * S;
+}
+
+template <class T>
+__device__ inline void weno_omega(const T be[3], T eps, T o[3]) {
+  T n[3];
+  weno_num<T>(be, eps, n);
+  const T r = fdiv(T(1), n[0] + n[1] + n[2]);
+  o[0] = n[0] * r;
+  o[1] = n[1] * r;
+  o[2] = n[2] * r;
+}
+
+template <class T>
+__device__ inline void weno_weights(const T c[5], T eps, T be[3], T o[3]) {
+  weno_beta<T>(c, be);
+  weno_omega<T>(be, eps, o);
 }
 
 // Fluxes minus the reference fluxes, from the perturbation w' and the full
@@ -108,13 +163,17 @@ __device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
 template <class T>
 __device__ inline Ref<T> make_ref(const GasParams& gp) {
   Ref<T> r;
-  for (int q = 0; q < 4; ++q) r.w[q] = T(gp.wref[q]);
-  double rho = gp.wref[0];
-  double u = rho > 0 ? gp.wref[1] / rho : 0.0, v = rho > 0 ? gp.wref[2] / rho : 0.0;
-  double p = (gp.gamma - 1.0) * (gp.wref[3] - 0.5 * rho * (u * u + v * v));
-  r.u = T(u);
-  r.v = T(v);
-  r.etr = T(gp.wref[3] + p);
+  if constexpr (std::is_same<T, float>::value) {
+    for (int q = 0; q < 4; ++q) r.w[q] = T(gp.wref[q]);
+    r.u = T(gp.uref);
+    r.v = T(gp.vref);
+    r.etr = T(gp.etr_ref);
+  } else {
+    // only the float32 kernels carry a reference state: the float64 form
+    // (and the adjoint's dual-number fluxes of full states) have none
+    for (int q = 0; q < 4; ++q) r.w[q] = T(0);
+    r.u = r.v = r.etr = T(0);
+  }
   return r;
 }
 
@@ -158,21 +217,35 @@ __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
       un, cc};
 }
 
-// Rusanov flux along n of the two interface states (perturbation form).
+// Rusanov flux along n of the two interface states (perturbation form),
+// h = (F_L.n + F_R.n)/2 - lam (w_R - w_L)/2 with lam the larger of the two
+// sides' |u.n| + c.  One side's part: its normal flux fn and speed sp.
 template <class T>
-__device__ inline void rusanov(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
-                               T gam, T gm1, T h[4]) {
-  T fl[4], gl[4], fr[4], gr[4], pl, rl, ul, vl, pr, rr, ur, vr;
-  pert_flux<T>(wl, ref, gm1, fl, gl, &pl, &rl, &ul, &vl);
-  pert_flux<T>(wr, ref, gm1, fr, gr, &pr, &rr, &ur, &vr);
-  const T sl = fabs(ul * nx + vl * ny) + fsqrt(fdiv(gam * pl, rl));
-  const T sr = fabs(ur * nx + vr * ny) + fsqrt(fdiv(gam * pr, rr));
+__device__ inline void rusanov_side(const T w[4], T nx, T ny, const Ref<T>& ref, T gam, T gm1,
+                                    T fn[4], T& sp) {
+  T f[4], g[4], p, r, u, v;
+  pert_flux<T>(w, ref, gm1, f, g, &p, &r, &u, &v);
+  sp = fabs(u * nx + v * ny) + fsqrt(fdiv(gam * p, r));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fn[q] = f[q] * nx + g[q] * ny;
+}
+
+template <class T>
+__device__ inline void rusanov_join(const T wl[4], const T wr[4], const T fnl[4],
+                                    const T fnr[4], T sl, T sr, T h[4]) {
   // NaN-propagating maximum: a non-physical state must not be hidden
   const T lam = (isnan(sl) || isnan(sr)) ? sl + sr : (sl > sr ? sl : sr);
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    h[q] = T(0.5) * ((fl[q] + fr[q]) * nx + (gl[q] + gr[q]) * ny) -
-           T(0.5) * lam * (wr[q] - wl[q]);
+  for (int q = 0; q < 4; ++q) h[q] = T(0.5) * (fnl[q] + fnr[q]) - T(0.5) * lam * (wr[q] - wl[q]);
+}
+
+template <class T>
+__device__ inline void rusanov(const T wl[4], const T wr[4], T nx, T ny, const Ref<T>& ref,
+                               T gam, T gm1, T h[4]) {
+  T fnl[4], fnr[4], sl, sr;
+  rusanov_side<T>(wl, nx, ny, ref, gam, gm1, fnl, sl);
+  rusanov_side<T>(wr, nx, ny, ref, gam, gm1, fnr, sr);
+  rusanov_join<T>(wl, wr, fnl, fnr, sl, sr, h);
 }
 
 // Roe's flux at the Roe average of the two interface states, with Harten's

@@ -66,6 +66,7 @@ struct GasParams {
   double gamma, gas_R, mu, prandtl;
   double eps, sw_lo, sw_hi;
   double wref[4];   // FP32 form: reference state (zero in the FP64 form)
+  double uref, vref, etr_ref;  // its velocity and E + p (set with wref)
   int sw;           // hfd_switch
   int flux;         // hfd_flux
 };

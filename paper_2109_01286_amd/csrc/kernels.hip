@@ -1,11 +1,12 @@
 // Hot-path kernels of the Hermite finite-difference method (gfx950).
 //
-// Edge pass (Section 2.2 / 2.3, Algorithm 1, eq. 2d_hweno_intp): one thread
-// per active edge.  Roe average of the edge's end states, characteristic
+// Edge pass (Section 2.2 / 2.3, Algorithm 1, eq. 2d_hweno_intp): one lane per
+// active edge in float32, two in float64 (one per side, sharing the six
+// stencil nodes).  Roe average of the edge's end states, characteristic
 // projection of values and gradients at the six stencil nodes, per side and
-// characteristic component the uniform WENO5 weights and the switch, the
-// 5-node Hermite value (15-term dot product with the stored row) or the
-// omega-weighted 3-node values, back-projection, Rusanov flux along the edge.
+// characteristic component the WENO5 smoothness indicators and the switch,
+// the 5-node Hermite value (15-term dot product with the stored row) or the
+// omega-weighted 3-node values, back-projection, Riemann flux along the edge.
 //
 // Vertex pass (eq. flux_polynomials and the rows d0, dx, dy; viscous
 // vertex-only rows; three-stage TVD Runge-Kutta): a block of 16 owned
@@ -67,20 +68,6 @@ __device__ inline const P* at(const P* base, int64_t uoff, uint32_t byte_off) {
   return reinterpret_cast<const P*>(b + byte_off);
 }
 
-// Record k of vertex `id` in a gather array of R V4 records per vertex.
-#ifndef HFD_GATHER32
-#define HFD_GATHER32 0
-#endif
-template <int R, class T>
-__device__ inline V4<T> gat(const V4<T>* base, int id, int k) {
-#if HFD_GATHER32
-  const uint32_t off = (uint32_t(id) * uint32_t(R) + uint32_t(k)) * uint32_t(sizeof(V4<T>));
-  return *reinterpret_cast<const V4<T>*>(reinterpret_cast<const char*>(base) + off);
-#else
-  return base[int64_t(id) * R + k];
-#endif
-}
-
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumber them so that XCD x runs one contiguous range of logical
 // blocks: neighbouring vertices / edges then share an L2 for their gathers.
@@ -98,18 +85,14 @@ __device__ inline int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 // Edge pass
 // ---------------------------------------------------------------------------
-// Switch of one characteristic component q of side s: the WENO5 smoothness
-// indicators and weights o (Jiang-Shu, linear weights 1/16, 10/16, 5/16) of
-// the five projected node values c[0..4], and the decision: true for the
+// Switch of one characteristic component q of side s from the smoothness
+// indicators be of its five projected node values: true for the
 // omega-weighted 3-node values, false for the 5-node Hermite value.
 template <class T>
-__device__ inline bool comp_switch(const T c[5], const GasParams& gp, int s, int q,
-                                   bool forced, uint8_t fm, T o[3]) {
-  const T lo = T(gp.sw_lo), hi = T(gp.sw_hi);
-  T be[3];
-  weno_weights<T>(c, T(gp.eps), be, o);
+__device__ inline bool comp_switch(const T be[3], const GasParams& gp, int s, int q,
+                                   bool forced, uint8_t fm) {
   if (forced) return (fm >> (4 * s + q)) & 1;
-  if (gp.sw == HFD_SWITCH_PAPER) return !(o[0] > lo && o[0] < hi);
+  if (gp.sw == HFD_SWITCH_PAPER) return !weno_in<T>(be, T(gp.eps), T(gp.sw_lo), T(gp.sw_hi));
   return gp.sw == HFD_SWITCH_WENO_ONLY;
 }
 
@@ -134,26 +117,40 @@ __device__ inline void back_project(const Frame<T>& F, const T C[4], T out[4]) {
     out[r] = F.R[r][0] * C[0] + F.R[r][1] * C[1] + F.R[r][2] * C[2] + F.R[r][3] * C[3];
 }
 
-// One side's decisions (bits 4 s + q) and weights, for a state finished by
-// side_finish once the side's 3-node rows are known to be needed.
+// One side's decisions (bits 4 s + q) from its indicators.
 template <class T>
-__device__ inline uint8_t side_weights(const T cv[4][5], const GasParams& gp, int s,
-                                       bool forced, uint8_t fm, T o[4][3]) {
+__device__ inline uint8_t side_decide(const T be[4][3], const GasParams& gp, int s,
+                                      bool forced, uint8_t fm) {
   uint8_t bits = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
-    bits |= uint8_t(comp_switch<T>(cv[q], gp, s, q, forced, fm, o[q]) ? 1 : 0) << (4 * s + q);
+    bits |= uint8_t(comp_switch<T>(be[q], gp, s, q, forced, fm) ? 1 : 0) << (4 * s + q);
   return bits;
 }
 
-template <class T>
-__device__ inline void side_finish(const T cv[4][5], const T hs[4], const T w3[9],
-                                   const T o[4][3], uint8_t bits, int s, const Frame<T>& F,
-                                   T out[4]) {
+// The side's interface state (back-projected).  Only when some component of
+// the side takes the 3-node branch are the side's 3-node rows read and its
+// WENO weights formed; otherwise every component is the Hermite value.
+template <class T, class RowFn>
+__device__ inline void side_state(uint8_t b, int s, const T be[4][3], const T cv[4][5],
+                                  const T hs[4], const Frame<T>& F, const GasParams& gp,
+                                  RowFn w3row, T out[4]) {
   T C[4];
+  if (b) {
+    T w3[9];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    C[q] = comp_value<T>((bits >> (4 * s + q)) & 1, cv[q], o[q], w3, F.L[q], hs);
+    for (int j = 0; j < 9; ++j) w3[j] = w3row(j);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T o[3];
+      weno_omega<T>(be[q], T(gp.eps), o);
+      C[q] = comp_value<T>((b >> (4 * s + q)) & 1, cv[q], o, w3, F.L[q], hs);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      C[q] = F.L[q][0] * hs[0] + F.L[q][1] * hs[1] + F.L[q][2] * hs[2] + F.L[q][3] * hs[3];
+  }
   back_project<T>(F, C, out);
 }
 
@@ -221,7 +218,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   T w[6][4], wx[6][4], wy[6][4];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
-    const V4<T> a = gat<1>(Gv, id[t], 0), bx = gat<2>(Gg, id[t], 0), by = gat<2>(Gg, id[t], 1);
+    const V4<T> a = Gv[id[t]], bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
     w[t][0] = a.x, w[t][1] = a.y, w[t][2] = a.z, w[t][3] = a.w;
     wx[t][0] = bx.x, wx[t][1] = bx.y, wx[t][2] = bx.z, wx[t][3] = bx.w;
     wy[t][0] = by.x, wy[t][1] = by.y, wy[t][2] = by.z, wy[t][3] = by.w;
@@ -252,26 +249,25 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     for (int q = 0; q < 4; ++q)
       cv[q][t] = F.L[q][0] * w[t][0] + F.L[q][1] * w[t][1] + F.L[q][2] * w[t][2] + F.L[q][3] * w[t][3];
   }
-  // per side: decisions, then the 3-node rows only if some component takes
-  // that branch, then the interface state
+  // smoothness indicators of both sides (shared differences), then per side
+  // the decisions and, only if some component takes that branch, the 3-node
+  // rows and weights; then the interface state
+  T be[2][4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) weno_beta_pair<T>(cv[q], be[0][q], be[1][q]);
   uint8_t bits = 0;
   T wl[4], wr[4];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    T c5[4][5], o[4][3], w3[9];
+    T c5[4][5];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
       for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][s == 0 ? p : 5 - p];
     }
-    const uint8_t b = side_weights<T>(c5, gp, s, forced, fm, o);
-#pragma unroll
-    for (int j = 0; j < 9; ++j) w3[j] = T(0);
-    if (b) {
-#pragma unroll
-      for (int j = 0; j < 9; ++j) w3[j] = row(c.w3, s * 9 + j);
-    }
-    side_finish<T>(c5, hs[s], w3, o, b, s, F, s == 0 ? wl : wr);
+    const uint8_t b = side_decide<T>(be[s], gp, s, forced, fm);
+    side_state<T>(b, s, be[s], c5, hs[s], F, gp, [&](int j) { return row(c.w3, s * 9 + j); },
+                  s == 0 ? wl : wr);
     bits |= b;
   }
   T h[4];
@@ -331,7 +327,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   T w[3][4], gx[3][4], gy[3][4];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const V4<T> a = gat<1>(Gv, id[j], 0), bx = gat<2>(Gg, id[j], 0), by = gat<2>(Gg, id[j], 1);
+    const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
     w[j][0] = a.x, w[j][1] = a.y, w[j][2] = a.z, w[j][3] = a.w;
     gx[j][0] = bx.x, gx[j][1] = bx.y, gx[j][2] = bx.z, gx[j][3] = bx.w;
     gy[j][0] = by.x, gy[j][1] = by.y, gy[j][2] = by.z, gy[j][3] = by.w;
@@ -378,18 +374,14 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     cv[q][3] = dpp_mov<0xB1>(cv[q][2]);
     cv[q][4] = dpp_mov<0xB1>(cv[q][1]);
   }
-  // decisions, then the 3-node rows only where some component of the side
-  // takes that branch
-  T o[4][3], w3[9];
-  const uint8_t b = side_weights<T>(cv, gp, s, forced, fm, o);
+  // decisions, then the 3-node rows and weights only where some component
+  // of the side takes that branch
+  T be[4][3];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) w3[j] = T(0);
-  if (b) {
-#pragma unroll
-    for (int j = 0; j < 9; ++j) w3[j] = row2(c.w3, j, 9 + j);
-  }
+  for (int q = 0; q < 4; ++q) weno_beta<T>(cv[q], be[q]);
+  const uint8_t b = side_decide<T>(be, gp, s, forced, fm);
   T wm[4];
-  side_finish<T>(cv, hs, w3, o, b, s, F, wm);
+  side_state<T>(b, s, be, cv, hs, F, gp, [&](int j) { return row2(c.w3, j, 9 + j); }, wm);
   T wl[4], wr[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -399,7 +391,17 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   }
   const uint8_t bits = uint8_t(b | uint8_t(__builtin_amdgcn_update_dpp(0, int(b), 0xB1, 0xF, 0xF, false)));
   T h[4];
-  riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
+  if (gp.flux == HFD_FLUX_RUSANOV) {
+    // each lane its own side's normal flux and speed, then swapped; only
+    // lane 0 stores h, so both lanes join as lane 0 (left = own side)
+    T fn[4], fo[4], sp;
+    rusanov_side<T>(wm, nx, ny, ref, gam, gm1, fn, sp);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fo[q] = dpp_mov<0xB1>(fn[q]);
+    rusanov_join<T>(wl, wr, fn, fo, sp, dpp_mov<0xB1>(sp), h);
+  } else {
+    riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
+  }
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, s == 0, s == 1);
 }
 
@@ -451,8 +453,12 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
   T gc[2][4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    T o[3];
-    const bool weno = comp_switch<T>(cv[q], gp, s, q, true, fm, o);
+    const bool weno = (fm >> (4 * s + q)) & 1;
+    T o[3] = {T(0), T(0), T(0)};
+    if (weno) {
+      T be[3];
+      weno_weights<T>(cv[q], T(gp.eps), be, o);
+    }
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       if (weno) {
