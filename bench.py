@@ -77,8 +77,8 @@ def time_precision(S, U0d, prec, wref, steps, warmup, cfl, chunk):
         done += n
     e_ms, n_e, v_ms, n_v = S.kernel_times()
     info = S.refresh_info()
-    # the float32 edge pass reads a side's 3-node rows only where that side
-    # takes the 3-node branch: count those sides at the initial state
+    # the edge passes read a side's 3-node rows only where that side takes
+    # the 3-node branch: count those sides at the initial state
     bytes_edge = info["bytes_edge_launch"]
     w3_sides = None
     if info["bytes_edge_w3_side"] > 0:

@@ -122,9 +122,9 @@ typedef struct hfd_info {
   double bytes_edge_launch;    /* edge pass                              */
   double bytes_vertex_launch;  /* vertex pass with the Runge-Kutta update */
   /* Bytes of the 3-node rows of one edge side, read only when some
-   * component of that side takes the 3-node branch (float32 form with the
-   * PAPER or SMOOTH switch or a forced mask); not in bytes_edge_launch.
-   * 0 when the rows are always read and counted there. */
+   * component of that side takes the 3-node branch (PAPER or SMOOTH switch,
+   * or a forced mask); not in bytes_edge_launch.  0 when the rows are
+   * always read (WENO everywhere) and counted there. */
   double bytes_edge_w3_side;
   double setup_ms[4];    /* host setup, upload, GPU precompute, total       */
   /* Vertex pass: bytes of a slot's local id when each block of 16 owned

@@ -262,10 +262,10 @@ void byte_model(hfd_ctx* c) {
   const double ne = double(I.n_edges), nv = double(I.nv), no = double(I.n_owned);
   const double visc = c->o.mu > 0.0 ? 1.0 : 0.0;
   // edge pass: ids, direction + Hermite + 3-node weights, the stage state
-  // (12 values per vertex), flux out.  The float32 kernel reads the 3-node
-  // rows of a side only when the side takes that branch somewhere: those
-  // bytes are per side (data-dependent), except with WENO everywhere.
-  const bool w3_lazy = mixed(c) && c->o.switch_mode != HFD_SWITCH_WENO_ONLY;
+  // (12 values per vertex), flux out.  Both kernels read the 3-node rows of
+  // a side only when the side takes that branch somewhere: those bytes are
+  // per side (data-dependent), except with WENO everywhere.
+  const bool w3_lazy = c->o.switch_mode != HFD_SWITCH_WENO_ONLY;
   I.bytes_edge_launch = ne * (6 * 4 + (w3_lazy ? 32 : 50) * s + 4 * s) + nv * 12 * s;
   I.bytes_edge_w3_side = w3_lazy ? 9 * s : 0.0;
   // vertex pass: CSR offsets and ids, coefficient records, state (values,
