@@ -104,7 +104,7 @@ __device__ inline bool isnan(Dual<B> a) { return isnan(a.v); }
 template <class T>
 __device__ inline void flux_jac_t(const T w[4], T nx, T ny, T gm1,
                                   const T g[4], T out[4]) {
-  const T rho = w[0], ir = T(1.0) / rho, u = w[1] * ir, v = w[2] * ir;
+  const T rho = w[0], ir = frcp(rho), u = w[1] * ir, v = w[2] * ir;
   const T un = u * nx + v * ny;
   const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
   // d un / dw, d p / dw
@@ -130,28 +130,28 @@ template <class T>
 __device__ inline void speed_grad(const T w[4], T nx, T ny, T gam,
                                   T out[4]) {
   const T gm1 = gam - T(1.0);
-  const T rho = w[0], ir = T(1.0) / rho, u = w[1] * ir, v = w[2] * ir;
+  const T rho = w[0], ir = frcp(rho), u = w[1] * ir, v = w[2] * ir;
   const T un = u * nx + v * ny;
   const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
-  const T c = sqrt(gam * p * ir);
+  const T c = fsqrt(gam * p * ir);
   const T sg = un > T(0.0) ? T(1.0) : (un < T(0.0) ? -T(1.0) : T(0.0));
   const T dun[4] = {-un * ir, nx * ir, ny * ir, T(0.0)};
   const T dp[4] = {gm1 * T(0.5) * (u * u + v * v), -gm1 * u, -gm1 * v, gm1};
-  const T k = gam / (T(2.0) * c * rho);
+  const T k = T(0.5) * gam * frcp(c) * ir;
   for (int j = 0; j < 4; ++j) out[j] = sg * dun[j] + k * (dp[j] - (j == 0 ? p * ir : T(0.0)));
 }
 
 template <class T>
 __device__ inline void cart_flux_n(const T w[4], T nx, T ny, T gm1,
                                    T f[4], T* sp, T gam) {
-  const T rho = w[0], ir = T(1.0) / rho, u = w[1] * ir, v = w[2] * ir;
+  const T rho = w[0], ir = frcp(rho), u = w[1] * ir, v = w[2] * ir;
   const T un = u * nx + v * ny;
   const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
   f[0] = rho * un;
   f[1] = w[1] * un + p * nx;
   f[2] = w[2] * un + p * ny;
   f[3] = (w[3] + p) * un;
-  *sp = fabs(un) + sqrt(gam * p * ir);
+  *sp = fabs(un) + fsqrt(gam * p * ir);
 }
 
 // x, opaque to the optimiser (no code): values derived from it after this
@@ -254,22 +254,25 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       B[q] = full(B[q], q);
     }
     const T ra = A[0], rb = B[0];
-    sa = sqrt(ra);
-    sb = sqrt(rb);
+    const T ira = frcp(ra), irb = frcp(rb);
+    sa = fsqrt(ra);
+    sb = fsqrt(rb);
     D = sa + sb;
-    pa = gm1 * (A[3] - T(0.5) * (A[1] * A[1] + A[2] * A[2]) / ra);
-    pb = gm1 * (B[3] - T(0.5) * (B[1] * B[1] + B[2] * B[2]) / rb);
-    const T Pa = A[1] / sa, Pb = B[1] / sb, Qa = A[2] / sa, Qb = B[2] / sb;
-    const T Ka = (A[3] + pa) / sa, Kb = (B[3] + pb) / sb;
-    u = (Pa + Pb) / D;
-    v = (Qa + Qb) / D;
-    H = (Ka + Kb) / D;
-    cc = sqrt(gm1 * (H - T(0.5) * (u * u + v * v)));
+    pa = gm1 * (A[3] - T(0.5) * (A[1] * A[1] + A[2] * A[2]) * ira);
+    pb = gm1 * (B[3] - T(0.5) * (B[1] * B[1] + B[2] * B[2]) * irb);
+    // 1/sqrt(r) = sqrt(r)/r
+    const T isa = sa * ira, isb = sb * irb, iD = frcp(D);
+    const T Pa = A[1] * isa, Pb = B[1] * isb, Qa = A[2] * isa, Qb = B[2] * isb;
+    const T Ka = (A[3] + pa) * isa, Kb = (B[3] + pb) * isb;
+    u = (Pa + Pb) * iD;
+    v = (Qa + Qb) * iD;
+    H = (Ka + Kb) * iD;
+    cc = fsqrt(gm1 * (H - T(0.5) * (u * u + v * v)));
   };
   auto eig = [&](T u, T v, T H, T cc, T L[4][4], T R[4][4]) {
     const T q2 = u * u + v * v;
     const T un = u * nx + v * ny, ut = -u * ny + v * nx;
-    const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1.0) / cc;
+    const T ic = frcp(cc), b1 = gm1 * ic * ic, b2 = T(0.5) * b1 * q2;
     const T Lv[4][4] = {
         {T(0.5) * (b2 + un * ic), -T(0.5) * (b1 * u + nx * ic), -T(0.5) * (b1 * v + ny * ic), T(0.5) * b1},
         {T(1.0) - b2, b1 * u, b1 * v, -b1},
@@ -378,7 +381,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   eig(u, v, H, cc, L, R);
   const T q2 = u * u + v * v;
   const T un = u * nx + v * ny;
-  const T b1 = gm1 / (cc * cc), b2 = T(0.5) * b1 * q2, ic = T(1.0) / cc;
+  const T ic = frcp(cc), b1 = gm1 * ic * ic, b2 = T(0.5) * b1 * q2;
 
   // ---- reverse: Riemann flux -> this side's state ------------------------------------
   T gw[4];
@@ -489,7 +492,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     T dot = T(0.0);
     for (int k = 0; k < 3; ++k) dot += gom[k] * om[k];
     T gbe[3];
-    for (int k = 0; k < 3; ++k) gbe[k] = -T(2.0) * (gom[k] - dot) * om[k] / (eps + be[k]);
+    for (int k = 0; k < 3; ++k) gbe[k] = -T(2.0) * (gom[k] - dot) * om[k] * frcp(eps + be[k]);
     const T t1 = cq[0] - 2 * cq[1] + cq[2], t2 = cq[0] - 4 * cq[1] + 3 * cq[2];
     const T t3 = cq[1] - 2 * cq[2] + cq[3], t4 = cq[1] - cq[3];
     const T t5 = cq[2] - 2 * cq[3] + cq[4], t6 = 3 * cq[2] - 4 * cq[3] + cq[4];
@@ -526,32 +529,38 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     gc = s == 0 ? gc + oc : oc + gc;
   }
   // c = sqrt(gm1 (H - q2/2))
-  gH += gc * gm1 / (T(2.0) * cc);
-  gu += gc * (-gm1 * u / (T(2.0) * cc));
-  gv += gc * (-gm1 * v / (T(2.0) * cc));
+  {
+    const T hc = gc * gm1 * T(0.5) * ic;
+    gH += hc;
+    gu -= hc * u;
+    gv -= hc * v;
+  }
   // ---- Roe average -> this lane's end state (node 2 or 3, position 2) ---------------
   {
     T A[4], B[4], sa, sb, D, pa, pb, u_, v_, H_, cc_;
     roe(A, B, sa, sb, D, pa, pb, u_, v_, H_, cc_);
-    const T gP = gu / D, gQ = gv / D, gK = gH / D;
-    const T gD = -(gu * u + gv * v + gH * H) / D;
+    const T iD = frcp(D);
+    const T gP = gu * iD, gQ = gv * iD, gK = gH * iD;
+    const T gD = -(gu * u + gv * v + gH * H) * iD;
     const T* S = s == 0 ? A : B;
     T* g = gW[2];
     const T r = S[0], s_ = s == 0 ? sa : sb, p = s == 0 ? pa : pb;
+    // 1/r, and 1/s = s/r (s = sqrt(r))
+    const T ir = frcp(r), is = s_ * ir;
     T gs = gD;
     // P = m/s, Q = n/s, K = (E + p)/s
-    g[1] += gP / s_;
-    g[2] += gQ / s_;
-    gs += -(gP * S[1] + gQ * S[2] + gK * (S[3] + p)) / (s_ * s_);
-    const T gE = gK / s_, gp_ = gK / s_;
+    g[1] += gP * is;
+    g[2] += gQ * is;
+    gs += -(gP * S[1] + gQ * S[2] + gK * (S[3] + p)) * is * is;
+    const T gE = gK * is, gp_ = gK * is;
     g[3] += gE;
     // p = gm1 (E - (m^2 + n^2) / (2 r))
     g[3] += gm1 * gp_;
-    g[1] += -gm1 * gp_ * S[1] / r;
-    g[2] += -gm1 * gp_ * S[2] / r;
-    g[0] += gm1 * gp_ * T(0.5) * (S[1] * S[1] + S[2] * S[2]) / (r * r);
+    g[1] += -gm1 * gp_ * S[1] * ir;
+    g[2] += -gm1 * gp_ * S[2] * ir;
+    g[0] += gm1 * gp_ * T(0.5) * (S[1] * S[1] + S[2] * S[2]) * ir * ir;
     // s = sqrt(r)
-    g[0] += gs / (T(2.0) * s_);
+    g[0] += gs * T(0.5) * is;
   }
   // ---- shared nodes: position p (1, 2) of one lane is position 5 - p of the
   // other; each lane adds the partner's contribution to its positions 1, T(2.)

@@ -15,10 +15,15 @@
 
 namespace hfd {
 
-// Division and square root.  float64 keeps the correctly rounded operations;
-// the float32 form uses the hardware reciprocal and square root (about 1 ulp,
-// far below the rounding of its float32 perturbation data) instead of the
-// much longer correctly rounded instruction sequences.
+// Division, reciprocal and square root.  The float32 form uses the hardware
+// reciprocal and square root (about 1 ulp, far below the rounding of its
+// float32 perturbation data) instead of the much longer correctly rounded
+// instruction sequences.  float64 keeps correctly rounded division and square
+// root; its reciprocals 1/x take the hardware estimate (relative error about
+// 2^-23) and two Newton-Raphson steps r <- r + r (1 - x r), each of which
+// squares the relative error, to within about an ulp (x finite, nonzero and
+// of normal magnitude: the densities, sound speeds and sums of these
+// kernels).
 template <class T>
 __device__ inline T fdiv(T a, T b) {
   return a / b;
@@ -26,6 +31,22 @@ __device__ inline T fdiv(T a, T b) {
 template <>
 __device__ inline float fdiv<float>(float a, float b) {
   return a * __builtin_amdgcn_rcpf(b);
+}
+template <class T>
+__device__ inline T frcp(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ inline float frcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ inline double frcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 template <class T>
 __device__ inline T fsqrt(T x) {
@@ -104,7 +125,7 @@ template <class T>
 __device__ inline void weno_omega(const T be[3], T eps, T o[3]) {
   T n[3];
   weno_num<T>(be, eps, n);
-  const T r = fdiv(T(1), n[0] + n[1] + n[2]);
+  const T r = frcp(n[0] + n[1] + n[2]);
   o[0] = n[0] * r;
   o[1] = n[1] * r;
   o[2] = n[2] * r;
@@ -133,7 +154,7 @@ __device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
   const T rho = R.w[0] + wp[0];
   const T m = R.w[1] + wp[1];
   const T n = R.w[2] + wp[2];
-  const T ir = fdiv(T(1), rho);
+  const T ir = frcp(rho);
   // m^2/rho - m_r u_r, m n/rho - m_r v_r, n^2/rho - n_r v_r
   const T amm = (wp[1] * (m + R.w[1]) - R.w[1] * R.u * wp[0]) * ir;
   const T amn = (wp[1] * n + R.w[1] * wp[2] - R.w[1] * R.v * wp[0]) * ir;
@@ -190,21 +211,21 @@ template <class T>
 __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
                                      const Ref<T>& ref, T gm1) {
   const T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
-  const T ira = fdiv(T(1), ra), irb = fdiv(T(1), rb);
+  const T ira = frcp(ra), irb = frcp(rb);
   const T ua = (ref.w[1] + A.y) * ira, ub = (ref.w[1] + B.y) * irb;
   const T va = (ref.w[2] + A.z) * ira, vb = (ref.w[2] + B.z) * irb;
   const T Ea = ref.w[3] + A.w, Eb = ref.w[3] + B.w;
   const T pa = gm1 * (Ea - T(0.5) * ra * (ua * ua + va * va));
   const T pb = gm1 * (Eb - T(0.5) * rb * (ub * ub + vb * vb));
   const T sa = fsqrt(ra), sb = fsqrt(rb);
-  const T iw = fdiv(T(1), sa + sb);
+  const T iw = frcp(sa + sb);
   const T u = (sa * ua + sb * ub) * iw;
   const T v = (sa * va + sb * vb) * iw;
   const T hh = (sa * (Ea + pa) * ira + sb * (Eb + pb) * irb) * iw;
   const T cc = fsqrt(gm1 * (hh - T(0.5) * (u * u + v * v)));
   const T q2 = u * u + v * v;
   const T un = u * nx + v * ny, ut = -u * ny + v * nx;
-  const T b1 = fdiv(gm1, cc * cc), b2 = T(0.5) * b1 * q2, ic = fdiv(T(1), cc);
+  const T ic = frcp(cc), b1 = gm1 * ic * ic, b2 = T(0.5) * b1 * q2;
   return Frame<T>{
       {{T(0.5) * (b2 + un * ic), T(-0.5) * (b1 * u + nx * ic), T(-0.5) * (b1 * v + ny * ic), T(0.5) * b1},
        {T(1) - b2, b1 * u, b1 * v, -b1},
@@ -225,7 +246,7 @@ __device__ inline void rusanov_side(const T w[4], T nx, T ny, const Ref<T>& ref,
                                     T fn[4], T& sp) {
   T f[4], g[4], p, r, u, v;
   pert_flux<T>(w, ref, gm1, f, g, &p, &r, &u, &v);
-  sp = fabs(u * nx + v * ny) + fsqrt(fdiv(gam * p, r));
+  sp = fabs(u * nx + v * ny) + fsqrt(gam * p * frcp(r));
 #pragma unroll
   for (int q = 0; q < 4; ++q) fn[q] = f[q] * nx + g[q] * ny;
 }
@@ -348,7 +369,7 @@ template <class T>
 __device__ inline void viscous_flux(const T w[4], const T wx[4], const T wy[4],
                                     const GasParams& gp, T fv[4], T gv[4]) {
   const T gm1 = T(gp.gamma - 1.0);
-  const T rho = w[0], ir = fdiv(T(1), rho);
+  const T rho = w[0], ir = frcp(rho);
   const T u = w[1] * ir, v = w[2] * ir;
   const T p = gm1 * (w[3] - T(0.5) * rho * (u * u + v * v));
   const T iR = T(1.0 / gp.gas_R);
