@@ -41,6 +41,8 @@ namespace {
 // faster in float32, 2 in float64, whose registers are scarcer)
 template <class T>
 constexpr int kAdjGatherBatch = sizeof(T) == 4 ? 4 : 2;
+// edges per block of the edge reverse (two lanes each: 256 threads)
+constexpr int kAdjEdgesPerBlock = 128;
 
 // Forward-mode dual number: a value and its derivative along one direction.
 // The adjoint of the Roe and HLLC fluxes runs their code (gas.h) on it, one
@@ -183,8 +185,10 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
            const T* __restrict__ de_t, const V4<T>* __restrict__ Lv,
            const V4<T>* __restrict__ Lg, T* __restrict__ out) {
   const int s = threadIdx.x & 1;
-  const int64_t e = int64_t(blockIdx.x) * (blockDim.x / 2) + threadIdx.x / 2;
-  if (e >= ne) return;  // both lanes of a pair leave together
+  const int64_t eb = int64_t(blockIdx.x) * kAdjEdgesPerBlock;
+  // lanes past the last edge recompute the last edge (both lanes of a pair
+  // alike) and their results are not written
+  const int64_t e = eb + threadIdx.x / 2 < ne ? eb + threadIdx.x / 2 : ne - 1;
   // lambda_h(e) = - sum over the (v, s') entries whose rows read h_e of
   // de[s'] . (lambda, lambda_x, lambda_y)(v): the lanes take alternate
   // entries (transposed order, contiguous per edge; every active edge has
@@ -572,7 +576,11 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     pw5[p][1] = dpp_mov<0xB1>(w5[5 - p][2]);
     for (int k = 0; k < 4; ++k) gW[p][k] += dpp_mov<0xB1>(gW[5 - p][k]);
   }
-  T* o = out + int64_t(e) * 72;
+  // The block's rows (72 values per edge) go through LDS and out as one
+  // contiguous run: stored directly, the lanes' rows lie 72 values apart and
+  // every store instruction would touch 64 cache lines.
+  __shared__ __attribute__((aligned(16))) T obuf[kAdjEdgesPerBlock * 72];
+  T* o = obuf + (threadIdx.x / 2) * 72;
   for (int p = 0; p < 3; ++p) {
     const int j = s == 0 ? p : 5 - p;
     for (int k = 0; k < 4; ++k) {
@@ -585,6 +593,14 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       o[12 * j + 4 + k] = gx;
       o[12 * j + 8 + k] = gy;
     }
+  }
+  __syncthreads();
+  {
+    const int64_t ce = ne - eb < kAdjEdgesPerBlock ? ne - eb : kAdjEdgesPerBlock;
+    const int nvec = int(ce * 72 * int64_t(sizeof(T)) / 16);  // 72 values: whole 16-byte units
+    const uint4* src = reinterpret_cast<const uint4*>(obuf);
+    uint4* dst = reinterpret_cast<uint4*>(out + eb * 72);
+    for (int i = threadIdx.x; i < nvec; i += blockDim.x) dst[i] = src[i];
   }
 }
 
@@ -793,7 +809,7 @@ template hipError_t launch_stage_gathers<float>(int64_t, int64_t, int64_t, const
 template <class T>
 hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
   if (a.ne > 0) {
-    const dim3 grid(unsigned((2 * a.ne + 255) / 256));
+    const dim3 grid(unsigned((a.ne + kAdjEdgesPerBlock - 1) / kAdjEdgesPerBlock));
     if (a.gp.flux == HFD_FLUX_ROE)
       hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_ROE>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
                          a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
