@@ -43,6 +43,10 @@ template <class T>
 constexpr int kAdjGatherBatch = sizeof(T) == 4 ? 4 : 2;
 // edges per block of the edge reverse (two lanes each: 256 threads)
 constexpr int kAdjEdgesPerBlock = 128;
+// values per stencil node in the edge reverse's rows: (w, w_x, w_y), or w
+// alone when the switch takes WENO everywhere (the gradients get nothing)
+template <int SWM>
+constexpr int kAdjNodeValues = SWM == HFD_SWITCH_WENO_ONLY ? 4 : 12;
 
 // Forward-mode dual number: a value and its derivative along one direction.
 // The adjoint of the Roe and HLLC fluxes runs their code (gas.h) on it, one
@@ -177,13 +181,20 @@ __device__ inline T launder(T x) {
 // 0, 1, 2 and lane 1 nodes 5, 4, 3 (positions 0, 1, 2 of each lane).
 // (the Roe and HLLC variants carry the dual-number flux: one wave per SIMD,
 // the whole register file)
-template <class T, int FLUX>
+// SWM: the switch mode (hfd_switch), or kSwForced for the decisions of a
+// forced mask, fixed at compile time.
+template <class T, int FLUX, int SWM>
 __global__ void __launch_bounds__(256, FLUX == HFD_FLUX_RUSANOV ? ADJ_EDGE_WAVES : 1)
 k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
            const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
            const int32_t* __restrict__ tptr, const int32_t* __restrict__ tv,
            const T* __restrict__ de_t, const V4<T>* __restrict__ Lv,
            const V4<T>* __restrict__ Lg, T* __restrict__ out) {
+  // With WENO everywhere no Hermite value is formed: the Hermite rows are not
+  // read and the node gradients get no contribution, so each node's part of
+  // the row is its 4 value entries instead of 12.
+  constexpr bool HERM = SWM != HFD_SWITCH_WENO_ONLY;
+  constexpr int NW = kAdjNodeValues<SWM>;
   const int s = threadIdx.x & 1;
   const int64_t eb = int64_t(blockIdx.x) * kAdjEdgesPerBlock;
   // lanes past the last edge recompute the last edge (both lanes of a pair
@@ -240,7 +251,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   int id[5];
   for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
   const T eps = gp.eps;
-  const uint8_t fm = force ? force[e] : uint8_t(0);
+  const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   // The float32 form stores the perturbation w - w_ref of the values (the
   // gradients unchanged); the reverse works on the full state.
   auto full = [&](T x, int q) -> T {
@@ -336,23 +347,28 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     T A[4], B[4], sa, sb, D, pa, pb, u, v, H, cc, L[4][4], R[4][4];
     roe(A, B, sa, sb, D, pa, pb, u, v, H, cc);
     eig(u, v, H, cc, L, R);
-    T W[5][4], w5[5][3], w3[9];
+    T W[5][4], w3[9];
     load_W(W);
-    load_w5(w5);
     load_w3(w3);
-    for (int t = 0; t < 5; ++t) {
-      const V4<T> bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
-      const T X[4] = {bx.x, bx.y, bx.z, bx.w}, Y[4] = {by.x, by.y, by.z, by.w};
-      for (int q = 0; q < 4; ++q) hs[q] += w5[t][0] * W[t][q] + w5[t][1] * X[q] + w5[t][2] * Y[q];
+    if constexpr (HERM) {
+      T w5[5][3];
+      load_w5(w5);
+      for (int t = 0; t < 5; ++t) {
+        const V4<T> bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
+        const T X[4] = {bx.x, bx.y, bx.z, bx.w}, Y[4] = {by.x, by.y, by.z, by.w};
+        for (int q = 0; q < 4; ++q)
+          hs[q] += w5[t][0] * W[t][q] + w5[t][1] * X[q] + w5[t][2] * Y[q];
+      }
     }
     for (int q = 0; q < 4; ++q) {
       T cq[5], be[3], om[3], Sk[3];
       proj(L, W, q, cq);
       weno_parts(w3, cq, be, om, Sk);
       bool wq;
-      if (force) wq = (fm >> (4 * s + q)) & 1;
-      else if (gp.sw == HFD_SWITCH_PAPER) wq = !weno_in<T>(be, eps, T(gp.sw_lo), T(gp.sw_hi));
-      else wq = (gp.sw == HFD_SWITCH_WENO_ONLY);
+      if constexpr (SWM == kSwForced) wq = (fm >> (4 * s + q)) & 1;
+      else if constexpr (SWM == HFD_SWITCH_PAPER)
+        wq = !weno_in<T>(be, eps, T(gp.sw_lo), T(gp.sw_hi));
+      else wq = (SWM == HFD_SWITCH_WENO_ONLY);
       weno[q] = wq;
       C[q] = wq ? om[0] * Sk[0] + om[1] * Sk[1] + om[2] * Sk[2]
                 : L[q][0] * hs[0] + L[q][1] * hs[1] + L[q][2] * hs[2] + L[q][3] * hs[3];
@@ -520,9 +536,11 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // hs = sum_t w5 . data: the value part here, the gradient parts at output
   asm volatile("" ::: "memory");
   T w5[5][3];
-  load_w5(w5);
-  for (int t = 0; t < 5; ++t)
-    for (int k = 0; k < 4; ++k) gW[t][k] += w5[t][0] * ghs[k];
+  if constexpr (HERM) {
+    load_w5(w5);
+    for (int t = 0; t < 5; ++t)
+      for (int k = 0; k < 4; ++k) gW[t][k] += w5[t][0] * ghs[k];
+  }
   // sum over the pair in a fixed order (left part + right part)
   {
     const T ou = dpp_mov<0xB1>(gu), ov = dpp_mov<0xB1>(gv), oH = dpp_mov<0xB1>(gH),
@@ -570,36 +588,44 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // other; each lane adds the partner's contribution to its positions 1, T(2.)
   // The gradient parts are w5[t][1] ghs and w5[t][2] ghs.
   T pghs[4], pw5[3][2];
-  for (int k = 0; k < 4; ++k) pghs[k] = dpp_mov<0xB1>(ghs[k]);
+  if constexpr (HERM) {
+    for (int k = 0; k < 4; ++k) pghs[k] = dpp_mov<0xB1>(ghs[k]);
+  }
   for (int p = 1; p <= 2; ++p) {
-    pw5[p][0] = dpp_mov<0xB1>(w5[5 - p][1]);
-    pw5[p][1] = dpp_mov<0xB1>(w5[5 - p][2]);
+    if constexpr (HERM) {
+      pw5[p][0] = dpp_mov<0xB1>(w5[5 - p][1]);
+      pw5[p][1] = dpp_mov<0xB1>(w5[5 - p][2]);
+    }
     for (int k = 0; k < 4; ++k) gW[p][k] += dpp_mov<0xB1>(gW[5 - p][k]);
   }
-  // The block's rows (72 values per edge) go through LDS and out as one
-  // contiguous run: stored directly, the lanes' rows lie 72 values apart and
-  // every store instruction would touch 64 cache lines.
-  __shared__ __attribute__((aligned(16))) T obuf[kAdjEdgesPerBlock * 72];
-  T* o = obuf + (threadIdx.x / 2) * 72;
+  // The block's rows (6 NW values per edge) go through LDS and out as one
+  // contiguous run: stored directly, the lanes' rows lie 6 NW values apart
+  // and every store instruction would touch 64 cache lines.
+  constexpr int RW = 6 * NW;
+  __shared__ __attribute__((aligned(16))) T obuf[kAdjEdgesPerBlock * RW];
+  T* o = obuf + (threadIdx.x / 2) * RW;
   for (int p = 0; p < 3; ++p) {
     const int j = s == 0 ? p : 5 - p;
     for (int k = 0; k < 4; ++k) {
-      T gx = w5[p][1] * ghs[k], gy = w5[p][2] * ghs[k];
-      if (p > 0) {
-        gx += pw5[p][0] * pghs[k];
-        gy += pw5[p][1] * pghs[k];
+      o[NW * j + k] = gW[p][k];
+      if constexpr (HERM) {
+        T gx = w5[p][1] * ghs[k], gy = w5[p][2] * ghs[k];
+        if (p > 0) {
+          gx += pw5[p][0] * pghs[k];
+          gy += pw5[p][1] * pghs[k];
+        }
+        o[NW * j + 4 + k] = gx;
+        o[NW * j + 8 + k] = gy;
       }
-      o[12 * j + k] = gW[p][k];
-      o[12 * j + 4 + k] = gx;
-      o[12 * j + 8 + k] = gy;
     }
   }
   __syncthreads();
   {
     const int64_t ce = ne - eb < kAdjEdgesPerBlock ? ne - eb : kAdjEdgesPerBlock;
-    const int nvec = int(ce * 72 * int64_t(sizeof(T)) / 16);  // 72 values: whole 16-byte units
+    // (6 NW values per edge: whole 16-byte units)
+    const int nvec = int(ce * RW * int64_t(sizeof(T)) / 16);
     const uint4* src = reinterpret_cast<const uint4*>(obuf);
-    uint4* dst = reinterpret_cast<uint4*>(out + eb * 72);
+    uint4* dst = reinterpret_cast<uint4*>(out + eb * RW);
     for (int i = threadIdx.x; i < nvec; i += blockDim.x) dst[i] = src[i];
   }
 }
@@ -618,7 +644,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
 // component) the viscous flux derivative (a dual-number evaluation of the
 // viscous flux seeded at that component), and the 12 output rows are
 // written in 16-wide runs.
-template <class T, bool VISC>
+template <class T, bool VISC, int NW>
 __global__ void __launch_bounds__(256)
 k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict__ U,
              const int32_t* __restrict__ vtp, const int32_t* __restrict__ vtv,
@@ -646,12 +672,13 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
           kk[i] = ok[i] ? b + 16 * i : k1 - 1;
         }
         const T* src[2];
-        for (int i = 0; i < 2; ++i) src[i] = bnode + int64_t(nte[kk[i]]) * 72 + 12 * ntj[kk[i]];
-        T x[2][12];
         for (int i = 0; i < 2; ++i)
-          for (int q = 0; q < 12; ++q) x[i][q] = src[i][q];
+          src[i] = bnode + int64_t(nte[kk[i]]) * (6 * NW) + NW * ntj[kk[i]];
+        T x[2][NW];
         for (int i = 0; i < 2; ++i)
-          for (int q = 0; q < 12; ++q) acc[q] += ok[i] ? x[i][q] : T(0.0);
+          for (int q = 0; q < NW; ++q) x[i][q] = src[i][q];
+        for (int i = 0; i < 2; ++i)
+          for (int q = 0; q < NW; ++q) acc[q] += ok[i] ? x[i][q] : T(0.0);
       }
     }
     // (2) lambda_f (12..15), lambda_g (16..19)
@@ -806,30 +833,59 @@ template hipError_t launch_stage_gathers<float>(int64_t, int64_t, int64_t, const
                                                 const double*, const double*, const GasParams&,
                                                 const StageGathers<float>&, hipStream_t);
 
+template <class T, int FLUX>
+hipError_t launch_adj_edge(const AdjointArgs<T>& a, hipStream_t st) {
+  const dim3 grid(unsigned((a.ne + kAdjEdgesPerBlock - 1) / kAdjEdgesPerBlock));
+  const int swm = a.force ? kSwForced : a.gp.sw;
+  if (swm == kSwForced)
+    hipLaunchKernelGGL((k_adj_edge<T, FLUX, kSwForced>), grid, dim3(256), 0, st, a.ne, a.ec,
+                       a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
+  else if (swm == HFD_SWITCH_PAPER)
+    hipLaunchKernelGGL((k_adj_edge<T, FLUX, HFD_SWITCH_PAPER>), grid, dim3(256), 0, st, a.ne,
+                       a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
+  else if (swm == HFD_SWITCH_SMOOTH_ONLY)
+    hipLaunchKernelGGL((k_adj_edge<T, FLUX, HFD_SWITCH_SMOOTH_ONLY>), grid, dim3(256), 0, st,
+                       a.ne, a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg,
+                       a.bnode);
+  else if (swm == HFD_SWITCH_WENO_ONLY)
+    hipLaunchKernelGGL((k_adj_edge<T, FLUX, HFD_SWITCH_WENO_ONLY>), grid, dim3(256), 0, st,
+                       a.ne, a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg,
+                       a.bnode);
+  else
+    return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
 template <class T>
 hipError_t launch_adjoint_residual(const AdjointArgs<T>& a, hipStream_t st) {
   if (a.ne > 0) {
-    const dim3 grid(unsigned((a.ne + kAdjEdgesPerBlock - 1) / kAdjEdgesPerBlock));
-    if (a.gp.flux == HFD_FLUX_ROE)
-      hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_ROE>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
-                         a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
-    else if (a.gp.flux == HFD_FLUX_HLLC)
-      hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_HLLC>), grid, dim3(256), 0, st, a.ne, a.ec, a.gp,
-                         a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
-    else
-      hipLaunchKernelGGL((k_adj_edge<T, HFD_FLUX_RUSANOV>), grid, dim3(256), 0, st, a.ne, a.ec,
-                         a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
+    hipError_t err;
+    if (a.gp.flux == HFD_FLUX_ROE) err = launch_adj_edge<T, HFD_FLUX_ROE>(a, st);
+    else if (a.gp.flux == HFD_FLUX_HLLC) err = launch_adj_edge<T, HFD_FLUX_HLLC>(a, st);
+    else err = launch_adj_edge<T, HFD_FLUX_RUSANOV>(a, st);
+    if (err != hipSuccess) return err;
   }
   if (a.nowned > 0) {
     const dim3 grid(unsigned((a.nowned + 15) / 16));
-    if (a.dvis_t)
-      hipLaunchKernelGGL((k_adj_vertex<T, true>), grid, dim3(256), 0, st, a.nowned, a.nv, a.gp,
-                         a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode, a.Lv,
-                         a.Lg, a.out, a.rc);
+    // the edge reverse's row layout follows its switch mode
+    const bool compact = !a.force && a.gp.sw == HFD_SWITCH_WENO_ONLY;
+    constexpr int NC = kAdjNodeValues<HFD_SWITCH_WENO_ONLY>, NF = kAdjNodeValues<kSwForced>;
+    if (a.dvis_t && compact)
+      hipLaunchKernelGGL((k_adj_vertex<T, true, NC>), grid, dim3(256), 0, st, a.nowned, a.nv,
+                         a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode,
+                         a.Lv, a.Lg, a.out, a.rc);
+    else if (a.dvis_t)
+      hipLaunchKernelGGL((k_adj_vertex<T, true, NF>), grid, dim3(256), 0, st, a.nowned, a.nv,
+                         a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode,
+                         a.Lv, a.Lg, a.out, a.rc);
+    else if (compact)
+      hipLaunchKernelGGL((k_adj_vertex<T, false, NC>), grid, dim3(256), 0, st, a.nowned, a.nv,
+                         a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode,
+                         a.Lv, a.Lg, a.out, a.rc);
     else
-      hipLaunchKernelGGL((k_adj_vertex<T, false>), grid, dim3(256), 0, st, a.nowned, a.nv, a.gp,
-                         a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode, a.Lv,
-                         a.Lg, a.out, a.rc);
+      hipLaunchKernelGGL((k_adj_vertex<T, false, NF>), grid, dim3(256), 0, st, a.nowned, a.nv,
+                         a.gp, a.U, a.vtp, a.vtv, a.dv_t, a.dvis_t, a.ntp, a.nte, a.ntj, a.bnode,
+                         a.Lv, a.Lg, a.out, a.rc);
   }
   return hipGetLastError();
 }

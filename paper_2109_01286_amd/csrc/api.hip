@@ -264,9 +264,12 @@ void byte_model(hfd_ctx* c) {
   // edge pass: ids, direction + Hermite + 3-node weights, the stage state
   // (12 values per vertex), flux out.  Both kernels read the 3-node rows of
   // a side only when the side takes that branch somewhere: those bytes are
-  // per side (data-dependent), except with WENO everywhere.
+  // per side (data-dependent).  With WENO everywhere they are always read,
+  // and neither the Hermite rows nor the gradients are.
   const bool w3_lazy = c->o.switch_mode != HFD_SWITCH_WENO_ONLY;
-  I.bytes_edge_launch = ne * (6 * 4 + (w3_lazy ? 32 : 50) * s + 4 * s) + nv * 12 * s;
+  const double rows = w3_lazy ? 32 : 20;  // direction (2) + Hermite (30) | 3-node (18)
+  const double state = w3_lazy ? 12 : 4;
+  I.bytes_edge_launch = ne * (6 * 4 + rows * s + 4 * s) + nv * state * s;
   I.bytes_edge_w3_side = w3_lazy ? 9 * s : 0.0;
   // vertex pass: CSR offsets and ids, coefficient records, state (values,
   // plus gradients with viscosity), edge fluxes, float64 RK update

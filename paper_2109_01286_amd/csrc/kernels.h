@@ -9,6 +9,10 @@
 
 namespace hfd {
 
+// Switch mode of the edge kernels when a forced mask gives the decisions
+// (beside the hfd_switch values, which are the other modes).
+constexpr int kSwForced = 3;
+
 // ---- lane primitives (device) -----------------------------------------------
 // Lane exchange through DPP (a VALU move, no LDS traffic).  0x140 mirrors a
 // row of 16 lanes (the partner differs in bit 3 of the lane index), 0x141

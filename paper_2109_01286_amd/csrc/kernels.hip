@@ -87,13 +87,16 @@ __device__ inline int64_t xcd_block() {
 // ---------------------------------------------------------------------------
 // Switch of one characteristic component q of side s from the smoothness
 // indicators be of its five projected node values: true for the
-// omega-weighted 3-node values, false for the 5-node Hermite value.
-template <class T>
+// omega-weighted 3-node values, false for the 5-node Hermite value.  SWM is
+// the switch mode (hfd_switch) or kSwForced (the bits fm of a forced mask),
+// fixed at compile time so that the edge kernels carry no branches on it.
+template <class T, int SWM>
 __device__ inline bool comp_switch(const T be[3], const GasParams& gp, int s, int q,
-                                   bool forced, uint8_t fm) {
-  if (forced) return (fm >> (4 * s + q)) & 1;
-  if (gp.sw == HFD_SWITCH_PAPER) return !weno_in<T>(be, T(gp.eps), T(gp.sw_lo), T(gp.sw_hi));
-  return gp.sw == HFD_SWITCH_WENO_ONLY;
+                                   uint8_t fm) {
+  if constexpr (SWM == kSwForced) return (fm >> (4 * s + q)) & 1;
+  else if constexpr (SWM == HFD_SWITCH_PAPER)
+    return !weno_in<T>(be, T(gp.eps), T(gp.sw_lo), T(gp.sw_hi));
+  else return SWM == HFD_SWITCH_WENO_ONLY;
 }
 
 // Interface value of one characteristic component: the omega-weighted 3-node
@@ -118,13 +121,12 @@ __device__ inline void back_project(const Frame<T>& F, const T C[4], T out[4]) {
 }
 
 // One side's decisions (bits 4 s + q) from its indicators.
-template <class T>
-__device__ inline uint8_t side_decide(const T be[4][3], const GasParams& gp, int s,
-                                      bool forced, uint8_t fm) {
+template <class T, int SWM>
+__device__ inline uint8_t side_decide(const T be[4][3], const GasParams& gp, int s, uint8_t fm) {
   uint8_t bits = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
-    bits |= uint8_t(comp_switch<T>(be[q], gp, s, q, forced, fm) ? 1 : 0) << (4 * s + q);
+    bits |= uint8_t(comp_switch<T, SWM>(be[q], gp, s, q, fm) ? 1 : 0) << (4 * s + q);
   return bits;
 }
 
@@ -186,7 +188,7 @@ template <> struct Edge2Waves<float> { static constexpr int value = HFD_EDGE2_WA
 // and serve both sides: the left state interpolates from nodes 0..4
 // (i-2 .. i+2), the right state from nodes 5..1 (i+3 .. i-1).  All loads of
 // an edge are issued before its arithmetic.
-template <class T>
+template <class T, int SWM>
 __global__ void __launch_bounds__(256, EdgeWaves<T>::value)
 k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
@@ -207,14 +209,13 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
   for (int t = 0; t < 6; ++t) id[t] = *at(c.stg, t * ne + e0, li);
   const T nx = row(c.n, 0), ny = row(c.n, 1);
-  const bool forced = force != nullptr;
   T w5[2][15];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
 #pragma unroll
     for (int j = 0; j < 15; ++j) w5[s][j] = row(c.w5, s * 15 + j);
   }
-  const uint8_t fm = forced ? force[e] : uint8_t(0);
+  const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   T w[6][4], wx[6][4], wy[6][4];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
@@ -265,7 +266,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
       for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][s == 0 ? p : 5 - p];
     }
-    const uint8_t b = side_decide<T>(be[s], gp, s, forced, fm);
+    const uint8_t b = side_decide<T, SWM>(be[s], gp, s, fm);
     side_state<T>(b, s, be[s], c5, hs[s], F, gp, [&](int j) { return row(c.w3, s * 9 + j); },
                   s == 0 ? wl : wr);
     bits |= b;
@@ -284,7 +285,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 // other end for the Roe average (node j = 2 of both lanes); the pair then
 // swaps the interface states and both evaluate the flux (lane 0 stores it).
 // All exchanges are DPP moves between lanes 2k and 2k+1.
-template <class T>
+template <class T, int SWM>
 __global__ void __launch_bounds__(256, Edge2Waves<T>::value)
 k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
@@ -308,8 +309,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   for (int j = 0; j < 3; ++j)
     id[j] = s == 0 ? *at(c.stg, j * ne + e0, li) : *at(c.stg, (5 - j) * ne + e0, li);
   const T nx = row(c.n, 0), ny = row(c.n, 1);
-  const bool forced = force != nullptr;
-  const uint8_t fm = forced ? force[e] : uint8_t(0);
+  const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   // Hermite rows: own side at its nodes 0..2; other side at its nodes 3 + m,
   // which are own nodes j = 2 - m (m = 0, 1)
   T wo[9], wt[6];
@@ -379,7 +379,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   T be[4][3];
 #pragma unroll
   for (int q = 0; q < 4; ++q) weno_beta<T>(cv[q], be[q]);
-  const uint8_t b = side_decide<T>(be, gp, s, forced, fm);
+  const uint8_t b = side_decide<T, SWM>(be, gp, s, fm);
   T wm[4];
   side_state<T>(b, s, be, cv, hs, F, gp, [&](int j) { return row2(c.w3, j, 9 + j); }, wm);
   T wl[4], wr[4];
@@ -911,18 +911,34 @@ inline unsigned nblocks(int64_t n, int bs) { return unsigned((n + bs - 1) / bs);
 
 }  // namespace
 
+template <class T, int SWM>
+void launch_edge_swm(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp, const V4<T>* Gv,
+                     const V4<T>* Gg, const uint8_t* force, V4<T>* H, double* hsoa,
+                     double* wlr, uint8_t* mask, hipStream_t st) {
+  // float: one lane per edge; double: two (one per side), register budget
+  if constexpr (sizeof(T) == 8 || HFD_EDGE32_TWO_LANES)
+    hipLaunchKernelGGL((k_edge2<T, SWM>), dim3(nblocks(2 * ne, 256)), dim3(256), 0, st, ne, c,
+                       gp, Gv, Gg, force, H, hsoa, wlr, mask);
+  else
+    hipLaunchKernelGGL((k_edge1<T, SWM>), dim3(nblocks(ne, 256)), dim3(256), 0, st, ne, c, gp,
+                       Gv, Gg, force, H, hsoa, wlr, mask);
+}
+
 template <class T>
 hipError_t launch_edge(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp,
                        const V4<T>* Gv, const V4<T>* Gg, const uint8_t* force, V4<T>* H,
                        double* hsoa, double* wlr, uint8_t* mask, hipStream_t st) {
   if (ne == 0) return hipSuccess;
-  // float: one lane per edge; double: two (one per side), register budget
-  if constexpr (sizeof(T) == 8 || HFD_EDGE32_TWO_LANES)
-    hipLaunchKernelGGL(k_edge2<T>, dim3(nblocks(2 * ne, 256)), dim3(256), 0, st, ne, c, gp,
-                       Gv, Gg, force, H, hsoa, wlr, mask);
+  if (force)
+    launch_edge_swm<T, kSwForced>(ne, c, gp, Gv, Gg, force, H, hsoa, wlr, mask, st);
+  else if (gp.sw == HFD_SWITCH_PAPER)
+    launch_edge_swm<T, HFD_SWITCH_PAPER>(ne, c, gp, Gv, Gg, force, H, hsoa, wlr, mask, st);
+  else if (gp.sw == HFD_SWITCH_SMOOTH_ONLY)
+    launch_edge_swm<T, HFD_SWITCH_SMOOTH_ONLY>(ne, c, gp, Gv, Gg, force, H, hsoa, wlr, mask, st);
+  else if (gp.sw == HFD_SWITCH_WENO_ONLY)
+    launch_edge_swm<T, HFD_SWITCH_WENO_ONLY>(ne, c, gp, Gv, Gg, force, H, hsoa, wlr, mask, st);
   else
-    hipLaunchKernelGGL(k_edge1<T>, dim3(nblocks(ne, 256)), dim3(256), 0, st, ne, c, gp, Gv,
-                       Gg, force, H, hsoa, wlr, mask);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 template hipError_t launch_edge<double>(int64_t, const EdgeCoef<double>&, const GasParams&,
