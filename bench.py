@@ -621,6 +621,10 @@ def main():
                                  if main_prec == "fp32" else None)},
         "kernels": kern,
     }
+    if main_prec == "fp32":
+        # counter traffic of the float32 passes, when taken for this source
+        for k, name in (("edge", "k_edge1<float"), ("vertex", "k_vertex<float")):
+            kern[k]["traffic"] = measured_traffic(a.workload, name)
     if variants:
         out["flux_variants"] = variants
     if "fp64" in res and main_prec == "fp32":

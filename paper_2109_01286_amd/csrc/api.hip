@@ -95,6 +95,7 @@ struct hfd_ctx {
   int32_t *gsp = nullptr, *gsr = nullptr, *gsg = nullptr;  // copy source -> ghosts
   int64_t n_gsrc = 0;
   double *bnode = nullptr, *AL1 = nullptr, *AL2 = nullptr, *AL3 = nullptr;
+  uint8_t* adj_mask = nullptr;  // the forward's switch decisions at the state being reversed
   double *de_t = nullptr, *dv_t = nullptr, *dvis_t = nullptr;  // rows in transposed order
   // float32 adjoint (mixed form, allocated at its first use)
   bool adj_coef32_ready = false;             // fde_t, fdv_t match de_t, dv_t
@@ -609,7 +610,8 @@ hfd_status ensure_adjoint(hfd_ctx* c) {
     if ((s = upload(c, &c->gsp, sp)) || (s = upload(c, &c->gsr, sr)) || (s = upload(c, &c->gsg, sg)))
       return s;
   }
-  if ((s = dalloc(c, &c->bnode, 72 * ne)) || (s = dalloc(c, &c->AL1, 12 * nv)) ||
+  if ((s = dalloc(c, &c->bnode, 72 * ne)) || (s = dalloc(c, &c->adj_mask, ne)) ||
+      (s = dalloc(c, &c->AL1, 12 * nv)) ||
       (s = dalloc(c, &c->AL2, 12 * nv)) || (s = dalloc(c, &c->AL3, 12 * nv)) ||
       (s = dalloc(c, &c->LGv[0], nv)) || (s = dalloc(c, &c->LGg[0], 2 * nv)) ||
       (s = dalloc(c, &c->LGv[1], nv)) || (s = dalloc(c, &c->LGg[1], 2 * nv)))
@@ -690,6 +692,16 @@ hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<T>* Gv,
   a.gp = gas_params(c, f32);
   a.Gv = Gv; a.Gg = Gg;
   a.force = c->force;
+  // The paper switch's decisions are the forward edge pass's at this state:
+  // that kernel writes them (its fluxes go to the edge-flux work buffer) and
+  // the reverse takes them as a forced mask, so that it differentiates the
+  // branches the forward took, also where its own arithmetic would put
+  // omega_1 on the other side of a threshold (float32 rounding).
+  if (!c->force && c->o.switch_mode == HFD_SWITCH_PAPER) {
+    HIPCHK(c, hfd::launch_edge<T>(h.ne, a.ec, a.gp, Gv, Gg, nullptr, bufs<T>(c).H, nullptr,
+                                  nullptr, c->adj_mask, st));
+    a.force = c->adj_mask;
+  }
   a.U = U;
   a.vtp = c->vtp; a.vtv = c->vtv;
   a.ntp = c->ntp; a.nte = c->nte; a.ntj = c->ntj;
