@@ -7,6 +7,9 @@
 // characteristic component the WENO5 smoothness indicators and the switch,
 // the 5-node Hermite value (15-term dot product with the stored row) or the
 // omega-weighted 3-node values, back-projection, Riemann flux along the edge.
+// Each edge kernel is compiled once per switch mode (the paper's switch,
+// Hermite everywhere, WENO everywhere, a forced mask): no run-time branches
+// on the mode, and no work that the mode does not need.
 //
 // Vertex pass (eq. flux_polynomials and the rows d0, dx, dy; viscous
 // vertex-only rows; three-stage TVD Runge-Kutta): a block of 16 owned
