@@ -448,6 +448,50 @@ def adjoint_ratio(steps=200, ckpt=20):
             "grad_finite": bool(torch.isfinite(g).all().item()), "fd_check": fd}
 
 
+def graph_line(steps=200, chunk=20):
+    """Forward steps on the vortex 257 x 257 lattice (65 536 vertices: each
+    launch takes a few tens of microseconds, so launch overheads show),
+    issued from the host `chunk` steps per library call, against the same
+    chunk captured once in a HIP graph (Solver.capture_steps) and replayed.
+    WENO everywhere with the 3-node cap, device-side CFL 0.3 time steps; both
+    runs start from the initial state and must end in the same state."""
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+    m, U, prm = inputs.workload("vortex257")
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, switch="weno", w3_cap=2.0)
+    out = {"workload": "vortex257", "steps": steps, "steps_per_call": chunk}
+    for prec in ("fp64", "fp32"):
+        if prec == "fp32":
+            S.set_precision("fp32", U[0:4, m.ghost_src == -1].mean(axis=1))
+        X0 = torch.as_tensor(S.to_internal(U), device="cuda:0")
+        dts = torch.empty(chunk, dtype=torch.float64, device="cuda:0")
+        X = X0.clone()
+        S.rk_steps(X, chunk, 0.3, dts)
+        X.copy_(X0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // chunk):
+            S.rk_steps(X, chunk, 0.3, dts)
+        torch.cuda.synchronize()
+        t_eager = time.perf_counter() - t0
+        Y = X0.clone()
+        g = S.capture_steps(Y, chunk, 0.3, dts)
+        g.replay()
+        Y.copy_(X0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // chunk):
+            g.replay()
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t0
+        S.check()
+        out[prec] = {"eager_ms_per_step": t_eager / steps * 1e3,
+                     "graph_ms_per_step": t_graph / steps * 1e3,
+                     "same_final_state": bool(torch.equal(X, Y))}
+    return out
+
+
 def viscous_line(steps=12, warmup=1):
     """Throughput of the viscous path on the Taylor-Green recipe at 513 x 513
     (262 k vertices, about the one-GPU share of the shock-vortex mesh split
@@ -518,6 +562,7 @@ def main():
     ap.add_argument("--no-viscous", action="store_true")
     ap.add_argument("--no-flux-variants", action="store_true")
     ap.add_argument("--no-config-errors", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (a "
                          "known-size kernel for calibrating HBM byte counters)")
@@ -656,6 +701,11 @@ def main():
                           " (perturbation rounding " +
                           "/".join(f"{x:.1e}" for x in v['pert_rounding_rel_l2_blocks']) + ")"
                           for k, v in r.items()))
+    if not a.no_graph:
+        section("graph", graph_line, lambda r: "[bench] HIP graph (vortex257, 20 steps per "
+                "call): " + ", ".join(f"{p} {r[p]['eager_ms_per_step']:.3f} ms/step eager, "
+                                      f"{r[p]['graph_ms_per_step']:.3f} replayed"
+                                      for p in ("fp64", "fp32")))
     if not a.no_viscous:
         section("viscous", viscous_line, lambda v: "[bench] viscous (tgv513): " + ", ".join(
             f"{p} {v[p]['value'] / 1e9:.3f} G vertex-stage/s, vertex "

@@ -365,6 +365,23 @@ class Solver:
         self._chk(lib().hfd_rk_steps(self._h, pU, nsteps, float(cfl), pd, _stream()))
         return dts
 
+    def capture_steps(self, U, nsteps, cfl, dts):
+        """A HIP graph (torch.cuda.CUDAGraph) of ``nsteps`` x (device-side
+        time step, Runge-Kutta step) on U in place, the step sizes going to
+        dts[:nsteps]: ``g.replay()`` runs them again on the same buffers,
+        with one launch from the host.  The library's kernels are all that is
+        captured (the call allocates, copies and clears nothing), so the
+        pass timing must be off.  Nothing runs at capture."""
+        import torch
+        if getattr(self, "_timing", False):
+            raise ValueError("capture_steps: pass timing is on (set_timing(False))")
+        self._state(U)
+        self._dev(dts, "dts", min_numel=max(int(nsteps), 1))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.rk_steps(U, nsteps, cfl, dts)
+        return g
+
     def stable_dt(self, U, cfl, out=None):
         """Device tensor [1] with cfl * min h/(|u|+c) (no host sync)."""
         import torch
@@ -452,6 +469,7 @@ class Solver:
 
     def set_timing(self, on=True):
         self._chk(lib().hfd_set_timing(self._h, int(bool(on))))
+        self._timing = bool(on)
 
     def kernel_times(self):
         """(edge_ms_total, n_edge, vertex_ms_total, n_vertex) since last call."""
