@@ -52,6 +52,20 @@
 #ifndef HFD_EDGE32_TWO_LANES
 #define HFD_EDGE32_TWO_LANES 0 // 1: the float32 edge pass uses the two-lane kernel
 #endif
+// vertex and edge slots per lane and batch of the vertex pass (16 lanes per
+// vertex), per precision
+#ifndef HFD_VERTEX_NVS32
+#define HFD_VERTEX_NVS32 2
+#endif
+#ifndef HFD_VERTEX_NES32
+#define HFD_VERTEX_NES32 4
+#endif
+#ifndef HFD_VERTEX_NVS64
+#define HFD_VERTEX_NVS64 1
+#endif
+#ifndef HFD_VERTEX_NES64
+#define HFD_VERTEX_NES64 3
+#endif
 #ifndef HFD_XCD_REMAP
 #define HFD_XCD_REMAP 1       // 1: contiguous block ranges per XCD
 #endif
@@ -557,8 +571,8 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
   static_assert(IB == 0 || VPB == kStageVertices, "staged lists are per 16 vertices");
   // slots per lane and iteration: every load of a batch is issued before any
   // of its data is used
-  constexpr int NVS = VL == 16 ? 2 : 3;   // vertex slots
-  constexpr int NES = VL == 16 ? 4 : 6;   // edge slots
+  constexpr int NVS = VL != 16 ? 3 : sizeof(T) == 4 ? HFD_VERTEX_NVS32 : HFD_VERTEX_NVS64;
+  constexpr int NES = VL != 16 ? 6 : sizeof(T) == 4 ? HFD_VERTEX_NES32 : HFD_VERTEX_NES64;
   __shared__ double sres[VPB][13];
   const int t = threadIdx.x;
   const int vl = t / VL, sub = t & (VL - 1);
