@@ -60,6 +60,12 @@
 #ifndef HFD_VERTEX_NES32
 #define HFD_VERTEX_NES32 4
 #endif
+#ifndef HFD_VERTEX_NVS32V
+#define HFD_VERTEX_NVS32V 1   // (float32 with the viscous rows)
+#endif
+#ifndef HFD_VERTEX_NES32V
+#define HFD_VERTEX_NES32V 4
+#endif
 #ifndef HFD_VERTEX_NVS64
 #define HFD_VERTEX_NVS64 1
 #endif
@@ -571,8 +577,12 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
   static_assert(IB == 0 || VPB == kStageVertices, "staged lists are per 16 vertices");
   // slots per lane and iteration: every load of a batch is issued before any
   // of its data is used
-  constexpr int NVS = VL != 16 ? 3 : sizeof(T) == 4 ? HFD_VERTEX_NVS32 : HFD_VERTEX_NVS64;
-  constexpr int NES = VL != 16 ? 6 : sizeof(T) == 4 ? HFD_VERTEX_NES32 : HFD_VERTEX_NES64;
+  constexpr int NVS = VL != 16 ? 3
+                      : sizeof(T) == 4 ? (VISC ? HFD_VERTEX_NVS32V : HFD_VERTEX_NVS32)
+                                       : HFD_VERTEX_NVS64;
+  constexpr int NES = VL != 16 ? 6
+                      : sizeof(T) == 4 ? (VISC ? HFD_VERTEX_NES32V : HFD_VERTEX_NES32)
+                                       : HFD_VERTEX_NES64;
   __shared__ double sres[VPB][13];
   const int t = threadIdx.x;
   const int vl = t / VL, sub = t & (VL - 1);
