@@ -15,6 +15,11 @@
 #include "kernels.h"
 #include "setup.h"
 
+// Stage a two-lane edge-pass block's stencil rows in LDS (0: gather every
+// node from HBM).
+#ifndef HFD_EDGE_STAGE
+#define HFD_EDGE_STAGE 1
+#endif
 // Stage a vertex-pass block's neighbour data in LDS (0: gather every slot
 // from HBM).
 #ifndef HFD_VERTEX_STAGE
@@ -46,6 +51,10 @@ struct hfd_ctx {
 
   // float64 coefficients
   int32_t* stg = nullptr;
+  // staging lists of the two-lane edge kernel (null: not staged)
+  int32_t *erp = nullptr, *erow = nullptr;
+  uint16_t* epos = nullptr;
+  int e_max_rows = 0;
   double *n = nullptr, *w5 = nullptr, *w3 = nullptr;
   double *w5g = nullptr, *w3g = nullptr;  // midpoint-derivative rows (edge_grad)
   uint8_t* gmask = nullptr;               // branch mask for them when none is asked
@@ -257,6 +266,49 @@ void build_stage(hfd_ctx* c) {
                         g.base.size());
 }
 
+// Staging lists of the two-lane edge kernel: per block of kEdgeStageEdges
+// consecutive edges the sorted distinct rows of their six stencil nodes,
+// and per stencil node (SoA [6][ne]) its position in its block's list.
+// Empty when a block's rows would not fit the LDS budget.
+void edge_stage_lists(const hfd::HostSetup& h, std::vector<int32_t>& rp,
+                      std::vector<int32_t>& rows, std::vector<uint16_t>& pos, int& longest) {
+  const int64_t ne = h.ne, eb = hfd::kEdgeStageEdges, nb = (ne + eb - 1) / eb;
+  std::vector<std::vector<int32_t>> bl;
+  bl.resize(size_t(nb));
+  pos.assign(size_t(6 * ne), 0);
+  int tl[16] = {0};
+  hfd::parallel_for(nb, [&](int64_t b0, int64_t b1, unsigned t) {
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t e0 = b * eb, e1 = std::min(ne, e0 + eb);
+      std::vector<int32_t>& L = bl[size_t(b)];
+      L.clear();
+      for (int j = 0; j < 6; ++j)
+        for (int64_t e = e0; e < e1; ++e) L.push_back(h.e_stg[j * ne + e]);
+      std::sort(L.begin(), L.end());
+      L.erase(std::unique(L.begin(), L.end()), L.end());
+      for (int j = 0; j < 6; ++j)
+        for (int64_t e = e0; e < e1; ++e)
+          pos[size_t(j * ne + e)] = uint16_t(
+              std::lower_bound(L.begin(), L.end(), h.e_stg[j * ne + e]) - L.begin());
+      tl[t] = std::max(tl[t], int(L.size()));
+    }
+  });
+  longest = *std::max_element(tl, tl + 16);
+  // 3 records of 4 float64 per row; 64 KB of LDS at most
+  if (longest * 3 * 32 > 64 * 1024) {
+    rp.clear();
+    rows.clear();
+    pos.clear();
+    longest = 0;
+    return;
+  }
+  rp.assign(size_t(nb + 1), 0);
+  for (int64_t b = 0; b < nb; ++b) rp[b + 1] = rp[b] + int32_t(bl[size_t(b)].size());
+  rows.resize(size_t(rp[nb]));
+  for (int64_t b = 0; b < nb; ++b)
+    std::copy(bl[size_t(b)].begin(), bl[size_t(b)].end(), rows.begin() + rp[b]);
+}
+
 void byte_model(hfd_ctx* c) {
   hfd_info& I = c->info;
   const double s = mixed(c) ? 4.0 : 8.0;
@@ -327,8 +379,12 @@ hfd_status ensure_mixed_buffers(hfd_ctx* c) {
   return HFD_OK;
 }
 
-hfd::EdgeCoef<double> ecoef64(const hfd_ctx* c) { return {c->stg, c->n, c->w5, c->w3}; }
-hfd::EdgeCoef<float> ecoef32(const hfd_ctx* c) { return {c->stg, c->fn, c->fw5, c->fw3}; }
+hfd::EdgeCoef<double> ecoef64(const hfd_ctx* c) {
+  return {c->stg, c->n, c->w5, c->w3, c->erp, c->erow, c->epos, c->e_max_rows};
+}
+hfd::EdgeCoef<float> ecoef32(const hfd_ctx* c) {
+  return {c->stg, c->fn, c->fw5, c->fw3, c->erp, c->erow, c->epos, c->e_max_rows};
+}
 hfd::VertexCoef<double> vcoef64(const hfd_ctx* c) {
   const auto& g = c->stage;
   return {c->vptr, c->eptr, c->vg,   c->ve,   c->dv,        c->de,       c->dvis,
@@ -862,6 +918,14 @@ hfd_status hfd_create(const double* xy, int64_t nv, const int32_t* tri, int64_t 
       (s = upload(c, &d_vh, h.v_h)) ||
       (s = upload(c, &d_vptr64, h.vptr)) || (s = upload(c, &d_eptr64, h.eptr)))
     return bail(s);
+  if (HFD_EDGE_STAGE && !op.stage_off && ne > 0) {
+    std::vector<int32_t> erp, erow;
+    std::vector<uint16_t> epos;
+    edge_stage_lists(h, erp, erow, epos, c->e_max_rows);
+    if (!erp.empty() && ((s = upload(c, &c->erp, erp)) || (s = upload(c, &c->erow, erow)) ||
+                         (s = upload(c, &c->epos, epos))))
+      return bail(s);
+  }
   if (c->stage.idx_bytes) {
     auto& g = c->stage;
     if ((s = upload(c, &c->hrp, g.rp)) || (s = upload(c, &c->hrow, g.rows)) ||

@@ -82,7 +82,15 @@ struct EdgeCoef {
   const T* n;           // [2][ne]
   const T* w5;          // [2][15][ne]
   const T* w3;          // [2][3][3][ne]
+  // staging lists of the two-lane edge kernel (null: gathers from HBM): per
+  // block of kEdgeStageEdges edges the sorted distinct stencil rows
+  // (erow[erp[b] .. erp[b+1])), per stencil node its position in that list
+  const int32_t* erp = nullptr;
+  const int32_t* erow = nullptr;
+  const uint16_t* epos = nullptr;  // [6][ne]
+  int max_rows = 0;                // longest list
 };
+constexpr int kEdgeStageEdges = 128;
 
 template <class T>
 struct VertexCoef {

@@ -72,6 +72,9 @@
 #ifndef HFD_VERTEX_NES64
 #define HFD_VERTEX_NES64 3
 #endif
+#ifndef HFD_EDGE1_STAGE
+#define HFD_EDGE1_STAGE 1     // 1: the one-lane edge kernel stages its stencil rows in LDS
+#endif
 #ifndef HFD_XCD_REMAP
 #define HFD_XCD_REMAP 1       // 1: contiguous block ranges per XCD
 #endif
@@ -201,6 +204,10 @@ __device__ inline void store_edge(int64_t ne, int64_t e, const T h[4], const T w
   }
 }
 
+// Dynamic LDS of the staging kernels (the edge pass's stencil rows, the
+// vertex pass's state rows and edge fluxes).
+extern __shared__ __attribute__((aligned(32))) unsigned char hfd_stage_lds[];
+
 // Waves per SIMD each edge kernel is compiled for (register budget 512/waves).
 template <class T> struct EdgeWaves { static constexpr int value = 2; };
 template <> struct EdgeWaves<float> { static constexpr int value = HFD_EDGE_WAVES; };
@@ -211,26 +218,35 @@ template <> struct Edge2Waves<float> { static constexpr int value = HFD_EDGE2_WA
 // and serve both sides: the left state interpolates from nodes 0..4
 // (i-2 .. i+2), the right state from nodes 5..1 (i+3 .. i-1).  All loads of
 // an edge are issued before its arithmetic.
-template <class T, int SWM>
+// STG: blocks of kEdgeStageEdges edges first copy their distinct stencil
+// rows to LDS, and the lanes read their nodes there by 2-byte position.
+template <class T, int SWM, bool STG>
 __global__ void __launch_bounds__(256, EdgeWaves<T>::value)
 k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
         V4<T>* __restrict__ H, double* __restrict__ hsoa, double* __restrict__ wlr,
         uint8_t* __restrict__ mask) {
   const int64_t e0 = xcd_block() * blockDim.x;
-  const int64_t e = e0 + threadIdx.x;
-  if (e >= ne) return;
+  int64_t e = e0 + threadIdx.x;
+  if constexpr (!STG) {
+    if (e >= ne) return;
+  } else {
+    if (e >= ne) e = ne - 1;  // (reaches the staging barrier, stores nothing)
+  }
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
   // Row r of a [rows][ne] coefficient array at this edge: the row base of the
   // block is uniform, the lane adds a 32-bit byte offset (one register for
   // all rows).
-  const uint32_t lo = threadIdx.x * uint32_t(sizeof(T));
-  const uint32_t li = threadIdx.x * 4u;
+  const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
+  const uint32_t li = uint32_t(e - e0) * 4u;
   auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
   int id[6];
 #pragma unroll
-  for (int t = 0; t < 6; ++t) id[t] = *at(c.stg, t * ne + e0, li);
+  for (int t = 0; t < 6; ++t) {
+    if constexpr (STG) id[t] = *at(c.epos, t * ne + e0, 2u * uint32_t(e - e0));
+    else id[t] = *at(c.stg, t * ne + e0, li);
+  }
   const T nx = row(c.n, 0), ny = row(c.n, 1);
   T w5[2][15];
 #pragma unroll
@@ -239,10 +255,34 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     for (int j = 0; j < 15; ++j) w5[s][j] = row(c.w5, s * 15 + j);
   }
   const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
+  V4<T>* lv = reinterpret_cast<V4<T>*>(hfd_stage_lds);  // (staged: [rows][3] w, w_x, w_y)
+  if constexpr (STG) {
+    const int64_t b = e0 / kEdgeStageEdges;
+    const int r0 = c.erp[b], nr = c.erp[b + 1] - r0;
+    for (int k = int(threadIdx.x); k < nr; k += int(blockDim.x)) {
+      const int64_t rw = c.erow[r0 + k];
+      lv[3 * k] = Gv[rw];
+      if constexpr (SWM != HFD_SWITCH_WENO_ONLY) {  // (WENO everywhere reads no gradient)
+        lv[3 * k + 1] = Gg[2 * rw];
+        lv[3 * k + 2] = Gg[2 * rw + 1];
+      }
+    }
+    __syncthreads();
+  }
   T w[6][4], wx[6][4], wy[6][4];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
-    const V4<T> a = Gv[id[t]], bx = Gg[2 * int64_t(id[t])], by = Gg[2 * int64_t(id[t]) + 1];
+    const int64_t i = id[t];
+    V4<T> a, bx, by;
+    if constexpr (STG) {
+      a = lv[3 * i];
+      bx = lv[3 * i + 1];
+      by = lv[3 * i + 2];
+    } else {
+      a = Gv[i];
+      bx = Gg[2 * i];
+      by = Gg[2 * i + 1];
+    }
     w[t][0] = a.x, w[t][1] = a.y, w[t][2] = a.z, w[t][3] = a.w;
     wx[t][0] = bx.x, wx[t][1] = bx.y, wx[t][2] = bx.z, wx[t][3] = bx.w;
     wy[t][0] = by.x, wy[t][1] = by.y, wy[t][2] = by.z, wy[t][3] = by.w;
@@ -296,7 +336,8 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   }
   T h[4];
   riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
-  store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, true, true);
+  const bool real = !STG || e0 + int64_t(threadIdx.x) < ne;
+  store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, real, real);
 }
 
 // Two lanes per edge, lane s interpolating side s.  Each stencil node is
@@ -308,7 +349,9 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 // other end for the Roe average (node j = 2 of both lanes); the pair then
 // swaps the interface states and both evaluate the flux (lane 0 stores it).
 // All exchanges are DPP moves between lanes 2k and 2k+1.
-template <class T, int SWM>
+// STG: the block's distinct stencil rows (values and gradients) are first
+// copied to LDS, and the lanes read their nodes there by 2-byte position.
+template <class T, int SWM, bool STG>
 __global__ void __launch_bounds__(256, Edge2Waves<T>::value)
 k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
@@ -316,21 +359,32 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
         uint8_t* __restrict__ mask) {
   const int64_t e0 = xcd_block() * (blockDim.x / 2);
   const int s = int(threadIdx.x & 1);
-  const int64_t e = e0 + threadIdx.x / 2;
-  if (e >= ne) return;  // (both lanes of an edge leave together)
+  int64_t e = e0 + threadIdx.x / 2;
+  if constexpr (!STG) {
+    if (e >= ne) return;  // (both lanes of an edge leave together)
+  } else {
+    // every thread reaches the staging barrier: lanes past the last edge
+    // recompute it and store nothing
+    if (e >= ne) e = ne - 1;
+  }
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
   // coefficient rows as in k_edge1, the pair of lanes sharing the edge; the
   // row offset given to at() must be wave-uniform, so a lane-dependent row
   // is a select between two loads
-  const uint32_t lo = (threadIdx.x / 2) * uint32_t(sizeof(T));
-  const uint32_t li = (threadIdx.x / 2) * 4u;
+  const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
+  const uint32_t li = uint32_t(e - e0) * 4u;
   auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
   auto row2 = [&](const T* a, int r0, int r1) { return s == 0 ? row(a, r0) : row(a, r1); };
   int id[3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j)
-    id[j] = s == 0 ? *at(c.stg, j * ne + e0, li) : *at(c.stg, (5 - j) * ne + e0, li);
+  for (int j = 0; j < 3; ++j) {
+    if constexpr (STG)
+      id[j] = s == 0 ? *at(c.epos, j * ne + e0, 2u * uint32_t(e - e0))
+                     : *at(c.epos, (5 - j) * ne + e0, 2u * uint32_t(e - e0));
+    else
+      id[j] = s == 0 ? *at(c.stg, j * ne + e0, li) : *at(c.stg, (5 - j) * ne + e0, li);
+  }
   const T nx = row(c.n, 0), ny = row(c.n, 1);
   const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   // Hermite rows: own side at its nodes 0..2; other side at its nodes 3 + m,
@@ -347,10 +401,35 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     for (int k = 0; k < 3; ++k)
       wt[3 * m + k] = row2(c.w5, 15 + 3 * (3 + m) + k, 3 * (3 + m) + k);
   }
+  // (staged: the block's rows in LDS, [rows][3] records w, w_x, w_y)
+  V4<T>* lv = reinterpret_cast<V4<T>*>(hfd_stage_lds);
+  if constexpr (STG) {
+    const int64_t b = e0 / kEdgeStageEdges;
+    const int r0 = c.erp[b], nr = c.erp[b + 1] - r0;
+    for (int k = int(threadIdx.x); k < nr; k += int(blockDim.x)) {
+      const int64_t rw = c.erow[r0 + k];
+      lv[3 * k] = Gv[rw];
+      if constexpr (SWM != HFD_SWITCH_WENO_ONLY) {  // (WENO everywhere reads no gradient)
+        lv[3 * k + 1] = Gg[2 * rw];
+        lv[3 * k + 2] = Gg[2 * rw + 1];
+      }
+    }
+    __syncthreads();
+  }
   T w[3][4], gx[3][4], gy[3][4];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const V4<T> a = Gv[id[j]], bx = Gg[2 * int64_t(id[j])], by = Gg[2 * int64_t(id[j]) + 1];
+    const int64_t t = id[j];
+    V4<T> a, bx, by;
+    if constexpr (STG) {
+      a = lv[3 * t];
+      bx = lv[3 * t + 1];
+      by = lv[3 * t + 2];
+    } else {
+      a = Gv[t];
+      bx = Gg[2 * t];
+      by = Gg[2 * t + 1];
+    }
     w[j][0] = a.x, w[j][1] = a.y, w[j][2] = a.z, w[j][3] = a.w;
     gx[j][0] = bx.x, gx[j][1] = bx.y, gx[j][2] = bx.z, gx[j][3] = bx.w;
     gy[j][0] = by.x, gy[j][1] = by.y, gy[j][2] = by.z, gy[j][3] = by.w;
@@ -425,7 +504,8 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   } else {
     riemann<T>(gp.flux, wl, wr, nx, ny, ref, gam, gm1, h);
   }
-  store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, s == 0, s == 1);
+  const bool real = !STG || e0 + int64_t(threadIdx.x / 2) < ne;
+  store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, real && s == 0, real && s == 1);
 }
 
 // Midpoint derivatives of the two interface states (hfd_edge_states only, not
@@ -562,8 +642,6 @@ __device__ inline int slot_id(const char* b, uint32_t r) {
   else if constexpr (IB == 1) return *reinterpret_cast<const uint8_t*>(b + r);
   else return *reinterpret_cast<const uint16_t*>(b + 2u * r);
 }
-
-extern __shared__ __attribute__((aligned(32))) unsigned char hfd_stage_lds[];
 
 template <class T, bool VISC, int IB>
 __global__ void __launch_bounds__(256, VISC ? 2 : VertexWaves<T>::value)
@@ -943,12 +1021,22 @@ void launch_edge_swm(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp, cons
                      const V4<T>* Gg, const uint8_t* force, V4<T>* H, double* hsoa,
                      double* wlr, uint8_t* mask, hipStream_t st) {
   // float: one lane per edge; double: two (one per side), register budget
-  if constexpr (sizeof(T) == 8 || HFD_EDGE32_TWO_LANES)
-    hipLaunchKernelGGL((k_edge2<T, SWM>), dim3(nblocks(2 * ne, 256)), dim3(256), 0, st, ne, c,
+  if constexpr (sizeof(T) == 8 || HFD_EDGE32_TWO_LANES) {
+    if (c.erp)
+      hipLaunchKernelGGL((k_edge2<T, SWM, true>), dim3(nblocks(2 * ne, 256)), dim3(256),
+                         size_t(c.max_rows) * 3 * sizeof(V4<T>), st, ne, c, gp, Gv, Gg, force,
+                         H, hsoa, wlr, mask);
+    else
+      hipLaunchKernelGGL((k_edge2<T, SWM, false>), dim3(nblocks(2 * ne, 256)), dim3(256), 0, st,
+                         ne, c, gp, Gv, Gg, force, H, hsoa, wlr, mask);
+  }
+  else if (HFD_EDGE1_STAGE && c.erp)
+    hipLaunchKernelGGL((k_edge1<T, SWM, true>), dim3(nblocks(ne, kEdgeStageEdges)),
+                       dim3(kEdgeStageEdges), size_t(c.max_rows) * 3 * sizeof(V4<T>), st, ne, c,
                        gp, Gv, Gg, force, H, hsoa, wlr, mask);
   else
-    hipLaunchKernelGGL((k_edge1<T, SWM>), dim3(nblocks(ne, 256)), dim3(256), 0, st, ne, c, gp,
-                       Gv, Gg, force, H, hsoa, wlr, mask);
+    hipLaunchKernelGGL((k_edge1<T, SWM, false>), dim3(nblocks(ne, 256)), dim3(256), 0, st, ne,
+                       c, gp, Gv, Gg, force, H, hsoa, wlr, mask);
 }
 
 template <class T>
