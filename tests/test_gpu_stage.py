@@ -1,8 +1,10 @@
-"""The vertex pass that stages each block's distinct state rows and edge
-fluxes in LDS gives the same bits as the pass that gathers every slot from
-HBM (only where the data is read from differs, not the arithmetic): the
-residual and Runge-Kutta steps, float64 and mixed, Euler and viscous, small
-instances of every workload and the full-size shock-vortex mesh."""
+"""The passes that stage data in LDS (the vertex pass each block's distinct
+state rows and edge fluxes, the edge passes each 128-edge block's distinct
+stencil rows) give the same bits as the passes that gather every slot and
+node from HBM (only where the data is read from differs, not the
+arithmetic): the residual and Runge-Kutta steps, float64 and mixed, Euler
+and viscous, the three switch modes of the workloads, small instances of
+every workload and the full-size shock-vortex mesh."""
 import pytest
 import torch
 
