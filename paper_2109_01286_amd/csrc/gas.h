@@ -198,18 +198,37 @@ __device__ inline Ref<T> make_ref(const GasParams& gp) {
   return r;
 }
 
-// Roe average of the edge's end states (nodes i, i+1) and the eigenvector
-// matrices of the flux Jacobian along n: R (columns: right eigenvectors for
-// u.n - c, u.n, u.n + c, shear) and its inverse L (rows).
+// Roe average of the edge's end states (nodes i, i+1) along n.  The
+// eigenvector matrices of the flux Jacobian are applied from its scalars:
+// proj(w) = L w (rows of L: the left eigenvectors for u.n - c, u.n, u.n + c
+// and the shear wave) and back(C) = R C (columns of R: the right ones), each
+// in about 14 operations instead of the 16 multiply-adds of a 4 x 4 product,
+// with 11 values to hold instead of the 32 entries of L and R.
 template <class T>
-struct Frame {
-  T L[4][4], R[4][4];
-  T un, c;  // normal velocity and sound speed of the Roe state
+struct RoeState {
+  T u, v, hh, cc, un, ut, b1, b2, ic, nx, ny;
+  __device__ void proj(const T w[4], T o[4]) const {
+    // L w = (a + b, 2 (w0 - a), a - b) / 2 and the shear row, with
+    // a = b2 w0 - b1 (u w1 + v w2 - w3), b = (un w0 - nx w1 - ny w2) / c
+    const T a = b2 * w[0] - b1 * (u * w[1] + v * w[2] - w[3]);
+    const T b = ic * (un * w[0] - nx * w[1] - ny * w[2]);
+    o[0] = T(0.5) * (a + b);
+    o[1] = w[0] - a;
+    o[2] = T(0.5) * (a - b);
+    o[3] = -ut * w[0] - ny * w[1] + nx * w[2];
+  }
+  __device__ void back(const T C[4], T o[4]) const {
+    const T sum = C[0] + C[1] + C[2], d = cc * (C[2] - C[0]);
+    o[0] = sum;
+    o[1] = u * sum + nx * d - ny * C[3];
+    o[2] = v * sum + ny * d + nx * C[3];
+    o[3] = hh * (C[0] + C[2]) + T(0.5) * (u * u + v * v) * C[1] + un * d + ut * C[3];
+  }
 };
 
 template <class T>
-__device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
-                                     const Ref<T>& ref, T gm1) {
+__device__ inline RoeState<T> roe_state(const V4<T>& A, const V4<T>& B, T nx, T ny,
+                                        const Ref<T>& ref, T gm1) {
   const T ra = ref.w[0] + A.x, rb = ref.w[0] + B.x;
   const T ira = frcp(ra), irb = frcp(rb);
   const T ua = (ref.w[1] + A.y) * ira, ub = (ref.w[1] + B.y) * irb;
@@ -226,6 +245,22 @@ __device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
   const T q2 = u * u + v * v;
   const T un = u * nx + v * ny, ut = -u * ny + v * nx;
   const T ic = frcp(cc), b1 = gm1 * ic * ic, b2 = T(0.5) * b1 * q2;
+  return RoeState<T>{u, v, hh, cc, un, ut, b1, b2, ic, nx, ny};
+}
+
+// The same with the matrices stored (Roe's flux).
+template <class T>
+struct Frame {
+  T L[4][4], R[4][4];
+  T un, c;  // normal velocity and sound speed of the Roe state
+};
+
+template <class T>
+__device__ inline Frame<T> roe_frame(const V4<T>& A, const V4<T>& B, T nx, T ny,
+                                     const Ref<T>& ref, T gm1) {
+  const RoeState<T> S = roe_state<T>(A, B, nx, ny, ref, gm1);
+  const T u = S.u, v = S.v, hh = S.hh, cc = S.cc, un = S.un, ut = S.ut;
+  const T b1 = S.b1, b2 = S.b2, ic = S.ic, q2 = u * u + v * v;
   return Frame<T>{
       {{T(0.5) * (b2 + un * ic), T(-0.5) * (b1 * u + nx * ic), T(-0.5) * (b1 * v + ny * ic), T(0.5) * b1},
        {T(1) - b2, b1 * u, b1 * v, -b1},

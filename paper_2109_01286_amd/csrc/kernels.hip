@@ -126,24 +126,16 @@ __device__ inline bool comp_switch(const T be[3], const GasParams& gp, int s, in
 }
 
 // Interface value of one characteristic component: the omega-weighted 3-node
-// values (w3: the side's three 3-node rows) or the Hermite value L_q . hs
-// (hs: the side's 5-node Hermite sum in physical variables; the row is the
-// same for all components).
+// values (w3: the side's three 3-node rows) or the Hermite value hq (the
+// component of L hs, hs the side's 5-node Hermite sum in physical variables;
+// the row is the same for all components).
 template <class T>
-__device__ inline T comp_value(bool weno, const T c[5], const T o[3], const T w3[9],
-                               const T Lq[4], const T hs[4]) {
+__device__ inline T comp_value(bool weno, const T c[5], const T o[3], const T w3[9], T hq) {
   if (weno)
     return o[0] * (w3[0] * c[0] + w3[1] * c[1] + w3[2] * c[2]) +
            o[1] * (w3[3] * c[1] + w3[4] * c[2] + w3[5] * c[3]) +
            o[2] * (w3[6] * c[2] + w3[7] * c[3] + w3[8] * c[4]);
-  return Lq[0] * hs[0] + Lq[1] * hs[1] + Lq[2] * hs[2] + Lq[3] * hs[3];
-}
-
-template <class T>
-__device__ inline void back_project(const Frame<T>& F, const T C[4], T out[4]) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    out[r] = F.R[r][0] * C[0] + F.R[r][1] * C[1] + F.R[r][2] * C[2] + F.R[r][3] * C[3];
+  return hq;
 }
 
 // One side's decisions (bits 4 s + q) from its indicators.
@@ -161,9 +153,10 @@ __device__ inline uint8_t side_decide(const T be[4][3], const GasParams& gp, int
 // WENO weights formed; otherwise every component is the Hermite value.
 template <class T, class RowFn>
 __device__ inline void side_state(uint8_t b, int s, const T be[4][3], const T cv[4][5],
-                                  const T hs[4], const Frame<T>& F, const GasParams& gp,
+                                  const T hs[4], const RoeState<T>& F, const GasParams& gp,
                                   RowFn w3row, T out[4]) {
   T C[4];
+  F.proj(hs, C);
   if (b) {
     T w3[9];
 #pragma unroll
@@ -172,14 +165,10 @@ __device__ inline void side_state(uint8_t b, int s, const T be[4][3], const T cv
     for (int q = 0; q < 4; ++q) {
       T o[3];
       weno_omega<T>(be[q], T(gp.eps), o);
-      C[q] = comp_value<T>((b >> (4 * s + q)) & 1, cv[q], o, w3, F.L[q], hs);
+      C[q] = comp_value<T>((b >> (4 * s + q)) & 1, cv[q], o, w3, C[q]);
     }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      C[q] = F.L[q][0] * hs[0] + F.L[q][1] * hs[1] + F.L[q][2] * hs[2] + F.L[q][3] * hs[3];
   }
-  back_project<T>(F, C, out);
+  F.back(C, out);
 }
 
 template <class T>
@@ -287,8 +276,8 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     wx[t][0] = bx.x, wx[t][1] = bx.y, wx[t][2] = bx.z, wx[t][3] = bx.w;
     wy[t][0] = by.x, wy[t][1] = by.y, wy[t][2] = by.z, wy[t][3] = by.w;
   }
-  const Frame<T> F = roe_frame<T>(V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]},
-                                  V4<T>{w[3][0], w[3][1], w[3][2], w[3][3]}, nx, ny, ref, gm1);
+  const RoeState<T> F = roe_state<T>(V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]},
+                                     V4<T>{w[3][0], w[3][1], w[3][2], w[3][3]}, nx, ny, ref, gm1);
   // Hermite sums in physical variables: the 5-node row is the same for the
   // four characteristic components, so L (sum_t w5_t . data_t) is the
   // projected Hermite value
@@ -309,9 +298,10 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   T cv[4][6];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
+    T pc[4];
+    F.proj(w[t], pc);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      cv[q][t] = F.L[q][0] * w[t][0] + F.L[q][1] * w[t][1] + F.L[q][2] * w[t][2] + F.L[q][3] * w[t][3];
+    for (int q = 0; q < 4; ++q) cv[q][t] = pc[q];
   }
   // smoothness indicators of both sides (shared differences), then per side
   // the decisions and, only if some component takes that branch, the 3-node
@@ -457,7 +447,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
                          : V4<T>{oth[0], oth[1], oth[2], oth[3]};
   const V4<T> B = s == 0 ? V4<T>{oth[0], oth[1], oth[2], oth[3]}
                          : V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]};
-  const Frame<T> F = roe_frame<T>(A, B, nx, ny, ref, gm1);
+  const RoeState<T> F = roe_state<T>(A, B, nx, ny, ref, gm1);
   T hs[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) hs[q] = hso[q] + dpp_mov<0xB1>(hst[q]);
@@ -466,10 +456,10 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   T cv[4][5];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
+    T pc[4];
+    F.proj(w[j], pc);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      cv[q][j] = F.L[q][0] * w[j][0] + F.L[q][1] * w[j][1] + F.L[q][2] * w[j][2] +
-                 F.L[q][3] * w[j][3];
+    for (int q = 0; q < 4; ++q) cv[q][j] = pc[q];
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -528,7 +518,7 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = T(gp.gamma - 1.0);
   const T nx = c.n[e], ny = c.n[ne + e];
-  const Frame<T> F = roe_frame<T>(Gv[c.stg[2 * ne + e]], Gv[c.stg[3 * ne + e]], nx, ny, ref, gm1);
+  const RoeState<T> F = roe_state<T>(Gv[c.stg[2 * ne + e]], Gv[c.stg[3 * ne + e]], nx, ny, ref, gm1);
   const uint8_t fm = mask[e];
   T cv[4][5], G[2][4];
 #pragma unroll
@@ -542,9 +532,10 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
     const T w[4] = {a.x, a.y, a.z, a.w};
     const T wx[4] = {bx.x, bx.y, bx.z, bx.w};
     const T wy[4] = {by.x, by.y, by.z, by.w};
+    T pc[4];
+    F.proj(w, pc);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      cv[q][j] = F.L[q][0] * w[0] + F.L[q][1] * w[1] + F.L[q][2] * w[2] + F.L[q][3] * w[3];
+    for (int q = 0; q < 4; ++q) cv[q][j] = pc[q];
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const double* r = w5g + int64_t((s * 2 + d) * 15 + 3 * j) * ne + e;
@@ -554,6 +545,8 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
     }
   }
   T gc[2][4];
+  F.proj(G[0], gc[0]);
+  F.proj(G[1], gc[1]);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const bool weno = (fm >> (4 * s + q)) & 1;
@@ -573,16 +566,13 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
                          T(r[2 * ne]) * cv[q][k + 2]);
         }
         gc[d][q] = acc;
-      } else {
-        gc[d][q] = F.L[q][0] * G[d][0] + F.L[q][1] * G[d][1] + F.L[q][2] * G[d][2] +
-                   F.L[q][3] * G[d][3];
       }
     }
   }
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
     T out[4];
-    back_project<T>(F, gc[d], out);
+    F.back(gc[d], out);
 #pragma unroll
     for (int q = 0; q < 4; ++q) grad[int64_t(8 * s + 4 * d + q) * ne + e] = double(out[q]);
   }
