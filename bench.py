@@ -662,13 +662,13 @@ def main():
                      "achieved": kern[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": kern[dom]["frac"],
                      "traffic": (measured_traffic(a.workload, "k_vertex<float" if dom == "vertex"
-                                                  else "k_edge1<float")
+                                                  else "k_edge2<float")
                                  if main_prec == "fp32" else None)},
         "kernels": kern,
     }
     if main_prec == "fp32":
         # counter traffic of the float32 passes, when taken for this source
-        for k, name in (("edge", "k_edge1<float"), ("vertex", "k_vertex<float")):
+        for k, name in (("edge", "k_edge2<float"), ("vertex", "k_vertex<float")):
             kern[k]["traffic"] = measured_traffic(a.workload, name)
     if variants:
         out["flux_variants"] = variants

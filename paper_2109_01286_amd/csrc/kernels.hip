@@ -1,8 +1,8 @@
 // Hot-path kernels of the Hermite finite-difference method (gfx950).
 //
-// Edge pass (Section 2.2 / 2.3, Algorithm 1, eq. 2d_hweno_intp): one lane per
-// active edge in float32, two in float64 (one per side, sharing the six
-// stencil nodes).  Roe average of the edge's end states, characteristic
+// Edge pass (Section 2.2 / 2.3, Algorithm 1, eq. 2d_hweno_intp): two lanes per
+// active edge (one per side, sharing the six stencil nodes; a one-lane kernel
+// for float32 is kept as an alternative).  Roe average of the edge's end states, characteristic
 // projection of values and gradients at the six stencil nodes, per side and
 // characteristic component the WENO5 smoothness indicators and the switch,
 // the 5-node Hermite value (15-term dot product with the stored row) or the
@@ -41,16 +41,16 @@
 #define HFD_VERTEX_WAVES 7    // waves per SIMD of the float32 vertex kernel (Euler)
 #endif
 #ifndef HFD_EDGE_WAVES
-#define HFD_EDGE_WAVES 2      // waves per SIMD of the float32 edge kernel
+#define HFD_EDGE_WAVES 2      // waves per SIMD of the one-lane (float32) edge kernel
 #endif
 #ifndef HFD_EDGE2_WAVES64
 #define HFD_EDGE2_WAVES64 2   // waves per SIMD of the two-lane edge kernel, float64
 #endif
 #ifndef HFD_EDGE2_WAVES32
-#define HFD_EDGE2_WAVES32 4   // the same in float32 (used when HFD_EDGE32_TWO_LANES)
+#define HFD_EDGE2_WAVES32 5   // the same in float32 (80 VGPRs: 6 fit)
 #endif
 #ifndef HFD_EDGE32_TWO_LANES
-#define HFD_EDGE32_TWO_LANES 0 // 1: the float32 edge pass uses the two-lane kernel
+#define HFD_EDGE32_TWO_LANES 1 // 0: the float32 edge pass uses the one-lane kernel
 #endif
 // vertex and edge slots per lane and batch of the vertex pass (16 lanes per
 // vertex), per precision
@@ -359,21 +359,25 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   }
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
-  // coefficient rows as in k_edge1, the pair of lanes sharing the edge; the
-  // row offset given to at() must be wave-uniform, so a lane-dependent row
-  // is a select between two loads
+  // coefficient rows as in k_edge1, the pair of lanes sharing the edge.  A
+  // side's rows are addressed from a per-lane pointer formed once (this
+  // lane's side or the other), plus the row's wave-uniform offset: one
+  // address addition per load instead of a per-load select of the row.
   const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
-  const uint32_t li = uint32_t(e - e0) * 4u;
   auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
-  auto row2 = [&](const T* a, int r0, int r1) { return s == 0 ? row(a, r0) : row(a, r1); };
+  const T* w5own = c.w5 + int64_t(s == 0 ? 0 : 15) * ne + e;
+  const T* w5oth = c.w5 + int64_t(s == 0 ? 15 : 0) * ne + e;
+  const T* w3own = c.w3 + int64_t(s == 0 ? 0 : 9) * ne + e;
+  auto rowp = [&](const T* p, int r) { return p[int64_t(r) * ne]; };
+  // this lane's stencil nodes j = 0, 1, 2: rows j (lane 0) or 5 - j (lane 1)
+  const int64_t jstep = s == 0 ? ne : -ne;
   int id[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     if constexpr (STG)
-      id[j] = s == 0 ? *at(c.epos, j * ne + e0, 2u * uint32_t(e - e0))
-                     : *at(c.epos, (5 - j) * ne + e0, 2u * uint32_t(e - e0));
+      id[j] = (c.epos + (s == 0 ? 0 : 5 * ne) + e)[j * jstep];
     else
-      id[j] = s == 0 ? *at(c.stg, j * ne + e0, li) : *at(c.stg, (5 - j) * ne + e0, li);
+      id[j] = (c.stg + (s == 0 ? 0 : 5 * ne) + e)[j * jstep];
   }
   const T nx = row(c.n, 0), ny = row(c.n, 1);
   const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
@@ -383,13 +387,13 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) wo[3 * j + k] = row2(c.w5, 3 * j + k, 15 + 3 * j + k);
+    for (int k = 0; k < 3; ++k) wo[3 * j + k] = rowp(w5own, 3 * j + k);
   }
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      wt[3 * m + k] = row2(c.w5, 15 + 3 * (3 + m) + k, 3 * (3 + m) + k);
+      wt[3 * m + k] = rowp(w5oth, 3 * (3 + m) + k);
   }
   // (staged: the block's rows in LDS, [rows][3] records w, w_x, w_y)
   V4<T>* lv = reinterpret_cast<V4<T>*>(hfd_stage_lds);
@@ -473,7 +477,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   for (int q = 0; q < 4; ++q) weno_beta<T>(cv[q], be[q]);
   const uint8_t b = side_decide<T, SWM>(be, gp, s, fm);
   T wm[4];
-  side_state<T>(b, s, be, cv, hs, F, gp, [&](int j) { return row2(c.w3, j, 9 + j); }, wm);
+  side_state<T>(b, s, be, cv, hs, F, gp, [&](int j) { return rowp(w3own, j); }, wm);
   T wl[4], wr[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -1010,7 +1014,8 @@ template <class T, int SWM>
 void launch_edge_swm(int64_t ne, const EdgeCoef<T>& c, const GasParams& gp, const V4<T>* Gv,
                      const V4<T>* Gg, const uint8_t* force, V4<T>* H, double* hsoa,
                      double* wlr, uint8_t* mask, hipStream_t st) {
-  // float: one lane per edge; double: two (one per side), register budget
+  // two lanes per edge (one per side); in float32 one lane per edge when
+  // HFD_EDGE32_TWO_LANES is 0
   if constexpr (sizeof(T) == 8 || HFD_EDGE32_TWO_LANES) {
     if (c.erp)
       hipLaunchKernelGGL((k_edge2<T, SWM, true>), dim3(nblocks(2 * ne, 256)), dim3(256),
