@@ -93,10 +93,11 @@ typedef struct hfd_opts {
   int32_t flux;        /* hfd_flux                                        */
   int32_t stage_off;   /* nonzero: the vertex pass gathers every slot's
                           neighbour data from HBM instead of staging each
-                          block's distinct rows and fluxes in LDS, and the
-                          float64 edge pass every stencil node instead of
-                          staging each block's distinct rows (same results
-                          bit for bit)                                    */
+                          block's distinct rows and fluxes in LDS, the edge
+                          passes every stencil node instead of staging each
+                          block's distinct rows, and the edge reverse every
+                          entry's lambda rows instead of staging each
+                          block's distinct ones (same results bit for bit) */
   int32_t edge_grad;   /* 1: also compute and keep (float64, 96 doubles per
                           edge) the midpoint-derivative rows that
                           hfd_edge_states needs for its grad output; 0: no */

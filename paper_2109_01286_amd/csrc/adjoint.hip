@@ -41,8 +41,6 @@ namespace {
 // faster in float32, 2 in float64, whose registers are scarcer)
 template <class T>
 constexpr int kAdjGatherBatch = sizeof(T) == 4 ? 4 : 2;
-// edges per block of the edge reverse (two lanes each: 256 threads)
-constexpr int kAdjEdgesPerBlock = 128;
 // values per stencil node in the edge reverse's rows: (w, w_x, w_y), or w
 // alone when the switch takes WENO everywhere (the gradients get nothing)
 template <int SWM>
@@ -189,17 +187,39 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
            const V4<T>* __restrict__ Gg, const uint8_t* __restrict__ force,
            const int32_t* __restrict__ tptr, const int32_t* __restrict__ tv,
            const T* __restrict__ de_t, const V4<T>* __restrict__ Lv,
-           const V4<T>* __restrict__ Lg, T* __restrict__ out) {
+           const V4<T>* __restrict__ Lg, const int32_t* __restrict__ lrp,
+           const int32_t* __restrict__ lrow, const uint16_t* __restrict__ lpos,
+           T* __restrict__ out) {
   // With WENO everywhere no Hermite value is formed: the Hermite rows are not
   // read and the node gradients get no contribution, so each node's part of
   // the row is its 4 value entries instead of 12.
   constexpr bool HERM = SWM != HFD_SWITCH_WENO_ONLY;
   constexpr int NW = kAdjNodeValues<SWM>;
+  // The block's output rows (6 NW values per edge) go through LDS; before
+  // that, the same LDS holds the staged lambda rows.
+  constexpr int RW = 6 * NW;
+  __shared__ __attribute__((aligned(32))) T obuf[kAdjEdgesPerBlock * RW];
+  static_assert(kAdjStageRows * 12 <= kAdjEdgesPerBlock * RW, "staged rows fit in obuf");
   const int s = threadIdx.x & 1;
   const int64_t eb = int64_t(blockIdx.x) * kAdjEdgesPerBlock;
   // lanes past the last edge recompute the last edge (both lanes of a pair
   // alike) and their results are not written
   const int64_t e = eb + threadIdx.x / 2 < ne ? eb + threadIdx.x / 2 : ne - 1;
+  // Staging: the (lambda, lambda_x, lambda_y) rows of the distinct vertices
+  // the block's entries name go to LDS once; the entries read them by
+  // position.
+  const bool stg = lrp != nullptr;
+  V4<T>* lam_s = reinterpret_cast<V4<T>*>(obuf);
+  if (stg) {
+    const int r0 = lrp[blockIdx.x], nr = lrp[blockIdx.x + 1] - r0;
+    for (int k = int(threadIdx.x); k < nr; k += int(blockDim.x)) {
+      const int64_t u = lrow[r0 + k];
+      lam_s[3 * k] = Lv[u];
+      lam_s[3 * k + 1] = Lg[2 * u];
+      lam_s[3 * k + 2] = Lg[2 * u + 1];
+    }
+    __syncthreads();
+  }
   // lambda_h(e) = - sum over the (v, s') entries whose rows read h_e of
   // de[s'] . (lambda, lambda_x, lambda_y)(v): the lanes take alternate
   // entries (transposed order, contiguous per edge; every active edge has
@@ -221,14 +241,20 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       int v[NB];
       T d[NB][3];
       for (int i = 0; i < NB; ++i) {
-        v[i] = tv[kk[i]];
+        v[i] = stg ? int(lpos[kk[i]]) : tv[kk[i]];
         for (int q = 0; q < 3; ++q) d[i][q] = de_t[3 * int64_t(kk[i]) + q];
       }
       V4<T> l0[NB], lx[NB], ly[NB];
       for (int i = 0; i < NB; ++i) {
-        l0[i] = Lv[v[i]];
-        lx[i] = Lg[2 * int64_t(v[i])];
-        ly[i] = Lg[2 * int64_t(v[i]) + 1];
+        if (stg) {
+          l0[i] = lam_s[3 * v[i]];
+          lx[i] = lam_s[3 * v[i] + 1];
+          ly[i] = lam_s[3 * v[i] + 2];
+        } else {
+          l0[i] = Lv[v[i]];
+          lx[i] = Lg[2 * int64_t(v[i])];
+          ly[i] = Lg[2 * int64_t(v[i]) + 1];
+        }
       }
       for (int i = 0; i < NB; ++i) {
         const T d0 = ok[i] ? d[i][0] : T(0.0), dx = ok[i] ? d[i][1] : T(0.0),
@@ -245,6 +271,8 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       gh[q] += dpp_mov<0xB1>(gh[q]);
     }
   }
+  // (the staged rows are read; the LDS takes the output rows later)
+  if (stg) __syncthreads();
   const T gam = gp.gamma, gm1 = gam - T(1.0);
   const T nx = c.n[e], ny = c.n[ne + e];
   const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
@@ -601,8 +629,6 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // The block's rows (6 NW values per edge) go through LDS and out as one
   // contiguous run: stored directly, the lanes' rows lie 6 NW values apart
   // and every store instruction would touch 64 cache lines.
-  constexpr int RW = 6 * NW;
-  __shared__ __attribute__((aligned(16))) T obuf[kAdjEdgesPerBlock * RW];
   T* o = obuf + (threadIdx.x / 2) * RW;
   for (int p = 0; p < 3; ++p) {
     const int j = s == 0 ? p : 5 - p;
@@ -839,18 +865,18 @@ hipError_t launch_adj_edge(const AdjointArgs<T>& a, hipStream_t st) {
   const int swm = a.force ? kSwForced : a.gp.sw;
   if (swm == kSwForced)
     hipLaunchKernelGGL((k_adj_edge<T, FLUX, kSwForced>), grid, dim3(256), 0, st, a.ne, a.ec,
-                       a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
+                       a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lrp, a.lrow, a.lpos, a.bnode);
   else if (swm == HFD_SWITCH_PAPER)
     hipLaunchKernelGGL((k_adj_edge<T, FLUX, HFD_SWITCH_PAPER>), grid, dim3(256), 0, st, a.ne,
-                       a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.bnode);
+                       a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg, a.lrp, a.lrow, a.lpos, a.bnode);
   else if (swm == HFD_SWITCH_SMOOTH_ONLY)
     hipLaunchKernelGGL((k_adj_edge<T, FLUX, HFD_SWITCH_SMOOTH_ONLY>), grid, dim3(256), 0, st,
                        a.ne, a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg,
-                       a.bnode);
+                       a.lrp, a.lrow, a.lpos, a.bnode);
   else if (swm == HFD_SWITCH_WENO_ONLY)
     hipLaunchKernelGGL((k_adj_edge<T, FLUX, HFD_SWITCH_WENO_ONLY>), grid, dim3(256), 0, st,
                        a.ne, a.ec, a.gp, a.Gv, a.Gg, a.force, a.etp, a.etv, a.de_t, a.Lv, a.Lg,
-                       a.bnode);
+                       a.lrp, a.lrow, a.lpos, a.bnode);
   else
     return hipErrorInvalidValue;
   return hipSuccess;

@@ -98,6 +98,8 @@ struct hfd_ctx {
   bool adj_ready = false;
   bool adj_coef_ready = false;  // de_t, dv_t, dvis_t match the current coefficients
   int32_t *etp = nullptr, *etv = nullptr, *ets = nullptr;
+  int32_t *alrp = nullptr, *alrow = nullptr;  // staging lists of the edge reverse
+  uint16_t* alpos = nullptr;
   int32_t *vtp = nullptr, *vtv = nullptr, *vts = nullptr;
   int32_t *ntp = nullptr, *nte = nullptr;
   int8_t* ntj = nullptr;
@@ -597,6 +599,47 @@ hfd_status ensure_adjoint_coefs(hfd_ctx* c) {
   return HFD_OK;
 }
 
+// Staging lists of the edge reverse: per block of eb consecutive edges
+// (entries ptr[e] .. ptr[e+1] of edge e, vertex tv[k]) the sorted distinct
+// vertices of its lambda_h entries, and per entry its position in its
+// block's list.  Empty when a list is longer than maxrows.
+bool adj_stage_lists(int64_t ne, int64_t eb, int maxrows, const std::vector<int32_t>& ptr,
+                     const std::vector<int32_t>& tv, std::vector<int32_t>& rp,
+                     std::vector<int32_t>& rows, std::vector<uint16_t>& pos) {
+  const int64_t nb = (ne + eb - 1) / eb;
+  std::vector<std::vector<int32_t>> bl;
+  bl.resize(size_t(nb));
+  pos.assign(tv.size(), 0);
+  int tl[16] = {0};
+  hfd::parallel_for(nb, [&](int64_t b0, int64_t b1, unsigned t) {
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t k0 = ptr[b * eb], k1 = ptr[std::min(ne, (b + 1) * eb)];
+      std::vector<int32_t>& L = bl[size_t(b)];
+      L.assign(tv.begin() + k0, tv.begin() + k1);
+      std::sort(L.begin(), L.end());
+      L.erase(std::unique(L.begin(), L.end()), L.end());
+      if (int64_t(L.size()) > maxrows) {
+        tl[t] = std::max(tl[t], int(L.size()));
+        continue;
+      }
+      for (int64_t k = k0; k < k1; ++k)
+        pos[size_t(k)] = uint16_t(std::lower_bound(L.begin(), L.end(), tv[k]) - L.begin());
+      tl[t] = std::max(tl[t], int(L.size()));
+    }
+  });
+  if (*std::max_element(tl, tl + 16) > maxrows) {
+    rp.clear();
+    rows.clear();
+    pos.clear();
+    return false;
+  }
+  rp.assign(size_t(nb + 1), 0);
+  for (int64_t b = 0; b < nb; ++b) rp[b + 1] = rp[b] + int32_t(bl[b].size());
+  rows.resize(size_t(rp[nb]));
+  for (int64_t b = 0; b < nb; ++b) std::copy(bl[b].begin(), bl[b].end(), rows.begin() + rp[b]);
+  return true;
+}
+
 hfd_status ensure_adjoint(hfd_ctx* c) {
   if (c->adj_ready) return ensure_adjoint_coefs(c);
   const hfd::HostSetup& h = c->hs;
@@ -615,6 +658,13 @@ hfd_status ensure_adjoint(hfd_ctx* c) {
       tv[i] = owner[pos[i]];
     }
     if ((s = upload(c, &c->etp, ptr)) || (s = upload(c, &c->etv, tv)) || (s = upload(c, &c->ets, ts)))
+      return s;
+    std::vector<int32_t> rp, rows;
+    std::vector<uint16_t> lpos;
+    if (!c->o.stage_off && ne > 0 &&
+        adj_stage_lists(ne, hfd::kAdjEdgesPerBlock, hfd::kAdjStageRows, ptr, tv, rp, rows, lpos) &&
+        ((s = upload(c, &c->alrp, rp)) || (s = upload(c, &c->alrow, rows)) ||
+         (s = upload(c, &c->alpos, lpos))))
       return s;
   }
   // gather row <- (owner, vertex slot)
@@ -743,6 +793,7 @@ hfd_status adjoint_apply(hfd_ctx* c, const double* U, const hfd::V4<T>* Gv,
   a.nowned = h.n_owned;
   a.nv = h.nv;
   a.etp = c->etp; a.etv = c->etv;
+  a.lrp = c->alrp; a.lrow = c->alrow; a.lpos = c->alpos;
   a.Lv = LGv; a.Lg = LGg;
   a.ec = ecoef<T>(c);
   a.gp = gas_params(c, f32);

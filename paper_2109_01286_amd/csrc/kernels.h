@@ -197,11 +197,24 @@ struct AdjCombine {
   double ca, cb, cc, cd, ce;
 };
 
+// edges per block of the edge reverse (two lanes each: 256 threads)
+constexpr int kAdjEdgesPerBlock = 128;
+// longest staging list of the edge reverse: the lambda rows of that many
+// vertices fit in the LDS of the block's output rows
+constexpr int kAdjStageRows = 256;
+
 template <class T>
 struct AdjointArgs {
   int64_t ne, nowned, nv;
   const int32_t *etp, *etv;         // edge m <- (owner vertex, edge slot)
   const T* de_t;                    // de rows in the order of etv
+  // staging lists of the edge reverse (null: lambda gathered from HBM): per
+  // block of kAdjEdgesPerBlock edges the sorted distinct vertices of its
+  // entries (lrow[lrp[b] .. lrp[b+1]), at most kAdjStageRows), per entry
+  // (order of etv) its position in that list
+  const int32_t* lrp;
+  const int32_t* lrow;
+  const uint16_t* lpos;
   const V4<T>* Lv;                  // lambda in gather layout
   const V4<T>* Lg;
   EdgeCoef<T> ec;

@@ -1,10 +1,11 @@
 """The passes that stage data in LDS (the vertex pass each block's distinct
 state rows and edge fluxes, the edge passes each 128-edge block's distinct
-stencil rows) give the same bits as the passes that gather every slot and
-node from HBM (only where the data is read from differs, not the
-arithmetic): the residual and Runge-Kutta steps, float64 and mixed, Euler
-and viscous, the three switch modes of the workloads, small instances of
-every workload and the full-size shock-vortex mesh."""
+stencil rows, the edge reverse each 128-edge block's distinct lambda rows)
+give the same bits as the passes that gather every slot and node from HBM
+(only where the data is read from differs, not the arithmetic): the
+residual, the adjoint residual and Runge-Kutta steps, float64 and mixed,
+Euler and viscous, the three switch modes of the workloads, small instances
+of every workload and the full-size shock-vortex mesh."""
 import pytest
 import torch
 
@@ -56,6 +57,10 @@ def check(A, B, Ud, steps=2, stable=True):
     ra, rb = A.residual(Ud), B.residual(Ud)
     assert mostly_finite(ra)
     assert same_bits(ra, rb)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    lam = torch.randn(Ud.shape, generator=gen, dtype=torch.float64).to(DEV)
+    ga, gb = A.adjoint_residual(Ud, lam), B.adjoint_residual(Ud, lam)
+    assert same_bits(ga, gb)
     dt = A.stable_dt(Ud, 0.3)
     Ua, Ub = Ud.clone(), Ud.clone()
     for _ in range(steps):
