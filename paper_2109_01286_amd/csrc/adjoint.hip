@@ -450,8 +450,9 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
     // gw[k] = gh . dh/d(w_side)[k]: the flux on dual numbers seeded with
     // direction k of this lane's state (full states, zero reference)
     GasParams gz = gp;
-    for (int q = 0; q < 4; ++q) gz.wref[q] = 0.0;
+    for (int q = 0; q < 4; ++q) gz.wref[q] = gz.f_wref[q] = 0.0;
     gz.uref = gz.vref = gz.etr_ref = 0.0;
+    gz.f_uref = gz.f_vref = gz.f_etr_ref = 0.0f;
     const Ref<Dual<T>> rz = make_ref<Dual<T>>(gz);
     for (int k = 0; k < 4; ++k) {
       Dual<T> Ld[4], Rd[4], hd[4];

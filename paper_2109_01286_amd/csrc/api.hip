@@ -183,6 +183,15 @@ GasParams gas_params(const hfd_ctx* c, bool mixed) {
   g.etr_ref = g.wref[3] + p;
   g.sw = c->o.switch_mode;
   g.flux = c->o.flux;
+  g.f_gamma = float(g.gamma);
+  g.f_gm1 = float(g.gamma - 1.0);
+  g.f_eps = float(g.eps);
+  g.f_sw_lo = float(g.sw_lo);
+  g.f_sw_hi = float(g.sw_hi);
+  for (int q = 0; q < 4; ++q) g.f_wref[q] = float(g.wref[q]);
+  g.f_uref = float(g.uref);
+  g.f_vref = float(g.vref);
+  g.f_etr_ref = float(g.etr_ref);
   return g;
 }
 

@@ -181,14 +181,22 @@ __device__ inline void pert_flux(const T wp[4], const Ref<T>& R, T gm1, T f[4],
   if (p_pert) *p_pert = pp;
 }
 
+// A parameter in the kernel's precision: float32 kernels take the copy the
+// host rounded once, the others convert the float64 value.
+template <class T>
+__device__ inline T gpar(double d, float f) {
+  if constexpr (std::is_same<T, float>::value) return f;
+  else return T(d);
+}
+
 template <class T>
 __device__ inline Ref<T> make_ref(const GasParams& gp) {
   Ref<T> r;
   if constexpr (std::is_same<T, float>::value) {
-    for (int q = 0; q < 4; ++q) r.w[q] = T(gp.wref[q]);
-    r.u = T(gp.uref);
-    r.v = T(gp.vref);
-    r.etr = T(gp.etr_ref);
+    for (int q = 0; q < 4; ++q) r.w[q] = gp.f_wref[q];
+    r.u = gp.f_uref;
+    r.v = gp.f_vref;
+    r.etr = gp.f_etr_ref;
   } else {
     // only the float32 kernels carry a reference state: the float64 form
     // (and the adjoint's dual-number fluxes of full states) have none

@@ -73,6 +73,10 @@ struct GasParams {
   double uref, vref, etr_ref;  // its velocity and E + p (set with wref)
   int sw;           // hfd_switch
   int flux;         // hfd_flux
+  // the same values rounded to float once on the host: the float32 kernels
+  // read these instead of converting on the vector ALUs
+  float f_gamma, f_gm1, f_eps, f_sw_lo, f_sw_hi;
+  float f_wref[4], f_uref, f_vref, f_etr_ref;
 };
 
 // Coefficients of the edge kernel, one precision.

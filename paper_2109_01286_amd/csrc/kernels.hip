@@ -121,7 +121,8 @@ __device__ inline bool comp_switch(const T be[3], const GasParams& gp, int s, in
                                    uint8_t fm) {
   if constexpr (SWM == kSwForced) return (fm >> (4 * s + q)) & 1;
   else if constexpr (SWM == HFD_SWITCH_PAPER)
-    return !weno_in<T>(be, T(gp.eps), T(gp.sw_lo), T(gp.sw_hi));
+    return !weno_in<T>(be, gpar<T>(gp.eps, gp.f_eps), gpar<T>(gp.sw_lo, gp.f_sw_lo),
+                      gpar<T>(gp.sw_hi, gp.f_sw_hi));
   else return SWM == HFD_SWITCH_WENO_ONLY;
 }
 
@@ -164,7 +165,7 @@ __device__ inline void side_state(uint8_t b, int s, const T be[4][3], const T cv
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       T o[3];
-      weno_omega<T>(be[q], T(gp.eps), o);
+      weno_omega<T>(be[q], gpar<T>(gp.eps, gp.f_eps), o);
       C[q] = comp_value<T>((b >> (4 * s + q)) & 1, cv[q], o, w3, C[q]);
     }
   }
@@ -223,7 +224,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     if (e >= ne) e = ne - 1;  // (reaches the staging barrier, stores nothing)
   }
   const Ref<T> ref = make_ref<T>(gp);
-  const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
+  const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   // Row r of a [rows][ne] coefficient array at this edge: the row base of the
   // block is uniform, the lane adds a 32-bit byte offset (one register for
   // all rows).
@@ -330,6 +331,35 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   store_edge<T>(ne, e, h, wl, wr, bits, gp, H, hsoa, wlr, mask, real, real);
 }
 
+// Roe state of an edge whose end states are held by a lane pair (lane 0
+// node i, lane 1 node i+1; w in the kernel's form, perturbation in float32):
+// each lane forms its node's square-root weights sqrt(rho) (1, u, v, H), the
+// pair swaps them and both add the two.  The weights are rounded before the
+// swap, so both lanes add the same two numbers and hold the same state.
+template <class T>
+__device__ inline RoeState<T> roe_state_pair(const T w[4], T nx, T ny, const Ref<T>& ref,
+                                             T gm1) {
+  const T r = ref.w[0] + w[0], ir = frcp(r);
+  const T u = (ref.w[1] + w[1]) * ir, v = (ref.w[2] + w[2]) * ir;
+  const T E = ref.w[3] + w[3];
+  const T p = gm1 * (E - T(0.5) * r * (u * u + v * v));
+  const T sq = fsqrt(r);
+  T x[4] = {sq, sq * u, sq * v, sq * (E + p) * ir};
+  T sum[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    asm volatile("" : "+v"(x[q]));  // (rounded: no product fused into the sum)
+    sum[q] = x[q] + dpp_mov<0xB1>(x[q]);
+  }
+  const T iw = frcp(sum[0]);
+  const T ur = sum[1] * iw, vr = sum[2] * iw, hh = sum[3] * iw;
+  const T q2 = ur * ur + vr * vr;
+  const T cc = fsqrt(gm1 * (hh - T(0.5) * q2));
+  const T un = ur * nx + vr * ny, ut = -ur * ny + vr * nx;
+  const T ic = frcp(cc), b1 = gm1 * ic * ic, b2 = T(0.5) * b1 * q2;
+  return RoeState<T>{ur, vr, hh, cc, un, ut, b1, b2, ic, nx, ny};
+}
+
 // Two lanes per edge, lane s interpolating side s.  Each stencil node is
 // gathered and projected once: lane 0 takes nodes 0, 1, 2 and lane 1 nodes
 // 5, 4, 3 (its j-th node is node 5 - j), which are the first three nodes of
@@ -358,7 +388,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     if (e >= ne) e = ne - 1;
   }
   const Ref<T> ref = make_ref<T>(gp);
-  const T gam = T(gp.gamma), gm1 = T(gp.gamma - 1.0);
+  const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   // coefficient rows as in k_edge1, the pair of lanes sharing the edge.  A
   // side's rows are addressed from a per-lane pointer formed once (this
   // lane's side or the other), plus the row's wave-uniform offset: one
@@ -444,14 +474,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
                 wt[3 * m + 2] * gy[2 - m][q];
   }
   // Roe frame of the edge's end states: lane 0 holds node 2, lane 1 node 3
-  T oth[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) oth[q] = dpp_mov<0xB1>(w[2][q]);
-  const V4<T> A = s == 0 ? V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]}
-                         : V4<T>{oth[0], oth[1], oth[2], oth[3]};
-  const V4<T> B = s == 0 ? V4<T>{oth[0], oth[1], oth[2], oth[3]}
-                         : V4<T>{w[2][0], w[2][1], w[2][2], w[2][3]};
-  const RoeState<T> F = roe_state<T>(A, B, nx, ny, ref, gm1);
+  const RoeState<T> F = roe_state_pair<T>(w[2], nx, ny, ref, gm1);
   T hs[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) hs[q] = hso[q] + dpp_mov<0xB1>(hst[q]);
@@ -520,7 +543,7 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
   const int s = int(threadIdx.x & 1);
   if (e >= ne) return;
   const Ref<T> ref = make_ref<T>(gp);
-  const T gm1 = T(gp.gamma - 1.0);
+  const T gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   const T nx = c.n[e], ny = c.n[ne + e];
   const RoeState<T> F = roe_state<T>(Gv[c.stg[2 * ne + e]], Gv[c.stg[3 * ne + e]], nx, ny, ref, gm1);
   const uint8_t fm = mask[e];
@@ -557,7 +580,7 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
     T o[3] = {T(0), T(0), T(0)};
     if (weno) {
       T be[3];
-      weno_weights<T>(cv[q], T(gp.eps), be, o);
+      weno_weights<T>(cv[q], gpar<T>(gp.eps, gp.f_eps), be, o);
     }
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
@@ -725,7 +748,7 @@ k_vertex(int64_t nowned, int64_t nv, VertexCoef<T> c, GasParams gp,
   }
 
   const Ref<T> ref = make_ref<T>(gp);
-  const T gm1 = T(gp.gamma - 1.0);
+  const T gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   T acc[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) acc[k] = T(0);
