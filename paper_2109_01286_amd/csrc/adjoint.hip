@@ -273,17 +273,17 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   }
   // (the staged rows are read; the LDS takes the output rows later)
   if (stg) __syncthreads();
-  const T gam = gp.gamma, gm1 = gam - T(1.0);
+  const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   const T nx = c.n[e], ny = c.n[ne + e];
   const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
   int id[5];
   for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];
-  const T eps = gp.eps;
+  const T eps = gpar<T>(gp.eps, gp.f_eps);
   const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   // The float32 form stores the perturbation w - w_ref of the values (the
   // gradients unchanged); the reverse works on the full state.
   auto full = [&](T x, int q) -> T {
-    if constexpr (sizeof(T) == 4) return x + T(gp.wref[q]);
+    if constexpr (sizeof(T) == 4) return x + gp.f_wref[q];
     else return x;
   };
   // Roe average of nodes 2 and 3 and the eigenvector matrices L (rows), R
@@ -395,7 +395,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
       bool wq;
       if constexpr (SWM == kSwForced) wq = (fm >> (4 * s + q)) & 1;
       else if constexpr (SWM == HFD_SWITCH_PAPER)
-        wq = !weno_in<T>(be, eps, T(gp.sw_lo), T(gp.sw_hi));
+        wq = !weno_in<T>(be, eps, gpar<T>(gp.sw_lo, gp.f_sw_lo), gpar<T>(gp.sw_hi, gp.f_sw_hi));
       else wq = (SWM == HFD_SWITCH_WENO_ONLY);
       weno[q] = wq;
       C[q] = wq ? om[0] * Sk[0] + om[1] * Sk[1] + om[2] * Sk[2]
@@ -768,7 +768,7 @@ k_adj_vertex(int64_t nowned, int64_t nv, GasParams gp, const double* __restrict_
   if (t < VPB && u0 + t < nowned) {
     // A_f^T lambda_f + A_g^T lambda_g at w_u (n = (1, 0) and (0, 1))
     const int64_t uu = u0 + t;
-    const T gm1 = gp.gamma - T(1.0);
+    const T gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
     T w[4], lf[4], lg[4], o[4] = {0, 0, 0, 0};
     for (int q = 0; q < 4; ++q) {
       w[q] = T(U[q * nv + uu]);
