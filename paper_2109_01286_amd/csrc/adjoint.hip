@@ -334,7 +334,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // this side's node values and coefficient rows.  The indices and the base
   // pointers pass through launder() at every use, so that the compiler
   // recomputes the addresses there instead of keeping them in registers.
-  const T* w5p = c.w5 + int64_t(s * 15) * ne + e;
+  const T* w5p = c.w5 + (int64_t(s) * ne + e) * 15;
   const T* w3p = c.w3 + int64_t(s * 9) * ne + e;
   auto load_W = [&](T W[5][4]) {
     for (int t = 0; t < 5; ++t) {
@@ -346,7 +346,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   auto load_w5 = [&](T w5[5][3]) {
     const T* b = launder(w5p);
     for (int t = 0; t < 5; ++t)
-      for (int k = 0; k < 3; ++k) w5[t][k] = b[int64_t(3 * t + k) * ne];
+      for (int k = 0; k < 3; ++k) w5[t][k] = b[3 * t + k];
   };
   auto load_w3 = [&](T w3[9]) {
     const T* b = launder(w3p);

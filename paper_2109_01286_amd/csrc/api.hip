@@ -1131,7 +1131,14 @@ hfd_status hfd_export_weights(const hfd_ctx* ctx, double* w5, double* w3, int32_
       for (int64_t r = 0; r < rows; ++r) out[e * rows + r] = tmp[r * ne + e];
     return HFD_OK;
   };
-  if (w5 && (s = soa_to_aos(c->w5, 30, w5))) return s;
+  if (w5) {
+    // device [2][ne][15] -> [ne][2][15]
+    std::vector<double> tmp(30 * ne);
+    HIPCHK(c, hipMemcpy(tmp.data(), c->w5, tmp.size() * 8, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < ne; ++e)
+      for (int sd = 0; sd < 2; ++sd)
+        for (int k = 0; k < 15; ++k) w5[(e * 2 + sd) * 15 + k] = tmp[(sd * ne + e) * 15 + k];
+  }
   if (w3 && (s = soa_to_aos(c->w3, 18, w3))) return s;
   if (rank) {
     std::vector<int32_t> tmp(2 * ne);
@@ -1162,7 +1169,14 @@ hfd_status hfd_import_weights(hfd_ctx* c, const double* w5, const double* w3,
     HIPCHK(c, hipMemcpy(d, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
     return HFD_OK;
   };
-  if (w5 && (s = aos_to_soa(w5, 30, c->w5))) return s;
+  if (w5) {
+    // [ne][2][15] -> device [2][ne][15]
+    std::vector<double> tmp(30 * ne);
+    for (int64_t e = 0; e < ne; ++e)
+      for (int sd = 0; sd < 2; ++sd)
+        for (int k = 0; k < 15; ++k) tmp[(sd * ne + e) * 15 + k] = w5[(e * 2 + sd) * 15 + k];
+    HIPCHK(c, hipMemcpy(c->w5, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
+  }
   if (w3 && (s = aos_to_soa(w3, 18, c->w3))) return s;
   if (dv) HIPCHK(c, hipMemcpy(c->dv, dv, 6 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
   if (de) HIPCHK(c, hipMemcpy(c->de, de, 3 * c->info.n_eslots * 8, hipMemcpyHostToDevice));

@@ -242,7 +242,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
 #pragma unroll
-    for (int j = 0; j < 15; ++j) w5[s][j] = row(c.w5, s * 15 + j);
+    for (int j = 0; j < 15; ++j) w5[s][j] = c.w5[(int64_t(s) * ne + e) * 15 + j];
   }
   const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   V4<T>* lv = reinterpret_cast<V4<T>*>(hfd_stage_lds);  // (staged: [rows][3] w, w_x, w_y)
@@ -390,13 +390,14 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   // coefficient rows as in k_edge1, the pair of lanes sharing the edge.  A
-  // side's rows are addressed from a per-lane pointer formed once (this
-  // lane's side or the other), plus the row's wave-uniform offset: one
-  // address addition per load instead of a per-load select of the row.
+  // side's Hermite weights are one 15-value record per edge (this lane's
+  // side and the other's, read with wide loads); the 3-node rows and the
+  // stencil positions are addressed from a per-lane pointer formed once,
+  // plus the row's wave-uniform offset.
   const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
   auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
-  const T* w5own = c.w5 + int64_t(s == 0 ? 0 : 15) * ne + e;
-  const T* w5oth = c.w5 + int64_t(s == 0 ? 15 : 0) * ne + e;
+  const T* w5own = c.w5 + (int64_t(s) * ne + e) * 15;
+  const T* w5oth = c.w5 + (int64_t(1 - s) * ne + e) * 15;
   const T* w3own = c.w3 + int64_t(s == 0 ? 0 : 9) * ne + e;
   auto rowp = [&](const T* p, int r) { return p[int64_t(r) * ne]; };
   // this lane's stencil nodes j = 0, 1, 2: rows j (lane 0) or 5 - j (lane 1)
@@ -417,13 +418,13 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) wo[3 * j + k] = rowp(w5own, 3 * j + k);
+    for (int k = 0; k < 3; ++k) wo[3 * j + k] = w5own[3 * j + k];
   }
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      wt[3 * m + k] = rowp(w5oth, 3 * (3 + m) + k);
+      wt[3 * m + k] = w5oth[3 * (3 + m) + k];
   }
   // (staged: the block's rows in LDS, [rows][3] records w, w_x, w_y)
   V4<T>* lv = reinterpret_cast<V4<T>*>(hfd_stage_lds);

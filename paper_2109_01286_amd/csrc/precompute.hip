@@ -324,7 +324,7 @@ k_edge_weights(int64_t ne, const double* __restrict__ pts,
     if (lane == 6) w += 1.0 - sv;  // anchor = node 2 of the side
     if (lane < 15) {
       if (lane % 3 != 0) w *= eh[e];
-      w5[int64_t(side * 15 + lane) * ne + e] = w;
+      w5[(int64_t(side) * ne + e) * 15 + lane] = w;
     }
     if (lane == 0) rank[int64_t(side) * ne + e] = r;
     // midpoint derivatives: rows 2 and 3 of the same operator at the final
