@@ -335,7 +335,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // pointers pass through launder() at every use, so that the compiler
   // recomputes the addresses there instead of keeping them in registers.
   const T* w5p = c.w5 + (int64_t(s) * ne + e) * 15;
-  const T* w3p = c.w3 + int64_t(s * 9) * ne + e;
+  const T* w3p = c.w3 + (int64_t(s) * ne + e) * 9;
   auto load_W = [&](T W[5][4]) {
     for (int t = 0; t < 5; ++t) {
       const V4<T> a = Gv[launder(id[t])];
@@ -350,7 +350,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   };
   auto load_w3 = [&](T w3[9]) {
     const T* b = launder(w3p);
-    for (int j = 0; j < 9; ++j) w3[j] = b[int64_t(j) * ne];
+    for (int j = 0; j < 9; ++j) w3[j] = b[j];
   };
   // projected node values of component q
   auto proj = [&](const T L[4][4], const T W[5][4], int q, T cq[5]) {

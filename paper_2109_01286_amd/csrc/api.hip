@@ -1124,22 +1124,17 @@ hfd_status hfd_export_weights(const hfd_ctx* ctx, double* w5, double* w3, int32_
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipDeviceSynchronize());
   const int64_t ne = c->hs.ne;
-  auto soa_to_aos = [&](const double* d, int64_t rows, double* out) -> hfd_status {
-    std::vector<double> tmp(rows * ne);
+  // device records [2 sides][ne][n] -> [ne][2 sides][n]
+  auto records_to_host = [&](const double* d, int64_t n, double* out) -> hfd_status {
+    std::vector<double> tmp(2 * n * ne);
     HIPCHK(c, hipMemcpy(tmp.data(), d, tmp.size() * 8, hipMemcpyDeviceToHost));
     for (int64_t e = 0; e < ne; ++e)
-      for (int64_t r = 0; r < rows; ++r) out[e * rows + r] = tmp[r * ne + e];
+      for (int64_t sd = 0; sd < 2; ++sd)
+        for (int64_t k = 0; k < n; ++k) out[(e * 2 + sd) * n + k] = tmp[(sd * ne + e) * n + k];
     return HFD_OK;
   };
-  if (w5) {
-    // device [2][ne][15] -> [ne][2][15]
-    std::vector<double> tmp(30 * ne);
-    HIPCHK(c, hipMemcpy(tmp.data(), c->w5, tmp.size() * 8, hipMemcpyDeviceToHost));
-    for (int64_t e = 0; e < ne; ++e)
-      for (int sd = 0; sd < 2; ++sd)
-        for (int k = 0; k < 15; ++k) w5[(e * 2 + sd) * 15 + k] = tmp[(sd * ne + e) * 15 + k];
-  }
-  if (w3 && (s = soa_to_aos(c->w3, 18, w3))) return s;
+  if (w5 && (s = records_to_host(c->w5, 15, w5))) return s;
+  if (w3 && (s = records_to_host(c->w3, 9, w3))) return s;
   if (rank) {
     std::vector<int32_t> tmp(2 * ne);
     HIPCHK(c, hipMemcpy(tmp.data(), c->rank, tmp.size() * 4, hipMemcpyDeviceToHost));
@@ -1162,22 +1157,17 @@ hfd_status hfd_import_weights(hfd_ctx* c, const double* w5, const double* w3,
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipDeviceSynchronize());
   const int64_t ne = c->hs.ne;
-  auto aos_to_soa = [&](const double* in, int64_t rows, double* d) -> hfd_status {
-    std::vector<double> tmp(rows * ne);
+  // [ne][2 sides][n] -> device records [2 sides][ne][n]
+  auto host_to_records = [&](const double* in, int64_t n, double* d) -> hfd_status {
+    std::vector<double> tmp(2 * n * ne);
     for (int64_t e = 0; e < ne; ++e)
-      for (int64_t r = 0; r < rows; ++r) tmp[r * ne + e] = in[e * rows + r];
+      for (int64_t sd = 0; sd < 2; ++sd)
+        for (int64_t k = 0; k < n; ++k) tmp[(sd * ne + e) * n + k] = in[(e * 2 + sd) * n + k];
     HIPCHK(c, hipMemcpy(d, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
     return HFD_OK;
   };
-  if (w5) {
-    // [ne][2][15] -> device [2][ne][15]
-    std::vector<double> tmp(30 * ne);
-    for (int64_t e = 0; e < ne; ++e)
-      for (int sd = 0; sd < 2; ++sd)
-        for (int k = 0; k < 15; ++k) tmp[(sd * ne + e) * 15 + k] = w5[(e * 2 + sd) * 15 + k];
-    HIPCHK(c, hipMemcpy(c->w5, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
-  }
-  if (w3 && (s = aos_to_soa(w3, 18, c->w3))) return s;
+  if (w5 && (s = host_to_records(w5, 15, c->w5))) return s;
+  if (w3 && (s = host_to_records(w3, 9, c->w3))) return s;
   if (dv) HIPCHK(c, hipMemcpy(c->dv, dv, 6 * c->info.n_vslots * 8, hipMemcpyHostToDevice));
   if (de) HIPCHK(c, hipMemcpy(c->de, de, 3 * c->info.n_eslots * 8, hipMemcpyHostToDevice));
   if (dv || de || dvis) c->adj_coef_ready = false;

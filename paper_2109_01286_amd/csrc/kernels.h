@@ -85,7 +85,7 @@ struct EdgeCoef {
   const int32_t* stg;   // [6][ne] gather rows
   const T* n;           // [2][ne]
   const T* w5;          // [2][ne][15]: per side and edge its 15 Hermite weights
-  const T* w3;          // [2][3][3][ne]
+  const T* w3;          // [2][ne][9]: per side and edge its three 3-node rows
   // staging lists of the two-lane edge kernel (null: gathers from HBM): per
   // block of kEdgeStageEdges edges the sorted distinct stencil rows
   // (erow[erp[b] .. erp[b+1])), per stencil node its position in that list

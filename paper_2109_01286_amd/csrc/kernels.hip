@@ -321,7 +321,7 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
       for (int p = 0; p < 5; ++p) c5[q][p] = cv[q][s == 0 ? p : 5 - p];
     }
     const uint8_t b = side_decide<T, SWM>(be[s], gp, s, fm);
-    side_state<T>(b, s, be[s], c5, hs[s], F, gp, [&](int j) { return row(c.w3, s * 9 + j); },
+    side_state<T>(b, s, be[s], c5, hs[s], F, gp, [&](int j) { return c.w3[(int64_t(s) * ne + e) * 9 + j]; },
                   s == 0 ? wl : wr);
     bits |= b;
   }
@@ -390,16 +390,14 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
   // coefficient rows as in k_edge1, the pair of lanes sharing the edge.  A
-  // side's Hermite weights are one 15-value record per edge (this lane's
-  // side and the other's, read with wide loads); the 3-node rows and the
-  // stencil positions are addressed from a per-lane pointer formed once,
-  // plus the row's wave-uniform offset.
+  // side's Hermite weights (15 values) and 3-node rows (9) are one record
+  // per edge, read with wide loads; the stencil positions are addressed from
+  // a per-lane pointer formed once, plus the row's wave-uniform offset.
   const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
   auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
   const T* w5own = c.w5 + (int64_t(s) * ne + e) * 15;
   const T* w5oth = c.w5 + (int64_t(1 - s) * ne + e) * 15;
-  const T* w3own = c.w3 + int64_t(s == 0 ? 0 : 9) * ne + e;
-  auto rowp = [&](const T* p, int r) { return p[int64_t(r) * ne]; };
+  const T* w3own = c.w3 + (int64_t(s) * ne + e) * 9;
   // this lane's stencil nodes j = 0, 1, 2: rows j (lane 0) or 5 - j (lane 1)
   const int64_t jstep = s == 0 ? ne : -ne;
   int id[3];
@@ -501,7 +499,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   for (int q = 0; q < 4; ++q) weno_beta<T>(cv[q], be[q]);
   const uint8_t b = side_decide<T, SWM>(be, gp, s, fm);
   T wm[4];
-  side_state<T>(b, s, be, cv, hs, F, gp, [&](int j) { return rowp(w3own, j); }, wm);
+  side_state<T>(b, s, be, cv, hs, F, gp, [&](int j) { return w3own[j]; }, wm);
   T wl[4], wr[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {

@@ -378,7 +378,7 @@ k_edge_weights(int64_t ne, const double* __restrict__ pts,
     double w = (lane < 3) ? L.out[lane] : 0.0;
     double sv = gsum<EG>(w);
     if (lane == 2 - j) w += 1.0 - sv;  // the side's anchor (node 2)
-    if (lane < 3) w3[int64_t((side * 3 + j) * 3 + lane) * ne + e] = w;
+    if (lane < 3) w3[(int64_t(side) * ne + e) * 9 + j * 3 + lane] = w;
     if (lane == 0) trunc3[int64_t(side * 3 + j) * ne + e] = int8_t(dropped);
     if (w3g) {  // gradient of the interpolant at the midpoint, as for w5g
       const int grows[2] = {1, 2};
