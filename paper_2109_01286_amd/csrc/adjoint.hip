@@ -274,7 +274,7 @@ k_adj_edge(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv
   // (the staged rows are read; the LDS takes the output rows later)
   if (stg) __syncthreads();
   const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
-  const T nx = c.n[e], ny = c.n[ne + e];
+  const T nx = c.n[2 * e], ny = c.n[2 * e + 1];
   const int ia = c.stg[2 * ne + e], ib = c.stg[3 * ne + e];
   int id[5];
   for (int t = 0; t < 5; ++t) id[t] = c.stg[(s == 0 ? t : 5 - t) * ne + e];

@@ -83,7 +83,7 @@ struct GasParams {
 template <class T>
 struct EdgeCoef {
   const int32_t* stg;   // [6][ne] gather rows
-  const T* n;           // [2][ne]
+  const T* n;           // [ne][2]: unit direction (one load per edge)
   const T* w5;          // [2][ne][15]: per side and edge its 15 Hermite weights
   const T* w3;          // [2][ne][9]: per side and edge its three 3-node rows
   // staging lists of the two-lane edge kernel (null: gathers from HBM): per

@@ -225,19 +225,17 @@ k_edge1(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   }
   const Ref<T> ref = make_ref<T>(gp);
   const T gam = gpar<T>(gp.gamma, gp.f_gamma), gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
-  // Row r of a [rows][ne] coefficient array at this edge: the row base of the
+  // Row r of a [rows][ne] index array at this edge: the row base of the
   // block is uniform, the lane adds a 32-bit byte offset (one register for
   // all rows).
-  const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
   const uint32_t li = uint32_t(e - e0) * 4u;
-  auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
   int id[6];
 #pragma unroll
   for (int t = 0; t < 6; ++t) {
     if constexpr (STG) id[t] = *at(c.epos, t * ne + e0, 2u * uint32_t(e - e0));
     else id[t] = *at(c.stg, t * ne + e0, li);
   }
-  const T nx = row(c.n, 0), ny = row(c.n, 1);
+  const T nx = c.n[2 * e], ny = c.n[2 * e + 1];
   T w5[2][15];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -393,8 +391,6 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
   // side's Hermite weights (15 values) and 3-node rows (9) are one record
   // per edge, read with wide loads; the stencil positions are addressed from
   // a per-lane pointer formed once, plus the row's wave-uniform offset.
-  const uint32_t lo = uint32_t(e - e0) * uint32_t(sizeof(T));
-  auto row = [&](const T* a, int r) { return *at(a, r * ne + e0, lo); };
   const T* w5own = c.w5 + (int64_t(s) * ne + e) * 15;
   const T* w5oth = c.w5 + (int64_t(1 - s) * ne + e) * 15;
   const T* w3own = c.w3 + (int64_t(s) * ne + e) * 9;
@@ -408,7 +404,7 @@ k_edge2(int64_t ne, EdgeCoef<T> c, GasParams gp, const V4<T>* __restrict__ Gv,
     else
       id[j] = (c.stg + (s == 0 ? 0 : 5 * ne) + e)[j * jstep];
   }
-  const T nx = row(c.n, 0), ny = row(c.n, 1);
+  const T nx = c.n[2 * e], ny = c.n[2 * e + 1];
   const uint8_t fm = SWM == kSwForced ? force[e] : uint8_t(0);
   // Hermite rows: own side at its nodes 0..2; other side at its nodes 3 + m,
   // which are own nodes j = 2 - m (m = 0, 1)
@@ -543,7 +539,7 @@ k_edge_grad(int64_t ne, EdgeCoef<T> c, const double* __restrict__ w5g,
   if (e >= ne) return;
   const Ref<T> ref = make_ref<T>(gp);
   const T gm1 = gpar<T>(gp.gamma - 1.0, gp.f_gm1);
-  const T nx = c.n[e], ny = c.n[ne + e];
+  const T nx = c.n[2 * e], ny = c.n[2 * e + 1];
   const RoeState<T> F = roe_state<T>(Gv[c.stg[2 * ne + e]], Gv[c.stg[3 * ne + e]], nx, ny, ref, gm1);
   const uint8_t fm = mask[e];
   T cv[4][5], G[2][4];

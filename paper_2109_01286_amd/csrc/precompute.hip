@@ -443,8 +443,8 @@ k_div_rows(int64_t nowned, int LD, const int64_t* __restrict__ vptr,
       y = mpts[2 * (m0 + k) + 1];
       // the edge's unit direction (active-edge array, [2][ne])
       const int64_t je = sedge[m0 + k];
-      fa = en[je];
-      fb = en[ne + je];
+      fa = en[2 * je];
+      fb = en[2 * je + 1];
     }
     for (int c = 0; c < NB5; ++c) {
       double p = (i < m) ? mono<DEG>(c, 0, x, y) : 0.0;

@@ -425,8 +425,8 @@ hfd_status host_setup(const double* xy, int64_t nv, const int32_t* tri,
       for (int t = 0; t < 6; ++t) geo.disp(st[2], st[t], rx[t], ry[t]);
       double h = std::hypot(rx[3], ry[3]);
       S.e_h[j] = h;
-      S.e_n[j] = rx[3] / h;
-      S.e_n[NE + j] = ry[3] / h;
+      S.e_n[2 * j] = rx[3] / h;
+      S.e_n[2 * j + 1] = ry[3] / h;
       for (int t = 0; t < 6; ++t) {
         S.e_pts[12 * j + 2 * t] = (rx[t] - 0.5 * rx[3]) / h;
         S.e_pts[12 * j + 2 * t + 1] = (ry[t] - 0.5 * ry[3]) / h;

@@ -81,7 +81,7 @@ struct HostSetup {
   HostArray<int32_t> e_stg;           // [6][ne] gather rows
   HostArray<double> e_pts;            // [ne][6][2] edge frame (midpoint origin, / h_e)
   std::vector<double> e_h;            // [ne] middle-edge length
-  std::vector<double> e_n;            // [2][ne] unit direction i -> i+1
+  std::vector<double> e_n;            // [ne][2] unit direction i -> i+1
 
   // owned vertices, internal order 0..n_owned-1
   std::vector<int64_t> vptr, eptr;    // [n_owned+1]
