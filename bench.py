@@ -583,9 +583,14 @@ def main():
     kw = workload_options(a.workload, prm)
     log(f"[bench] {a.workload}: {m.nv} vertices ({m.n_owned()} owned), inputs "
         f"{time.perf_counter() - t0:.1f} s")
+    torch.cuda.init()
+    torch.cuda.synchronize()
+    mem0 = (torch.cuda.mem_get_info(0), torch.cuda.memory_reserved(0))
     t0 = time.perf_counter()
     S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, **kw)
     info = S.info
+    torch.cuda.synchronize()
+    mem1 = (torch.cuda.mem_get_info(0), torch.cuda.memory_reserved(0))
     log(f"[bench] setup {time.perf_counter() - t0:.1f} s (host {info['setup_ms'][0]:.0f} ms, "
         f"upload {info['setup_ms'][1]:.0f} ms, GPU precompute {info['setup_ms'][2]:.0f} ms); "
         f"{info['n_edges']} active edges, ranks {info['rank_hist'][10:15]}")
@@ -633,6 +638,29 @@ def main():
                     S.set_flux("rusanov")
             log(f"[bench] {prec} edge pass by flux: " + ", ".join(
                 f"{k} {v.get('edge_ms', float('nan')):.3f} ms" for k, v in variants[prec].items()))
+    torch.cuda.synchronize()
+    mem2 = (torch.cuda.mem_get_info(0), torch.cuda.memory_reserved(0))
+
+    def lib_bytes(a0, a1):
+        # device memory taken between two points, less what torch's caching
+        # allocator reserved meanwhile: the library's own allocations
+        return (a0[0][0] - a1[0][0]) - (a1[1] - a0[1])
+
+    total = mem0[0][1]
+    fwd = lib_bytes(mem0, mem2)
+    device_memory = {
+        "total_gb": total / 1e9,
+        "library_after_setup_gb": lib_bytes(mem0, mem1) / 1e9,
+        "library_forward_gb": fwd / 1e9,
+        "bytes_per_owned_vertex": fwd / m.n_owned(),
+        "owned_vertices_fitting": int(0.95 * total / (fwd / m.n_owned())),
+        "note": "forward path with both precisions resident (float64 coefficients "
+                "and their float32 copies); the adjoint's buffers come on first use",
+    }
+    log(f"[bench] device memory: {fwd / 1e9:.2f} GB for the forward path "
+        f"({fwd / m.n_owned():.0f} B per owned vertex; "
+        f"{device_memory['owned_vertices_fitting'] / 1e6:.0f} M owned vertices would fit "
+        f"in 95 % of {total / 1e9:.0f} GB)")
     main_prec = "fp32" if "fp32" in res else "fp64"
     r = res[main_prec]
     dom, kern = r["dom"], r["kern"]
@@ -665,6 +693,7 @@ def main():
                                                   else "k_edge2<float")
                                  if main_prec == "fp32" else None)},
         "kernels": kern,
+        "device_memory": device_memory,
     }
     if main_prec == "fp32":
         # counter traffic of the float32 passes, when taken for this source
