@@ -308,6 +308,47 @@ def fp32_residual_errors():
     return out
 
 
+def riemann_after_steps(steps=10, cfl=0.03):
+    """The 2D Riemann case (201 x 201) after ``steps`` Runge-Kutta steps in
+    float64 and in the float32 mixed form, with WENO everywhere, the HLLC
+    flux and capped 3-node weights at CFL 0.03: the smallest step at which
+    this case stays finite for ten steps (at CFL 0.1 it fails in step 4, at
+    0.3 in step 2; with the paper switch in step 1).  The float32 run takes
+    the float64 run's time steps.  Reports per block (w, w_x, w_y) the
+    relative L2 difference of the two states, and the float32 residual's
+    relative L2 error at the float64 state after the steps."""
+    import torch
+
+    from paper_2109_01286_amd import hfd, inputs
+
+    m, U0, prm = inputs.workload("riemann201", None)
+    S = hfd.Solver(m.xy, m.tri, m.ghost_src, m.period, device=0, switch="weno",
+                   w3_cap=2.0, flux="hllc")
+    own = slice(0, S.n_owned)
+    U64 = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+    dts = []
+    for _ in range(steps):
+        dts.append(S.stable_dt(U64, cfl).item())
+        S.rk_step(U64, dts[-1])
+    S.check()
+    R64 = S.residual(U64)
+    S.set_precision("fp32", U0[0:4, m.ghost_src == -1].mean(axis=1))
+    U32 = torch.as_tensor(S.to_internal(U0), device="cuda:0")
+    for dt in dts:
+        S.rk_step(U32, dt)
+    S.check()
+    R32 = S.residual(U64)
+
+    def rel(a, b):
+        return [float(torch.linalg.norm(a[4 * k:4 * k + 4, own] - b[4 * k:4 * k + 4, own])
+                      / torch.linalg.norm(b[4 * k:4 * k + 4, own])) for k in range(3)]
+
+    return {"workload": "riemann201", "steps": steps, "cfl": cfl, "switch": "weno",
+            "flux": "hllc", "w3_cap": 2.0, "t": float(sum(dts)),
+            "state_fp32_vs_fp64_rel_l2_blocks": rel(U32, U64),
+            "residual_fp32_vs_fp64_rel_l2_blocks": rel(R32, R64)}
+
+
 def adjoint_fd(S, Ud, dt, steps, xy, area, g, ndir=32, seed=4242):
     """Central differences of the objective in ``ndir`` seeded directions
     delta ~ N(0, 1), step eps = 1e-6 ||U0||_inf / ||delta||_inf and eps / 4,
@@ -724,6 +765,11 @@ def main():
         section("accuracy", accuracy_runs, lambda r: "[bench] accuracy: " + ", ".join(
             f"{k} rho L2 fp64 {v['fp64']['rho']['l2']:.3e} fp32 {v['fp32']['rho']['l2']:.3e}"
             for k, v in r.items()))
+    if not a.no_config_errors:
+        section("riemann_steps", riemann_after_steps, lambda r: (
+            f"[bench] riemann201 after {r['steps']} steps (WENO, HLLC, CFL {r['cfl']}): "
+            "fp32 vs fp64 state " + "/".join(f"{x:.1e}" for x in r["state_fp32_vs_fp64_rel_l2_blocks"])
+            + ", residual " + "/".join(f"{x:.1e}" for x in r["residual_fp32_vs_fp64_rel_l2_blocks"])))
     if not a.no_config_errors:
         section("fp32_error", fp32_residual_errors, lambda r: "[bench] fp32 residual error: " +
                 "; ".join(f"{k} " + "/".join(f"{x:.1e}" for x in v['fp32_rel_l2_blocks']) +
